@@ -1,0 +1,237 @@
+"""CPU oracle for the agent-mechanics step -- TEST INFRASTRUCTURE ONLY.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may import this
+package.  The product path (the HIP library and its Python binding) never imports,
+links or calls it, and the two share no code: the only thing both sides see is the
+seeded inputs built by the `workloads` package.
+
+The arithmetic lives in `mech_oracle.c` (plain C, FP64, -ffp-contract=off), which
+states what it computes.  This module builds it with gcc and wraps it with ctypes.
+
+Parity status of each function (what pins it is listed in tests/test_oracle_*.py):
+  bin                pinned: numpy floor + lexsort, hand-built cases
+  velocity_allpairs  pinned: two-cell closed forms, lattices, Newton's third law
+  velocity_voxel     pinned: equals all-pairs (pair set exactly, sums to 1e-13)
+  run / integrate    pinned: two-cell closed-form trajectories, exact AB2 recurrence
+                     in 50-digit arithmetic, reflecting-wall special cases
+  FP32 variants      pinned: decisions equal FP64 on well-separated pairs; Kahan sum
+                     within the textbook compensated-summation bound of math.fsum
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "mech_oracle.c")
+_LIB = os.path.join(_HERE, "libmech_oracle.so")
+
+FP64, FP32, FP32_KAHAN = 0, 1, 2
+
+
+class OracleParams(C.Structure):
+    _fields_ = [("lo", C.c_double * 3), ("hi", C.c_double * 3), ("h", C.c_double),
+                ("dt", C.c_double), ("c_rep", C.c_double), ("alpha", C.c_double),
+                ("n_types", C.c_int32), ("pad_", C.c_int32), ("c_adh", C.c_double * 64)]
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (OpenMP over cells; no fast-math, no contraction)."""
+    if force or not os.path.exists(_LIB):
+        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+               "-fno-fast-math", "-Wall", "-Wextra", "-Wno-unused-parameter", _SRC, "-o",
+               _LIB + ".tmp", "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = C.CDLL(_LIB)
+        P = C.POINTER
+        dp, up, ip, lp = P(C.c_double), P(C.c_uint32), P(C.c_int32), P(C.c_int64)
+        L.oracle_grid_dims.argtypes = [P(OracleParams), ip]
+        L.oracle_bin.argtypes = [P(OracleParams), C.c_int64, dp, up, up, up, up, lp]
+        L.oracle_velocity_allpairs.argtypes = [P(OracleParams), C.c_int64, dp, dp, ip,
+                                               C.c_int32, dp, lp]
+        L.oracle_velocity_voxel.argtypes = [P(OracleParams), C.c_int64, dp, dp, ip, C.c_int32,
+                                            dp, lp, lp]
+        L.oracle_integrate.argtypes = [P(OracleParams), C.c_int64, dp, dp, dp, C.c_int32]
+        L.oracle_run.argtypes = [P(OracleParams), C.c_int64, dp, dp, ip, dp, C.c_int64,
+                                 C.c_int32, C.c_int32, C.c_int32, lp, lp, lp]
+        L.oracle_velocity_sampled.argtypes = [P(OracleParams), C.c_int64, dp, dp, ip,
+                                              C.c_int32, C.c_int64, lp, dp, lp]
+        L.oracle_set_threads.argtypes = [C.c_int32]
+        L.oracle_sum_f32.argtypes = [P(C.c_float), C.c_int64, C.c_int32]
+        L.oracle_sum_f32.restype = C.c_float
+        for f in ("oracle_grid_dims", "oracle_bin", "oracle_velocity_allpairs",
+                  "oracle_velocity_voxel", "oracle_integrate", "oracle_run",
+                  "oracle_velocity_sampled", "oracle_set_threads"):
+            getattr(L, f).restype = C.c_int32
+        _lib = L
+    return _lib
+
+
+def params(lo, hi, h=30.0, dt=0.1, c_rep=10.0, alpha=1.25, c_adh=((0.4,),)) -> OracleParams:
+    p = OracleParams()
+    for a in range(3):
+        p.lo[a] = float(lo[a])
+        p.hi[a] = float(hi[a])
+    p.h, p.dt, p.c_rep, p.alpha = float(h), float(dt), float(c_rep), float(alpha)
+    c = np.asarray(c_adh, dtype=np.float64)
+    p.n_types = int(c.shape[0])
+    for k, val in enumerate(c.reshape(-1)):
+        p.c_adh[k] = float(val)
+    return p
+
+
+def params_of(pop) -> OracleParams:
+    return params(pop.lo, pop.hi, pop.voxel, pop.dt, pop.c_rep, pop.alpha, pop.c_adh)
+
+
+def _d(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _u(a):
+    return a.ctypes.data_as(C.POINTER(C.c_uint32))
+
+
+def _i(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def _l(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int64))
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise RuntimeError(f"oracle {what} failed with code {rc}")
+
+
+def set_threads(t: int = 0) -> int:
+    """Set the OpenMP thread count (0 keeps it); returns the count in effect."""
+    return int(lib().oracle_set_threads(int(t)))
+
+
+def sum_f32(x, kahan=True) -> float:
+    """The FP32 velocity's accumulator applied to a plain sequence of floats."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    return float(lib().oracle_sum_f32(x.ctypes.data_as(C.POINTER(C.c_float)), x.size,
+                                      int(kahan)))
+
+
+def grid_dims(p: OracleParams):
+    d = np.zeros(3, dtype=np.int32)
+    _check(lib().oracle_grid_dims(C.byref(p), _i(d)), "grid_dims")
+    return tuple(int(x) for x in d)
+
+
+def bin(p: OracleParams, pos):
+    """Returns vid[n], voxel_start[V+1], sorted_ids[n], occ[M] (all uint32)."""
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    n = pos.shape[0]
+    nx, ny, nz = grid_dims(p)
+    V = nx * ny * nz
+    vid = np.zeros(max(n, 1), np.uint32)
+    start = np.zeros(V + 1, np.uint32)
+    ids = np.zeros(max(n, 1), np.uint32)
+    occ = np.zeros(max(V, 1), np.uint32)
+    m = np.zeros(1, np.int64)
+    _check(lib().oracle_bin(C.byref(p), n, _d(pos), _u(vid), _u(start), _u(ids), _u(occ),
+                            _l(m)), "bin")
+    return vid[:n], start, ids[:n], occ[:int(m[0])]
+
+
+def _types(t, n):
+    if t is None:
+        return np.zeros(max(n, 1), np.int32)
+    return np.ascontiguousarray(t, dtype=np.int32)
+
+
+def velocity_allpairs(p, pos, radius, types=None, precision=FP64):
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    radius = np.ascontiguousarray(radius, dtype=np.float64)
+    n = pos.shape[0]
+    vel = np.zeros((max(n, 1), 3), np.float64)
+    inter = np.zeros(1, np.int64)
+    _check(lib().oracle_velocity_allpairs(C.byref(p), n, _d(pos), _d(radius),
+                                          _i(_types(types, n)), precision, _d(vel),
+                                          _l(inter)), "velocity_allpairs")
+    return vel[:n], int(inter[0])
+
+
+def velocity_voxel(p, pos, radius, types=None, precision=FP64):
+    """Returns (vel[n,3] in id order, interactions, candidates)."""
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    radius = np.ascontiguousarray(radius, dtype=np.float64)
+    n = pos.shape[0]
+    vel = np.zeros((max(n, 1), 3), np.float64)
+    inter = np.zeros(1, np.int64)
+    cand = np.zeros(1, np.int64)
+    _check(lib().oracle_velocity_voxel(C.byref(p), n, _d(pos), _d(radius),
+                                       _i(_types(types, n)), precision, _d(vel), _l(inter),
+                                       _l(cand)), "velocity_voxel")
+    return vel[:n], int(inter[0]), int(cand[0])
+
+
+def velocity_sampled(p, pos, radius, types, sample_ids, precision=FP64):
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    radius = np.ascontiguousarray(radius, dtype=np.float64)
+    n = pos.shape[0]
+    sid = np.ascontiguousarray(sample_ids, dtype=np.int64)
+    vel = np.zeros((max(len(sid), 1), 3), np.float64)
+    inter = np.zeros(1, np.int64)
+    _check(lib().oracle_velocity_sampled(C.byref(p), n, _d(pos), _d(radius),
+                                         _i(_types(types, n)), precision, len(sid), _l(sid),
+                                         _d(vel), _l(inter)), "velocity_sampled")
+    return vel[:len(sid)], int(inter[0])
+
+
+def integrate(p, pos, vel, vprev, euler_start=False):
+    """In place: pos, vprev (both (n,3) float64 C-contiguous)."""
+    assert pos.flags.c_contiguous and vprev.flags.c_contiguous
+    vel = np.ascontiguousarray(vel, dtype=np.float64)
+    _check(lib().oracle_integrate(C.byref(p), pos.shape[0], _d(pos), _d(vel), _d(vprev),
+                                  int(euler_start)), "integrate")
+
+
+def run(p, pos, radius, types=None, vprev=None, steps=1, precision=FP64, euler_first=False,
+        allpairs=False, per_step=False):
+    """Advance copies of pos/vprev by `steps` steps.
+
+    Returns dict(pos, vprev, interactions, candidates[, per_step_interactions])."""
+    pos = np.array(pos, dtype=np.float64, order="C", copy=True)
+    radius = np.ascontiguousarray(radius, dtype=np.float64)
+    n = pos.shape[0]
+    vp = (np.zeros((n, 3), np.float64) if vprev is None
+          else np.array(vprev, dtype=np.float64, order="C", copy=True))
+    if n == 0:
+        return dict(pos=pos, vprev=vp, interactions=0, candidates=0,
+                    per_step_interactions=np.zeros(steps, np.int64))
+    inter = np.zeros(1, np.int64)
+    cand = np.zeros(1, np.int64)
+    ps = np.zeros(max(steps, 1), np.int64)
+    _check(lib().oracle_run(C.byref(p), n, _d(pos), _d(radius), _i(_types(types, n)), _d(vp),
+                            int(steps), int(precision), int(euler_first), int(allpairs),
+                            _l(ps), _l(inter), _l(cand)), "run")
+    out = dict(pos=pos, vprev=vp, interactions=int(inter[0]), candidates=int(cand[0]))
+    if per_step:
+        out["per_step_interactions"] = ps[:steps]
+    return out
+
+
+def run_pop(pop, steps=None, precision=FP64, euler_first=False, per_step=False):
+    return run(params_of(pop), pop.pos, pop.radius, pop.type, None,
+               pop.steps if steps is None else steps, precision, euler_first, False, per_step)
