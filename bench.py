@@ -1,0 +1,194 @@
+"""Benchmark of the agent-mechanics step on one MI355X.
+
+Default workload: the 1M-cell tumour (900k cells in a 600 um ball plus 100k scattered
+in a 2 mm cube, radii N(8.4, 0.5) clipped to [6, 11], 30 um voxels, FP32 force
+arithmetic with Kahan-compensated sums and FP64 integration).  One step = binning,
+counting sort, reorder, 27-voxel forces, Adams-Bashforth and walls, all on the device.
+
+Prints one JSON line: throughput in cell-neighbour interactions/s (value) and
+cell-steps/s, step latency p50/p99, the roofline of the force kernel measured with HIP
+events on the population's stream, and the CPU oracle timed on a bounded sample.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload tumour1m|sph100k|plain1k]
+                  [--precision fp32k|fp32|fp64] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "cell-neighbour interactions/s and cell-steps/s at 1M cells; p50/p99 sim latency"
+
+# MI355X published peaks
+PEAK_HBM_GBS = 8000.0
+PEAK_FP32_VECTOR_TFLOPS = 157.3
+PEAK_FP64_VECTOR_TFLOPS = 78.6
+
+# Algorithmic work of the force kernel (a6 + a7), per unit:
+#   candidate pair visited in the 27 voxels: dx, dy, dz (3), d2 (1 mul + 2 fma = 5),
+#     R (1), R_A (1), R_A^2 (1)                                       -> 11 FLOP
+#   interacting pair: sqrt (1), d (1), 1 - d/R (2), c_rep u^2 (2), 1 - d/R_A (2),
+#     C a^2 (2), w (1), w/d (1), three products (3), three sums (3)  -> 18 FLOP
+#     (+ 9 for the Kahan compensation of the three sums)              -> 27 FLOP
+#   cell: Adams-Bashforth 3 x (2 mul + 1 sub + 1 fma) + walls          -> negligible
+FLOP_PER_CANDIDATE = 11
+FLOP_PER_INTERACTION = {"fp64": 18, "fp32": 18, "fp32k": 27}
+# algorithmic HBM bytes per cell of the force kernel: own f64 position (24) + own and
+# neighbour float shadow read once each (16 + 16) or f64 position + radius (32) +
+# v_prev in/out + voxel id (4) + new f64 position (24)
+FORCE_BYTES_PER_CELL = {"fp64": 24 + 32 + 4 + 48 + 24, "fp32": 24 + 32 + 4 + 24 + 24,
+                        "fp32k": 24 + 32 + 4 + 24 + 24}
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(pop, precision: str, budget_s: float = 12.0):
+    """The oracle as it stands, on the host cores, on whole steps of the same workload."""
+    import oracle
+    cores = oracle.set_threads(0)
+    p = oracle.params_of(pop)
+    prec = {"fp64": oracle.FP64, "fp32": oracle.FP32, "fp32k": oracle.FP32_KAHAN}[precision]
+    pos, vp = pop.pos, None
+    steps, inter, t_total = 0, 0, 0.0
+    while t_total < budget_s and steps < pop.steps:
+        t0 = time.perf_counter()
+        out = oracle.run(p, pos, pop.radius, pop.type, vp, steps=1, precision=prec)
+        t_total += time.perf_counter() - t0
+        pos, vp = out["pos"], out["vprev"]
+        steps += 1
+        inter += out["interactions"]
+    return {"value": inter / t_total, "unit": "interactions/s", "cores": cores, "kind": "oracle",
+            "cell_steps_per_s": pop.n * steps / t_total,
+            "sample": f"{pop.name}: first {steps} step(s) of the full population, "
+                      f"{precision} oracle, {t_total:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="tumour1m")
+    ap.add_argument("--precision", default=None)
+    ap.add_argument("--profile-steps", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build runs the mechanics step on a single "
+              "MI355X and has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import workloads
+    from paper_2306_11544_amd import binding as B
+
+    precision = args.precision or {"tumour1m": "fp32k", "sph100k": "fp64",
+                                   "plain1k": "fp64"}[args.workload]
+    pop = workloads.config(args.workload)
+    prm = B.params_of(pop, B.PRECISIONS[precision])
+    log(f"workload {pop.name} n={pop.n} precision={precision} steps={args.steps} "
+        f"warmup={args.warmup}")
+
+    torch.cuda.init()
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    ws = torch.empty(B.population_workspace_bytes(prm, pop.n), dtype=torch.uint8, device=dev)
+    P = B.Population(prm, pop.pos, pop.radius, pop.type, stream=stream.cuda_stream, workspace=ws)
+
+    P.step(args.warmup)
+    torch.cuda.synchronize()
+
+    # timed region: K steps, inputs already resident in HBM
+    _, i0, c0 = P.stats()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    P.step(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = e0.elapsed_time(e1)
+    _, i1, c1 = P.stats()
+    elapsed_s = max(gpu_ms / 1e3, 1e-9)
+    inter = i1 - i0
+    cand = c1 - c0
+    value = inter / elapsed_s
+    cell_steps = pop.n * args.steps / elapsed_s
+    log(f"timed {args.steps} steps: {gpu_ms:.3f} ms (wall {wall * 1e3:.3f} ms)")
+
+    # per-step latency distribution (one event pair per graph launch)
+    lat = []
+    nlat = min(args.steps, 100)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(nlat + 1)]
+    evs[0].record(stream)
+    for k in range(nlat):
+        P.step(1)
+        evs[k + 1].record(stream)
+    torch.cuda.synchronize()
+    lat = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(nlat)])
+
+    # force kernel alone: HIP events around it on the population's stream
+    _, ip0, cp0 = P.stats()
+    bin_ms, force_ms = P.profile(args.profile_steps)
+    _, ip1, cp1 = P.stats()
+    per_launch_inter = (ip1 - ip0) / args.profile_steps
+    per_launch_cand = (cp1 - cp0) / args.profile_steps
+    flops = FLOP_PER_CANDIDATE * per_launch_cand + FLOP_PER_INTERACTION[precision] * per_launch_inter
+    achieved_tflops = flops / (force_ms * 1e-3) / 1e12
+    peak = PEAK_FP64_VECTOR_TFLOPS if precision == "fp64" else PEAK_FP32_VECTOR_TFLOPS
+    force_bytes = FORCE_BYTES_PER_CELL[precision] * pop.n
+    force_gbs = force_bytes / (force_ms * 1e-3) / 1e9
+    log(f"phases: binning+reorder {bin_ms:.4f} ms, force+update {force_ms:.4f} ms; "
+        f"{achieved_tflops:.2f} TFLOP/s, {force_gbs:.1f} GB/s algorithmic")
+    P.close()
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": gpu_ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "fp32k": "f32"}[precision],
+        "data": "synthetic",
+        "config": {"workload": pop.name, "cells": pop.n, "precision": precision,
+                   "voxel_um": pop.voxel, "dt_min": pop.dt,
+                   "integration": "f64 two-step Adams-Bashforth"},
+        "cell_steps_per_s": cell_steps,
+        "candidates_per_s": cand / elapsed_s,
+        "step_latency_ms": {"p50": float(np.percentile(lat, 50)),
+                            "p99": float(np.percentile(lat, 99))},
+        "phase_ms": {"binning_reorder": bin_ms, "force_update": force_ms},
+        "roofline": {"bound": "alu", "kernel": "k_force_rows", "achieved": achieved_tflops,
+                     "peak": peak, "unit": "TFLOP/s", "frac": achieved_tflops / peak,
+                     "traffic": None,
+                     "hbm_algorithmic_GBs": force_gbs,
+                     "hbm_frac": force_gbs / PEAK_HBM_GBS},
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(pop, precision)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

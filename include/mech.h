@@ -1,0 +1,168 @@
+/*
+ * mech.h -- C ABI of the MI355X (gfx950) agent-mechanics library, libmech.so.
+ *
+ * The library advances a population of spherical cells with the mechanics step of a
+ * PhysiCell-style agent-based simulation: the region the paper calls "update
+ * velocity", which it finds to dominate and to degrade as cells lose spatial locality
+ * (Sections 4.1 and 5.4).  One step:
+ *   a1  voxel of every cell on a uniform grid of edge h (anchored at domain_lo, x fastest)
+ *   a2  voxel histogram
+ *   a3  exclusive scan of the counts and the list of occupied voxels (the paper's
+ *       non-empty voxel list, Section 5.4)
+ *   a4  rank of each cell inside its voxel by ascending cell id (bit-exact order)
+ *   a5  gather of the cell state into that voxel order, so that cells close in space
+ *       are close in memory (the layout the paper recommends, Sections 5.4 and 6)
+ *   a6  velocity of each cell: sum over the cells of the 27 surrounding voxels of
+ *         w = c_rep (1 - d/R)^2 [d < R] - C[t_i][t_j] (1 - d/R_A)^2,  along (x_i - x_j)/d,
+ *       with R = r_i + r_j, R_A = rel_adh_distance * R, for pairs with 0 < d^2 < R_A^2
+ *   a7  two-step Adams-Bashforth update x += dt (1.5 v - 0.5 v_prev), reflecting walls
+ *       (mirror at each face, then clamp), v_prev <- v
+ * The force law, the overdamped velocity, the Adams-Bashforth update and the walls are
+ * not printed in the paper; they are the method as this library defines it.
+ *
+ * Conventions
+ *   - Every int-returning call returns MECH_OK (0) or a negative MECH_E_* code; the
+ *     text of the last error on the calling thread is mech_last_error().
+ *   - Host arrays passed in are copied; the caller keeps ownership.  Device memory is
+ *     owned by the population until destroy_population, except with
+ *     create_population_in, where the caller owns the workspace and it must outlive
+ *     the population.
+ *   - step_mechanics is asynchronous on the population's stream; a device fault shows
+ *     up as MECH_E_DEVICE at the next synchronising call (read_*, destroy).
+ *   - A population is used from one host thread at a time.  Different populations may
+ *     run on different streams concurrently.
+ *   - Units: um, min, um/min.  n_cells < 2^31 and n_voxels < 2^31.
+ *   - Cell ids are the row indices of the arrays given at creation; every read_* call
+ *     returns arrays in id order unless it says otherwise.
+ */
+#ifndef MECH_H
+#define MECH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MECH_ABI_VERSION 1
+
+enum {
+    MECH_OK = 0,
+    MECH_E_INVALID = -1,          /* bad argument, NaN/Inf input, asymmetric C, bad type */
+    MECH_E_VOXEL_TOO_SMALL = -2,  /* voxel_size < rel_adh_distance * 2 * max radius     */
+    MECH_E_OUT_OF_DOMAIN = -3,    /* a cell outside [domain_lo, domain_hi] at creation  */
+    MECH_E_NOMEM = -4,            /* device allocation failed or workspace too small    */
+    MECH_E_BUDGET = -5,           /* batch: request does not fit the HBM budget         */
+    MECH_E_DEVICE = -6,           /* HIP runtime or kernel error                        */
+    MECH_E_NONFINITE = -7,        /* state read back holds NaN or Inf                   */
+    MECH_E_FULL = -8              /* batch: no free slot                                */
+};
+
+enum { MECH_FP64 = 0, MECH_FP32 = 1, MECH_FP32_KAHAN = 2 };
+enum { MECH_AB2_ZERO_HISTORY = 0, MECH_AB2_EULER_START = 1 };
+/* MechParams.flags bits */
+enum {
+    MECH_FLAG_NO_GRAPH = 1        /* launch each step's kernels directly (no HIP graph) */
+};
+
+typedef struct MechParams {
+    int32_t abi_version;        /* MECH_ABI_VERSION                                    */
+    int32_t precision;          /* MECH_FP64 | MECH_FP32 | MECH_FP32_KAHAN             */
+    int32_t ab2_start;          /* history of the first step when none is given        */
+    int32_t flags;              /* MECH_FLAG_* bits, otherwise 0                        */
+    double domain_lo[3];        /* um; reflecting walls                                 */
+    double domain_hi[3];
+    double voxel_size;          /* h, um (30)                                           */
+    double dt;                  /* min (0.1)                                            */
+    double c_rep;               /* repulsion coefficient, um/min (10)                   */
+    double rel_adh_distance;    /* R_A / (r_i + r_j) (1.25)                             */
+    int32_t n_types;            /* 1..8                                                 */
+    int32_t reserved;           /* must be 0                                            */
+    double c_adh[64];           /* n_types x n_types adhesion matrix, row major,
+                                   symmetric (Newton's third law), um/min               */
+} MechParams;
+
+typedef struct MechPopulation MechPopulation;
+
+/* Text of the last error on this thread ("" if none).  Valid until the next call. */
+const char* mech_last_error(void);
+
+/* MECH_ABI_VERSION of the loaded library. */
+int32_t mech_abi_version(void);
+
+/* Number of HIP devices visible (0 without a GPU; no device is initialised otherwise). */
+int32_t mech_device_count(void);
+
+/* Device bytes a population of n_cells needs (what create_population allocates and
+ * what create_population_in requires), or a negative MECH_E_* code. */
+int64_t population_workspace_bytes(const MechParams* params, int64_t n_cells);
+
+/* Create a population on the current HIP device.
+ *   pos            n_cells x 3 doubles, row major, id order; each inside the domain
+ *   radius         n_cells doubles > 0
+ *   type           n_cells int32 in [0, n_types), or NULL for all type 0
+ *   prev_velocity  n_cells x 3 doubles (the history v_prev of the first step; pass the
+ *                  velocity read back by read_state to resume a run), or NULL: then the
+ *                  first step uses zero history, or v_prev = v with MECH_AB2_EULER_START
+ *   hip_stream     hipStream_t to run on, or NULL for a stream the population owns
+ * The initial binning (a1-a5) runs before this returns; read_binning then describes the
+ * given positions.  On error *out is NULL and nothing is left allocated. */
+int create_population(const MechParams* params, int64_t n_cells, const double* pos,
+                      const double* radius, const int32_t* type,
+                      const double* prev_velocity, void* hip_stream, MechPopulation** out);
+
+/* Same, but all device arrays are carved from the caller's device buffer `workspace`
+ * of `workspace_bytes` (>= population_workspace_bytes, 256-byte aligned); the library
+ * makes no device allocation.  MECH_E_NOMEM if the buffer is too small. */
+int create_population_in(const MechParams* params, int64_t n_cells, const double* pos,
+                         const double* radius, const int32_t* type,
+                         const double* prev_velocity, void* hip_stream, void* workspace,
+                         int64_t workspace_bytes, MechPopulation** out);
+
+/* Enqueue n_steps steps (a1-a7 each) on the population's stream and return.  After the
+ * first call, each step is one launch of a captured HIP graph.  Makes no allocation. */
+int step_mechanics(MechPopulation* pop, int64_t n_steps);
+
+/* Wait for the stream and copy the state out in id order:
+ *   pos  n_cells x 3 (required)
+ *   vel  n_cells x 3 or NULL: the velocity of the last step, which is also the v_prev of
+ *        the next one (zeros, or the given prev_velocity, before any step)
+ * n_cells must equal the population size.  MECH_E_NONFINITE if any value is NaN/Inf. */
+int read_state(MechPopulation* pop, double* pos, double* vel, int64_t n_cells);
+
+/* Wait and copy the binning of the last step (or of creation, before any step):
+ *   voxel_of_cell  n_cells uint32, id order (may be NULL)
+ *   voxel_start    n_voxels + 1 uint32: exclusive prefix of voxel counts (may be NULL)
+ *   sorted_ids     n_cells uint32: ids in (voxel, id) order (may be NULL)
+ *   occ            n_voxels uint32: occupied voxels, ascending; *n_occ of them are valid
+ *                  (may be NULL)
+ *   n_occ, n_voxels  outputs (may be NULL) */
+int read_binning(MechPopulation* pop, uint32_t* voxel_of_cell, uint32_t* voxel_start,
+                 uint32_t* sorted_ids, uint32_t* occ, int64_t* n_occ, int64_t* n_voxels);
+
+/* Wait and return the running totals: steps taken, interacting ordered pairs
+ * (0 < d^2 < R_A^2), and candidate pairs visited in the 27-voxel neighbourhoods. */
+int read_stats(MechPopulation* pop, int64_t* steps, int64_t* interactions,
+               int64_t* candidates);
+
+/* Run n_steps steps (a1-a7, same results as step_mechanics) with direct launches and
+ * HIP events on the population's stream around the two phases; on return
+ *   phase_ms[0]  mean ms per step of binning and reorder (a1-a5)
+ *   phase_ms[1]  mean ms per step of the neighbour-force and update kernel (a6-a7)
+ * Synchronises.  For tuning and roofline measurement. */
+int profile_step(MechPopulation* pop, int64_t n_steps, double* phase_ms);
+
+/* Size and grid of a population: n_cells, and voxels per axis. */
+int population_info(MechPopulation* pop, int64_t* n_cells, int32_t dims[3]);
+
+/* hipStream_t the population runs on. */
+void* population_stream(MechPopulation* pop);
+
+/* Wait for the stream and free everything the population owns.  NULL is a no-op. */
+int destroy_population(MechPopulation* pop);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MECH_H */

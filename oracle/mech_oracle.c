@@ -36,7 +36,8 @@
  * 5.4) -- which this oracle also follows, since it is the algorithm being checked.
  *
  * FP32 variant (an approximation; it fixes what the FP32 kernels compute): positions
- * and radii are rounded to float once per step, the pair arithmetic runs in float,
+ * and radii are rounded to float once per step, the pair arithmetic runs in float with
+ * d2 = fma(dz, dz, fma(dy, dy, dx*dx)) (two fused multiply-adds, correctly rounded),
  * the force sum is plain float or Kahan-compensated per component, and the update in
  * step 4 runs in double on the float velocity; v_prev holds the float velocity.
  *
@@ -162,7 +163,7 @@ static int pair_f32(const OracleParams* p, const float* xi, float ri, int ti,
                     const float* xj, float rj, int tj, AccF* acc, int kahan)
 {
     float dx = xi[0] - xj[0], dy = xi[1] - xj[1], dz = xi[2] - xj[2];
-    float d2 = dx * dx + dy * dy + dz * dz;
+    float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));   /* fused, as the float kernels */
     float R = ri + rj;
     float RA = (float)p->alpha * R;
     if (!(d2 > 0.0f && d2 < RA * RA)) return 0;

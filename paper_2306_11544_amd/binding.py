@@ -1,0 +1,275 @@
+"""ctypes binding of libmech.so: the C-ABI entry points under the same names.
+
+Argument marshalling only: every step of the mechanics path runs in the HIP kernels
+behind these calls.  If libmech.so has not been built this module raises on first use;
+there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmech.so")
+
+MECH_OK = 0
+MECH_E_INVALID, MECH_E_VOXEL_TOO_SMALL, MECH_E_OUT_OF_DOMAIN = -1, -2, -3
+MECH_E_NOMEM, MECH_E_BUDGET, MECH_E_DEVICE, MECH_E_NONFINITE, MECH_E_FULL = -4, -5, -6, -7, -8
+MECH_FP64, MECH_FP32, MECH_FP32_KAHAN = 0, 1, 2
+MECH_AB2_ZERO_HISTORY, MECH_AB2_EULER_START = 0, 1
+MECH_FLAG_NO_GRAPH = 1
+MECH_ABI_VERSION = 1
+
+PRECISIONS = {"fp64": MECH_FP64, "fp32": MECH_FP32, "fp32k": MECH_FP32_KAHAN}
+
+# every symbol include/mech.h declares
+EXPORTS = ("mech_last_error", "mech_abi_version", "mech_device_count",
+           "population_workspace_bytes", "create_population", "create_population_in",
+           "step_mechanics", "read_state", "read_binning", "read_stats", "profile_step",
+           "population_info", "population_stream", "destroy_population")
+
+
+class MechError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class MechParams(C.Structure):
+    _fields_ = [("abi_version", C.c_int32), ("precision", C.c_int32), ("ab2_start", C.c_int32),
+                ("flags", C.c_int32), ("domain_lo", C.c_double * 3), ("domain_hi", C.c_double * 3),
+                ("voxel_size", C.c_double), ("dt", C.c_double), ("c_rep", C.c_double),
+                ("rel_adh_distance", C.c_double), ("n_types", C.c_int32), ("reserved", C.c_int32),
+                ("c_adh", C.c_double * 64)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libmech.so (raises if it is missing: build it with paper_2306_11544_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run `python -m paper_2306_11544_amd.build` "
+                              "(the mechanics step has no CPU fallback)")
+        L = C.CDLL(LIB_PATH)
+        P = C.POINTER
+        vp, dp, ip, up, lp = C.c_void_p, P(C.c_double), P(C.c_int32), P(C.c_uint32), P(C.c_int64)
+        sig = {
+            "mech_last_error": (C.c_char_p, []),
+            "mech_abi_version": (C.c_int32, []),
+            "mech_device_count": (C.c_int32, []),
+            "population_workspace_bytes": (C.c_int64, [P(MechParams), C.c_int64]),
+            "create_population": (C.c_int, [P(MechParams), C.c_int64, dp, dp, ip, dp, vp, P(vp)]),
+            "create_population_in": (C.c_int, [P(MechParams), C.c_int64, dp, dp, ip, dp, vp, vp,
+                                               C.c_int64, P(vp)]),
+            "step_mechanics": (C.c_int, [vp, C.c_int64]),
+            "read_state": (C.c_int, [vp, dp, dp, C.c_int64]),
+            "read_binning": (C.c_int, [vp, up, up, up, up, lp, lp]),
+            "read_stats": (C.c_int, [vp, lp, lp, lp]),
+            "profile_step": (C.c_int, [vp, C.c_int64, dp]),
+            "population_info": (C.c_int, [vp, lp, ip]),
+            "population_stream": (C.c_void_p, [vp]),
+            "destroy_population": (C.c_int, [vp]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype, f.argtypes = res, args
+        _lib = L
+    return _lib
+
+
+def _ck(rc):
+    if rc != MECH_OK:
+        raise MechError(rc, mech_last_error())
+
+
+def _d(a):
+    return None if a is None else a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def mech_last_error() -> str:
+    return lib().mech_last_error().decode()
+
+
+def mech_abi_version() -> int:
+    return int(lib().mech_abi_version())
+
+
+def mech_device_count() -> int:
+    return int(lib().mech_device_count())
+
+
+def make_params(lo, hi, voxel_size=30.0, dt=0.1, c_rep=10.0, rel_adh_distance=1.25,
+                c_adh=((0.4,),), precision=MECH_FP64, ab2_start=MECH_AB2_ZERO_HISTORY,
+                flags=0) -> MechParams:
+    if isinstance(precision, str):
+        precision = PRECISIONS[precision]
+    p = MechParams()
+    p.abi_version = MECH_ABI_VERSION
+    p.precision, p.ab2_start, p.flags = int(precision), int(ab2_start), int(flags)
+    for a in range(3):
+        p.domain_lo[a], p.domain_hi[a] = float(lo[a]), float(hi[a])
+    p.voxel_size, p.dt, p.c_rep = float(voxel_size), float(dt), float(c_rep)
+    p.rel_adh_distance = float(rel_adh_distance)
+    c = np.asarray(c_adh, dtype=np.float64)
+    p.n_types = int(c.shape[0])
+    p.reserved = 0
+    for k, v in enumerate(c.reshape(-1)):
+        p.c_adh[k] = float(v)
+    return p
+
+
+def params_of(pop, precision=MECH_FP64, ab2_start=MECH_AB2_ZERO_HISTORY, flags=0) -> MechParams:
+    """Parameters of a workloads.Population."""
+    return make_params(pop.lo, pop.hi, pop.voxel, pop.dt, pop.c_rep, pop.alpha, pop.c_adh,
+                       precision, ab2_start, flags)
+
+
+def population_workspace_bytes(params: MechParams, n_cells: int) -> int:
+    r = int(lib().population_workspace_bytes(C.byref(params), int(n_cells)))
+    if r < 0:
+        raise MechError(r, mech_last_error())
+    return r
+
+
+def _cells(pos, radius, type_, prev_velocity):
+    pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
+    radius = np.ascontiguousarray(radius, dtype=np.float64).reshape(-1)
+    t = None if type_ is None else np.ascontiguousarray(type_, dtype=np.int32).reshape(-1)
+    vp = (None if prev_velocity is None
+          else np.ascontiguousarray(prev_velocity, dtype=np.float64).reshape(-1, 3))
+    if radius.shape[0] != pos.shape[0] or (t is not None and t.shape[0] != pos.shape[0]) or \
+            (vp is not None and vp.shape[0] != pos.shape[0]):
+        raise MechError(MECH_E_INVALID, "array lengths differ")
+    return pos, radius, t, vp
+
+
+def create_population(params: MechParams, pos, radius, type=None, prev_velocity=None,
+                      stream=None) -> C.c_void_p:
+    pos, radius, t, vp = _cells(pos, radius, type, prev_velocity)
+    h = C.c_void_p()
+    _ck(lib().create_population(C.byref(params), pos.shape[0], _d(pos), _d(radius),
+                                None if t is None else t.ctypes.data_as(C.POINTER(C.c_int32)),
+                                _d(vp), stream, C.byref(h)))
+    return h
+
+
+def create_population_in(params: MechParams, pos, radius, type, prev_velocity, stream,
+                         workspace_ptr: int, workspace_bytes: int) -> C.c_void_p:
+    pos, radius, t, vp = _cells(pos, radius, type, prev_velocity)
+    h = C.c_void_p()
+    _ck(lib().create_population_in(C.byref(params), pos.shape[0], _d(pos), _d(radius),
+                                   None if t is None else t.ctypes.data_as(C.POINTER(C.c_int32)),
+                                   _d(vp), stream, C.c_void_p(workspace_ptr),
+                                   int(workspace_bytes), C.byref(h)))
+    return h
+
+
+def step_mechanics(h, n_steps: int = 1) -> None:
+    _ck(lib().step_mechanics(h, int(n_steps)))
+
+
+def population_info(h):
+    n = C.c_int64()
+    dims = (C.c_int32 * 3)()
+    _ck(lib().population_info(h, C.byref(n), dims))
+    return int(n.value), tuple(int(x) for x in dims)
+
+
+def read_state(h, with_velocity: bool = True):
+    n, _ = population_info(h)
+    pos = np.empty((n, 3), np.float64)
+    vel = np.empty((n, 3), np.float64) if with_velocity else None
+    _ck(lib().read_state(h, _d(pos), _d(vel), n))
+    return pos, vel
+
+
+def read_binning(h):
+    n, dims = population_info(h)
+    V = dims[0] * dims[1] * dims[2]
+    up = lambda a: a.ctypes.data_as(C.POINTER(C.c_uint32))
+    vid = np.empty(max(n, 1), np.uint32)
+    start = np.empty(V + 1, np.uint32)
+    ids = np.empty(max(n, 1), np.uint32)
+    occ = np.empty(V, np.uint32)
+    m, nv = C.c_int64(), C.c_int64()
+    _ck(lib().read_binning(h, up(vid), up(start), up(ids), up(occ), C.byref(m), C.byref(nv)))
+    return vid[:n], start, ids[:n], occ[:m.value]
+
+
+def read_stats(h):
+    s, i, c = C.c_int64(), C.c_int64(), C.c_int64()
+    _ck(lib().read_stats(h, C.byref(s), C.byref(i), C.byref(c)))
+    return int(s.value), int(i.value), int(c.value)
+
+
+def profile_step(h, n_steps: int = 1):
+    """Mean ms per step of (binning + reorder, force + update), timed with HIP events."""
+    ms = np.zeros(2, np.float64)
+    _ck(lib().profile_step(h, int(n_steps), _d(ms)))
+    return float(ms[0]), float(ms[1])
+
+
+def population_stream(h) -> int:
+    return int(lib().population_stream(h) or 0)
+
+
+def destroy_population(h) -> None:
+    if h:
+        _ck(lib().destroy_population(h))
+
+
+class Population:
+    """Owns one device population; `with Population(...) as p:` destroys it on exit."""
+
+    def __init__(self, params: MechParams, pos, radius, type=None, prev_velocity=None,
+                 stream=None, workspace=None):
+        self.n = int(np.asarray(pos).reshape(-1, 3).shape[0])
+        self._ws = workspace  # keeps a caller's device buffer (e.g. a torch tensor) alive
+        if workspace is not None:
+            self.h = create_population_in(params, pos, radius, type, prev_velocity, stream,
+                                          int(workspace.data_ptr()),
+                                          int(workspace.numel() * workspace.element_size()))
+        else:
+            self.h = create_population(params, pos, radius, type, prev_velocity, stream)
+
+    def step(self, n_steps=1):
+        step_mechanics(self.h, n_steps)
+        return self
+
+    def state(self, with_velocity=True):
+        return read_state(self.h, with_velocity)
+
+    def binning(self):
+        return read_binning(self.h)
+
+    def stats(self):
+        return read_stats(self.h)
+
+    def profile(self, n_steps=1):
+        return profile_step(self.h, n_steps)
+
+    @property
+    def stream(self) -> int:
+        return population_stream(self.h)
+
+    def close(self):
+        if self.h:
+            destroy_population(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,129 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol that
+include/mech.h declares, and rejects bad arguments on the host before touching a device."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import workloads
+from paper_2306_11544_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "mech.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b([a-z_][a-z0-9_]*)\s*\(", text)) -
+                  {"sizeof", "defined", "if", "return"})
+
+
+def test_header_declares_what_binding_exports():
+    assert declared_functions() == sorted(B.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = B.lib()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", B.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    syms = {line.split()[-1] for line in out.splitlines() if line.strip()}
+    for name in declared_functions():
+        assert name in syms, name
+
+
+def test_params_struct_matches_header_layout():
+    # 4 int32 + 6 double + 4 double + 2 int32 + 64 double
+    assert C.sizeof(B.MechParams) == 16 + 48 + 32 + 8 + 512
+    assert B.MechParams.c_adh.offset == 16 + 48 + 32 + 8
+
+
+def test_abi_version():
+    assert B.mech_abi_version() == B.MECH_ABI_VERSION
+
+
+def _p(**kw):
+    pop = workloads.plain(10)
+    return B.params_of(pop, **kw), pop
+
+
+@pytest.mark.parametrize("mutate,code", [
+    (lambda p: setattr(p, "abi_version", 99), B.MECH_E_INVALID),
+    (lambda p: setattr(p, "precision", 7), B.MECH_E_INVALID),
+    (lambda p: setattr(p, "ab2_start", 3), B.MECH_E_INVALID),
+    (lambda p: setattr(p, "flags", 0x100), B.MECH_E_INVALID),
+    (lambda p: setattr(p, "voxel_size", 0.0), B.MECH_E_INVALID),
+    (lambda p: setattr(p, "voxel_size", float("nan")), B.MECH_E_INVALID),
+    (lambda p: setattr(p, "dt", -0.1), B.MECH_E_INVALID),
+    (lambda p: setattr(p, "c_rep", float("inf")), B.MECH_E_INVALID),
+    (lambda p: setattr(p, "rel_adh_distance", 0.5), B.MECH_E_INVALID),
+    (lambda p: setattr(p, "n_types", 9), B.MECH_E_INVALID),
+    (lambda p: setattr(p, "n_types", 0), B.MECH_E_INVALID),
+    (lambda p: p.domain_hi.__setitem__(0, -200.0), B.MECH_E_INVALID),
+])
+def test_workspace_bytes_rejects_bad_params(mutate, code):
+    p, pop = _p()
+    mutate(p)
+    with pytest.raises(B.MechError) as e:
+        B.population_workspace_bytes(p, 10)
+    assert e.value.code == code
+    assert B.mech_last_error() != ""
+
+
+def test_asymmetric_adhesion_matrix_rejected():
+    pop = workloads.spheroid(100, seed=3)
+    p = B.params_of(pop)
+    p.c_adh[1] = 0.2  # C[0][1] != C[1][0]
+    with pytest.raises(B.MechError) as e:
+        B.create_population(p, pop.pos, pop.radius, pop.type)
+    assert e.value.code == B.MECH_E_INVALID and "symmetric" in B.mech_last_error()
+
+
+@pytest.mark.parametrize("case,code", [
+    ("nan_pos", B.MECH_E_INVALID), ("out_of_domain", B.MECH_E_OUT_OF_DOMAIN),
+    ("bad_radius", B.MECH_E_INVALID), ("bad_type", B.MECH_E_INVALID),
+    ("voxel_too_small", B.MECH_E_VOXEL_TOO_SMALL), ("nan_vprev", B.MECH_E_INVALID),
+    ("length_mismatch", B.MECH_E_INVALID)])
+def test_create_rejects_bad_cells_before_any_device_call(case, code):
+    pop = workloads.plain(50, seed=4)
+    p = B.params_of(pop)
+    pos, rad, typ, vp = pop.pos.copy(), pop.radius.copy(), pop.type.copy(), None
+    if case == "nan_pos":
+        pos[3, 1] = np.nan
+    elif case == "out_of_domain":
+        pos[7, 2] = pop.hi[2] + 1e-9
+    elif case == "bad_radius":
+        rad[0] = -1.0
+    elif case == "bad_type":
+        typ[5] = 1
+    elif case == "voxel_too_small":
+        rad[9] = 12.5  # 1.25 * 2 * 12.5 = 31.25 > 30
+    elif case == "nan_vprev":
+        vp = np.zeros_like(pos)
+        vp[2, 0] = np.inf
+    elif case == "length_mismatch":
+        rad = rad[:-1]
+    with pytest.raises(B.MechError) as e:
+        B.create_population(p, pos, rad, typ, vp)
+    assert e.value.code == code, B.mech_last_error()
+
+
+def test_workspace_bytes_scales_with_cells():
+    p, _ = _p()
+    a = B.population_workspace_bytes(p, 1000)
+    b = B.population_workspace_bytes(p, 2000)
+    assert b > a > 0
+    p32, _ = _p(precision=B.MECH_FP32_KAHAN)
+    assert B.population_workspace_bytes(p32, 1000) > 0
+
+
+def test_null_handles_are_rejected():
+    lib = B.lib()
+    assert lib.step_mechanics(None, 1) == B.MECH_E_INVALID
+    assert lib.read_stats(None, None, None, None) == B.MECH_E_INVALID
+    assert lib.destroy_population(None) == B.MECH_OK
+    assert lib.population_stream(None) is None

@@ -1,0 +1,158 @@
+"""Positions from the HIP path match the oracle after the stated step counts.
+
+Error metric: max over cells and axes of |x_gpu - x_oracle| / S, with S the domain
+half-width (positions near 0 make a per-component relative error meaningless).
+Bars: 1e-10 in FP64, 1e-4 in FP32 and FP32 + Kahan (both against the FP64 oracle).
+Interaction counts are integers decided in the same precision on both sides and are
+compared exactly on the first step; over a trajectory only a pair within rounding of
+its cutoff may differ, so later steps allow a handful of flips."""
+import numpy as np
+import pytest
+
+import workloads
+from gpu_helpers import pos_err, require_gpu, run_gpu, say
+from paper_2306_11544_amd import binding as B
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10
+FP32_TOL = 1e-4
+
+_ORACLE_RUNS = {}
+
+
+def _oracle_full(orc, name):
+    """The oracle's FP64 run of a named workload for its full step count (computed once)."""
+    if name not in _ORACLE_RUNS:
+        _ORACLE_RUNS[name] = orc.run_pop(workloads.config(name))
+    return _ORACLE_RUNS[name]
+
+
+def _scaled_tumour(n, seed):
+    f = (n / 1e6) ** (1 / 3)
+    return workloads.tumour(n, seed=seed, core_radius=600 * f, half=1000 * f)
+
+
+@pytest.mark.parametrize("name,maker,steps", [
+    ("plain1k", lambda: workloads.plain(), 100),
+    ("sph20k", lambda: workloads.spheroid(20000, seed=21), 200),
+    ("tumour20k", lambda: _scaled_tumour(20000, 22), 100),
+    ("ragged1001", lambda: workloads.spheroid(1001, seed=23), 150),
+])
+def test_fp64_trajectory(orc, name, maker, steps):
+    require_gpu()
+    pop = maker()
+    say("fp64", name, pop.n, steps)
+    want = orc.run_pop(pop, steps=steps, per_step=True)
+    got = run_gpu(pop, steps, per_step=True)
+    err = pos_err(got["pos"], want["pos"], pop.half_width)
+    assert err <= FP64_TOL, err
+    # v_prev after the last step is that step's velocity
+    assert np.abs(got["vel"] - want["vprev"]).max() <= 1e-9 * max(1.0, np.abs(want["vprev"]).max())
+    assert got["per_step"][0] == want["per_step_interactions"][0]
+    assert np.abs(got["per_step"] - want["per_step_interactions"]).max() <= 2
+    assert got["candidates"] == want["candidates"]
+
+
+def test_fp64_spheroid_full_1000_steps(orc):
+    """The 100k-cell two-type spheroid for its full 1,000 steps."""
+    require_gpu()
+    pop = workloads.config("sph100k")
+    say("fp64 sph100k 1000 steps")
+    got = run_gpu(pop, pop.steps)
+    want = _oracle_full(orc, "sph100k")
+    err = pos_err(got["pos"], want["pos"], pop.half_width)
+    say("fp64 sph100k err", err, "inter", got["interactions"], want["interactions"])
+    assert err <= FP64_TOL, err
+    assert abs(got["interactions"] - want["interactions"]) <= 1e-9 * want["interactions"] + 2
+
+
+@pytest.mark.parametrize("precision", [B.MECH_FP32, B.MECH_FP32_KAHAN])
+def test_fp32_spheroid_full_1000_steps(orc, precision):
+    require_gpu()
+    pop = workloads.config("sph100k")
+    say("fp32 sph100k 1000 steps", precision)
+    got = run_gpu(pop, pop.steps, precision=precision)
+    want = _oracle_full(orc, "sph100k")
+    err = pos_err(got["pos"], want["pos"], pop.half_width)
+    say("fp32 err vs fp64 oracle", err)
+    assert err <= FP32_TOL, err
+
+
+@pytest.mark.parametrize("precision", [B.MECH_FP32, B.MECH_FP32_KAHAN])
+def test_fp32_first_step_decisions_exact(orc, precision):
+    """Same float decisions as the oracle's float variant: equal counts on step 1,
+    velocities close to the float oracle's."""
+    require_gpu()
+    pop = workloads.spheroid(50000, seed=24)
+    say("fp32 step1", precision)
+    got = run_gpu(pop, 1, precision=precision)
+    want = orc.run_pop(pop, steps=1, precision=precision)
+    assert got["interactions"] == want["interactions"]
+    scale = np.abs(want["vprev"]).max()
+    assert np.abs(got["vel"] - want["vprev"]).max() <= 2e-5 * scale
+
+
+def test_tumour1m_first_step_sampled(orc):
+    """The 1M-cell tumour in FP32 + Kahan at full size: first-step velocities of sampled
+    cells (each computed alone by the oracle) and the exact interaction count."""
+    require_gpu()
+    pop = workloads.config("tumour1m")
+    say("tumour1m fp32k step 1")
+    got = run_gpu(pop, 1, precision=B.MECH_FP32_KAHAN)
+    rng = np.random.default_rng(25)
+    ids = rng.choice(pop.n, 4000, replace=False)
+    p = orc.params_of(pop)
+    v32, _ = orc.velocity_sampled(p, pop.pos, pop.radius, pop.type, ids, orc.FP32_KAHAN)
+    v64, _ = orc.velocity_sampled(p, pop.pos, pop.radius, pop.type, ids, orc.FP64)
+    scale = np.abs(v64).max()
+    assert np.abs(got["vel"][ids] - v32).max() <= 2e-5 * scale
+    assert np.abs(got["vel"][ids] - v64).max() <= 1e-4 * scale
+    _, inter, cand = orc.velocity_voxel(p, pop.pos, pop.radius, pop.type, orc.FP32_KAHAN)
+    assert got["interactions"] == inter
+    assert got["candidates"] == cand
+    # Newton's third law over the whole population
+    assert np.abs(got["vel"].sum(axis=0)).max() <= 1e-5 * np.abs(got["vel"]).sum()
+
+
+def test_tumour1m_full_run_properties():
+    """All 200 steps at full size: state finite, inside the walls, momentum balanced."""
+    require_gpu()
+    pop = workloads.config("tumour1m")
+    say("tumour1m fp32k 200 steps")
+    got = run_gpu(pop, pop.steps, precision=B.MECH_FP32_KAHAN)
+    lo, hi = np.array(pop.lo), np.array(pop.hi)
+    assert np.all(got["pos"] >= lo) and np.all(got["pos"] <= hi)
+    assert np.abs(got["vel"].sum(axis=0)).max() <= 1e-4 * np.abs(got["vel"]).sum()
+    assert got["interactions"] > 200 * 3e7
+
+
+def test_euler_start(orc):
+    require_gpu()
+    pop = workloads.plain()
+    say("euler start")
+    got = run_gpu(pop, 100, ab2_start=B.MECH_AB2_EULER_START)
+    want = orc.run_pop(pop, steps=100, euler_first=True)
+    assert pos_err(got["pos"], want["pos"], pop.half_width) <= FP64_TOL
+    zero = orc.run_pop(pop, steps=100)
+    assert pos_err(zero["pos"], want["pos"], pop.half_width) > 1e-8  # the start matters
+
+
+def test_two_cell_closed_form_on_gpu():
+    """The two-cell trajectory of the GPU path against the closed-form separation."""
+    require_gpu()
+    import mpmath as mp
+    pop = workloads.plain(2, seed=1)
+    u = np.array([1.0, 2.0, 2.0]) / 3.0
+    pop.pos = np.array([-6.0 * u, 6.0 * u])
+    pop.radius = np.array([8.4, 8.4])
+    R, RA = 16.8, 21.0
+    rho = mp.sqrt(mp.mpf("0.04"))
+    K = 2 * (10 / mp.mpf(R) ** 2 - mp.mpf("0.4") / mp.mpf(RA) ** 2)
+    s1 = R * (1 - rho) / (1 - rho / 1.25)
+    s2 = R * (1 + rho) / (1 + rho / 1.25)
+    q = (12 - s1) / (12 - s2) * mp.e ** (K * (s1 - s2) * 10)
+    exact = float((s1 - s2 * q) / (1 - q))
+    got = run_gpu(pop, 100, ab2_start=B.MECH_AB2_EULER_START)
+    s = np.linalg.norm(got["pos"][1] - got["pos"][0])
+    assert abs(s - exact) < 5e-4

@@ -1,0 +1,155 @@
+"""Runtime behaviour of the HIP path: determinism, HIP graphs against eager launches,
+resume from read-back state, caller-owned workspace and stream, edge cases."""
+import numpy as np
+import pytest
+
+import workloads
+from gpu_helpers import pos_err, require_gpu, run_gpu, say
+from paper_2306_11544_amd import binding as B
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("precision", [B.MECH_FP64, B.MECH_FP32_KAHAN])
+def test_bitwise_deterministic(precision):
+    require_gpu()
+    pop = workloads.spheroid(30000, seed=31)
+    say("determinism", precision)
+    a = run_gpu(pop, 60, precision=precision)
+    b = run_gpu(pop, 60, precision=precision)
+    assert np.array_equal(a["pos"], b["pos"]) and np.array_equal(a["vel"], b["vel"])
+    assert a["interactions"] == b["interactions"]
+
+
+@pytest.mark.parametrize("precision", [B.MECH_FP64, B.MECH_FP32])
+def test_graph_replays_equal_eager(precision):
+    """Each replay of the captured step equals the eager launch of the same step,
+    with reads and synchronisations between the replays."""
+    require_gpu()
+    pop = workloads.spheroid(20000, seed=32)
+    say("graph vs eager", precision)
+    pg = B.Population(B.params_of(pop, precision), pop.pos, pop.radius, pop.type)
+    pe = B.Population(B.params_of(pop, precision, flags=B.MECH_FLAG_NO_GRAPH), pop.pos,
+                      pop.radius, pop.type)
+    try:
+        for k in range(8):
+            pg.step(1)
+            pe.step(1)
+            a, va = pg.state()
+            b, vb = pe.state()
+            assert np.array_equal(a, b) and np.array_equal(va, vb), k
+            assert pg.stats() == pe.stats()
+        pg.step(5)
+        pe.step(5)
+        assert np.array_equal(pg.state()[0], pe.state()[0])
+    finally:
+        pg.close()
+        pe.close()
+
+
+@pytest.mark.parametrize("precision", [B.MECH_FP64, B.MECH_FP32_KAHAN])
+def test_resume_is_bitwise(precision):
+    require_gpu()
+    pop = workloads.spheroid(10000, seed=33)
+    say("resume", precision)
+    full = run_gpu(pop, 80, precision=precision)
+    half = run_gpu(pop, 40, precision=precision)
+    pop2 = workloads.spheroid(10000, seed=33)
+    pop2.pos = half["pos"]
+    rest = run_gpu(pop2, 40, precision=precision, prev_velocity=half["vel"])
+    assert np.array_equal(full["pos"], rest["pos"])
+    assert np.array_equal(full["vel"], rest["vel"])
+
+
+def test_workspace_and_stream_from_torch():
+    require_gpu()
+    import torch
+    pop = workloads.spheroid(8000, seed=34)
+    say("torch workspace")
+    p = B.params_of(pop, B.MECH_FP32_KAHAN)
+    nbytes = B.population_workspace_bytes(p, pop.n)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.Stream()
+    with B.Population(p, pop.pos, pop.radius, pop.type, stream=stream.cuda_stream,
+                      workspace=ws) as P:
+        assert P.stream == stream.cuda_stream
+        P.step(30)
+        a, _ = P.state()
+    b = run_gpu(pop, 30, precision=B.MECH_FP32_KAHAN)["pos"]
+    assert np.array_equal(a, b)
+    small = torch.empty(nbytes // 2, dtype=torch.uint8, device="cuda")
+    with pytest.raises(B.MechError) as e:
+        B.Population(p, pop.pos, pop.radius, pop.type, workspace=small)
+    assert e.value.code == B.MECH_E_NOMEM
+
+
+def test_empty_population():
+    require_gpu()
+    pop = workloads.plain(0, seed=35)
+    say("empty")
+    got = run_gpu(pop, 5)
+    assert got["pos"].shape == (0, 3) and got["interactions"] == 0
+
+
+def test_single_and_isolated_cells(orc):
+    require_gpu()
+    pop = workloads.plain(3, seed=36)
+    pop.pos = np.array([[0.0, 0.0, 0.0], [60.0, 60.0, 60.0], [-90.0, 90.0, 0.0]])
+    say("isolated")
+    got = run_gpu(pop, 20)
+    assert np.array_equal(got["pos"], pop.pos) and got["interactions"] == 0
+
+
+def test_coincident_pile(orc):
+    """Cells stacked at one point (d = 0) skip each other; a jittered pile of thousands
+    of cells in one voxel is the worst case of the in-voxel rank and of the force loop."""
+    require_gpu()
+    pop = workloads.plain(500, seed=37)
+    pop.pos = np.zeros((500, 3))
+    say("pile exact")
+    got = run_gpu(pop, 3)
+    assert np.array_equal(got["pos"], pop.pos)
+    pop = workloads.plain(4000, seed=38)
+    rng = np.random.default_rng(39)
+    pop.pos = rng.uniform(-2.0, 2.0, size=(pop.n, 3))
+    say("pile jitter")
+    want = orc.run_pop(pop, steps=5)
+    got = run_gpu(pop, 5)
+    assert pos_err(got["pos"], want["pos"], pop.half_width) <= 1e-10
+    assert got["interactions"] == want["interactions"]
+
+
+def test_walls_and_flat_domain(orc):
+    require_gpu()
+    pop = workloads.plain(3000, seed=40, half=60.0)
+    pop.pos[:200, 0] = pop.hi[0]
+    pop.pos[200:400, 2] = pop.lo[2]
+    say("walls")
+    want = orc.run_pop(pop, steps=50)
+    got = run_gpu(pop, 50)
+    assert pos_err(got["pos"], want["pos"], pop.half_width) <= 1e-10
+    flat = workloads.plain(1500, seed=41)
+    flat.lo = (flat.lo[0], flat.lo[1], 0.0)
+    flat.hi = (flat.hi[0], flat.hi[1], 0.0)
+    flat.pos[:, 2] = 0.0
+    say("flat")
+    want = orc.run_pop(flat, steps=50)
+    got = run_gpu(flat, 50)
+    assert pos_err(got["pos"], want["pos"], flat.half_width) <= 1e-10
+    assert np.all(got["pos"][:, 2] == 0.0)
+
+
+def test_nonfinite_state_is_reported():
+    """A finite but huge c_rep overflows the velocity to inf (w / d with d = 1e-3);
+    read_state says so.  Positions stay finite: the walls clamp them."""
+    require_gpu()
+    pop = workloads.plain(2, seed=42)
+    pop.pos = np.array([[0.0, 0.0, 0.0], [1e-3, 0.0, 0.0]])
+    pop.c_rep = 1e308
+    say("nonfinite")
+    p = B.params_of(pop)
+    with B.Population(p, pop.pos, pop.radius, pop.type) as P:
+        P.step(1)
+        with pytest.raises(B.MechError) as e:
+            P.state()
+        assert e.value.code == B.MECH_E_NONFINITE
