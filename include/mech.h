@@ -62,7 +62,10 @@ enum { MECH_FP64 = 0, MECH_FP32 = 1, MECH_FP32_KAHAN = 2 };
 enum { MECH_AB2_ZERO_HISTORY = 0, MECH_AB2_EULER_START = 1 };
 /* MechParams.flags bits */
 enum {
-    MECH_FLAG_NO_GRAPH = 1        /* launch each step's kernels directly (no HIP graph) */
+    MECH_FLAG_NO_GRAPH = 1,       /* launch each step's kernels directly (no HIP graph) */
+    MECH_FLAG_SIMPLE_FORCE = 2    /* one thread per cell reading neighbours from global
+                                     memory, instead of the LDS-staged wave-per-voxel
+                                     force kernel (same results up to summation order) */
 };
 
 typedef struct MechParams {

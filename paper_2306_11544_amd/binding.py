@@ -20,6 +20,7 @@ MECH_E_NOMEM, MECH_E_BUDGET, MECH_E_DEVICE, MECH_E_NONFINITE, MECH_E_FULL = -4, 
 MECH_FP64, MECH_FP32, MECH_FP32_KAHAN = 0, 1, 2
 MECH_AB2_ZERO_HISTORY, MECH_AB2_EULER_START = 0, 1
 MECH_FLAG_NO_GRAPH = 1
+MECH_FLAG_SIMPLE_FORCE = 2
 MECH_ABI_VERSION = 1
 
 PRECISIONS = {"fp64": MECH_FP64, "fp32": MECH_FP32, "fp32k": MECH_FP32_KAHAN}
@@ -52,6 +53,12 @@ def lib():
     """Load libmech.so (raises if it is missing: build it with paper_2306_11544_amd.build)."""
     global _lib
     if _lib is None:
+        try:
+            # torch ships its own HIP runtime; loading it first makes libmech.so bind to
+            # that same runtime, so torch streams and memory are valid in both
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: run `python -m paper_2306_11544_amd.build` "
                               "(the mechanics step has no CPU fallback)")

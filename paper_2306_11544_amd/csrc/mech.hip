@@ -34,6 +34,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "mech.h"
@@ -193,10 +194,12 @@ __global__ __launch_bounds__(BLOCK) void k_scan_reduce(const uint32_t* __restric
 
 __global__ __launch_bounds__(BLOCK) void k_scan_top(uint64_t* __restrict__ tsum, uint32_t nt,
                                                     uint32_t* __restrict__ voxel_start,
-                                                    uint32_t V, uint32_t* __restrict__ n_occ)
+                                                    uint32_t V, uint32_t* __restrict__ n_occ,
+                                                    uint32_t* __restrict__ work_counter)
 {
     __shared__ uint64_t sh[BLOCK / WAVE];
     uint64_t carry = 0;
+    if (threadIdx.x == 0) *work_counter = 0u;  // the force kernel of this step hands out voxels
     for (uint32_t base = 0; base < nt; base += BLOCK) {
         uint32_t i = base + threadIdx.x;
         uint64_t x = i < nt ? tsum[i] : 0;
@@ -519,6 +522,214 @@ __global__ __launch_bounds__(BLOCK) void k_force_rows(uint32_t n, PhysArgs P, Fo
     add_stats(a.stats, inter, cand);
 }
 
+// ------------------------------------------------------------------------ a6 + a7, LDS-staged
+
+// Per-wave LDS: the candidates of one chunk of the 27-voxel neighbourhood (x, y, z, r),
+// their types, and per-lane lists of in-range candidate indices.
+constexpr int FL_WAVES = 4;                // waves per workgroup
+constexpr int FL_LIST = 16;                // list entries per lane before a flush
+
+template <int PREC> struct Stage;
+template <> struct Stage<0> { using T = double4; static constexpr int CAP = 256; };
+template <> struct Stage<1> { using T = float4; static constexpr int CAP = 512; };
+template <> struct Stage<2> { using T = float4; static constexpr int CAP = 512; };
+
+// Orders this wave's LDS accesses: writes by one lane are seen by the others after it.
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// In-range decision only (the term is computed later from the list).
+__device__ __forceinline__ bool in_range64(const double4& me, const double4& c, double alpha)
+{
+#pragma clang fp contract(off)
+    const double dx = me.x - c.x, dy = me.y - c.y, dz = me.z - c.z;
+    const double d2 = dx * dx + dy * dy + dz * dz;
+    const double RA = alpha * (me.w + c.w);
+    return d2 > 0.0 && d2 < RA * RA;
+}
+
+__device__ __forceinline__ bool in_range32(const float4& me, const float4& c, float alpha)
+{
+#pragma clang fp contract(off)
+    const float dx = me.x - c.x, dy = me.y - c.y, dz = me.z - c.z;
+    const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
+    const float RA = alpha * (me.w + c.w);
+    return d2 > 0.0f && d2 < RA * RA;
+}
+
+// One wave per occupied voxel, taken from a global counter (fine-grained dynamic
+// schedule over non-empty voxels).  The wave stages its 27-voxel neighbourhood in LDS
+// (9 rows, each a contiguous range of the voxel-ordered arrays) and splits its lanes
+// as (target, slice): target t of r = min(64, remaining) takes lanes t, t + r, ...,
+// so all 64 lanes test candidates.  A lane appends the in-range candidates of its slice
+// to an LDS list and evaluates them in a batch, so the force arithmetic does not
+// diverge on the rare in-range branch.  Slices are combined in a fixed order: results
+// are bitwise reproducible.
+template <int PREC, bool MULTI, typename VPT>
+__global__ __launch_bounds__(FL_WAVES * WAVE) void k_force_lds(PhysArgs P, ForceArgs<VPT> a,
+                                                               const uint32_t* __restrict__ occ,
+                                                               const uint32_t* __restrict__ n_occ,
+                                                               uint32_t* __restrict__ counter)
+{
+    using CT = typename Stage<PREC>::T;
+    using Real = typename std::conditional<PREC == 0, double, float>::type;
+    constexpr int CAP = Stage<PREC>::CAP;
+    __shared__ CT s_stage[FL_WAVES][CAP];
+    __shared__ uint8_t s_type[FL_WAVES][MULTI ? CAP : 1];
+    __shared__ uint16_t s_list[FL_WAVES][FL_LIST][WAVE];
+
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int w = threadIdx.x / WAVE;
+    CT* stage = s_stage[w];
+    const uint32_t M = *n_occ;
+    uint32_t inter = 0, cand = 0;
+
+    for (;;) {
+        uint32_t o = 0;
+        if (lane == 0) o = atomicAdd(counter, 1u);
+        o = __builtin_amdgcn_readfirstlane(__shfl(o, 0, WAVE));
+        if (o >= M) break;
+        const uint32_t vox = __builtin_amdgcn_readfirstlane(occ[o]);
+        const int kx = (int)(vox % (uint32_t)P.nx);
+        const int ky = (int)((vox / (uint32_t)P.nx) % (uint32_t)P.ny);
+        const int kz = (int)(vox / ((uint32_t)P.nx * (uint32_t)P.ny));
+        const int x0 = kx > 0 ? kx - 1 : 0;
+        const int x1 = kx < P.nx - 1 ? kx + 1 : P.nx - 1;
+        // the 9 rows in (dz, dy) order; rows outside the grid are empty
+        uint32_t rb[9], pre[10];
+        pre[0] = 0;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            const int y = ky + (q % 3) - 1, z = kz + (q / 3) - 1;
+            uint32_t b = 0, e = 0;
+            if (y >= 0 && y < P.ny && z >= 0 && z < P.nz) {
+                const uint32_t row = (uint32_t)P.nx * ((uint32_t)y + (uint32_t)P.ny * (uint32_t)z);
+                b = a.voxel_start[row + x0];
+                e = a.voxel_start[row + x1 + 1];
+            }
+            rb[q] = b;
+            pre[q + 1] = pre[q] + (e - b);
+        }
+        const uint32_t C = pre[9];
+        const uint32_t vb = a.voxel_start[vox], k = a.voxel_start[vox + 1] - vb;
+
+        for (uint32_t t0 = 0; t0 < k; t0 += WAVE) {
+            const uint32_t r = min((uint32_t)WAVE, k - t0);
+            const uint32_t t = (uint32_t)lane % r, s = (uint32_t)lane / r;
+            const uint32_t St = (uint32_t)WAVE / r + (t < (uint32_t)WAVE % r ? 1u : 0u);
+            const uint32_t i = vb + t0 + t;
+            CT me;
+            if constexpr (PREC == 0) {
+                me = make_double4(a.XS[0][i], a.XS[1][i], a.XS[2][i], a.R[i]);
+            } else {
+                me = a.SH[i];
+            }
+            const int ti = MULTI ? a.T[i] : 0;
+            Real acc[3] = {0, 0, 0}, cmp[3] = {0, 0, 0};
+            uint32_t cnt = 0;
+
+            // evaluate this lane's listed candidates in order, then empty the list
+            auto flush = [&]() {
+                for (uint32_t q = 0; q < (uint32_t)FL_LIST; ++q) {
+                    if (!__any(q < cnt)) break;
+                    if (q < cnt) {
+                        const uint32_t m = s_list[w][q][lane];
+                        const CT c = stage[m];
+                        if constexpr (PREC == 0) {
+                            const double cadh = MULTI ? a.cadh[ti * P.n_types + s_type[w][m]] : P.c_adh0;
+                            pair64(me.x, me.y, me.z, me.w, c.x, c.y, c.z, c.w, P.alpha, P.c_rep, cadh,
+                                   acc[0], acc[1], acc[2]);
+                        } else {
+                            const float cadh = MULTI ? a.cadh_f[ti * P.n_types + s_type[w][m]] : P.c_adh0_f;
+                            pair32<PREC == 2>(me.x, me.y, me.z, me.w, c, P.alpha_f, P.c_rep_f, cadh, acc, cmp);
+                        }
+                    }
+                }
+                cnt = 0;
+            };
+
+            for (uint32_t cb = 0; cb < C; cb += CAP) {
+                const uint32_t len = min((uint32_t)CAP, C - cb);
+                wave_sync();
+                for (uint32_t f = lane; f < len; f += WAVE) {
+                    const uint32_t ff = cb + f;
+                    uint32_t g = ff + rb[0];
+#pragma unroll
+                    for (int q = 1; q < 9; ++q)
+                        if (ff >= pre[q]) g = ff - pre[q] + rb[q];
+                    if constexpr (PREC == 0) {
+                        stage[f] = make_double4(a.XS[0][g], a.XS[1][g], a.XS[2][g], a.R[g]);
+                    } else {
+                        stage[f] = a.SH[g];
+                    }
+                    if (MULTI) s_type[w][f] = (uint8_t)a.T[g];
+                }
+                wave_sync();
+                for (uint32_t m = s; m < len; m += St) {
+                    bool in;
+                    if constexpr (PREC == 0)
+                        in = in_range64(me, stage[m], P.alpha);
+                    else
+                        in = in_range32(me, stage[m], P.alpha_f);
+                    if (in) {
+                        s_list[w][cnt][lane] = (uint16_t)m;
+                        ++cnt;
+                    }
+                    if (__any(cnt == (uint32_t)FL_LIST)) {
+                        inter += cnt;
+                        flush();
+                    }
+                }
+                inter += cnt;
+                flush();
+            }
+            // combine the slices of each target in slice order
+            wave_sync();
+            Real* part = reinterpret_cast<Real*>(stage);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                part[lane * 6 + c] = acc[c];
+                part[lane * 6 + 3 + c] = cmp[c];
+            }
+            wave_sync();
+            if (s == 0) {
+                Real tot[3] = {0, 0, 0}, tc[3] = {0, 0, 0};
+                for (uint32_t q = 0; q < St; ++q) {
+                    const uint32_t l = t + q * r;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const Real term = part[l * 6 + c] - part[l * 6 + 3 + c];
+                        if (PREC == 2) {
+                            const Real y = term - tc[c];
+                            const Real tt = tot[c] + y;
+                            tc[c] = (tt - tot[c]) - y;
+                            tot[c] = tt;
+                        } else {
+                            tot[c] += term;
+                        }
+                    }
+                }
+                cand += C - 1;
+                const double xs[3] = {a.XS[0][i], a.XS[1][i], a.XS[2][i]};
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const double v = (double)tot[c];
+                    const double vp = a.euler ? v : (double)a.VP[c][i];
+                    const double xn = xs[c] + P.dt * (1.5 * v - 0.5 * vp);
+                    a.X[c][i] = reflect(xn, (&P.lo[0])[c], (&P.hi[0])[c]);
+                    a.VP[c][i] = (VPT)v;
+                }
+            }
+            wave_sync();
+        }
+    }
+    add_stats(a.stats, inter, cand);
+}
+
 // read_state: voxel order -> id order, interleaved xyz.
 template <typename VPT>
 __global__ __launch_bounds__(BLOCK) void k_unpermute(uint32_t n, const uint32_t* __restrict__ id,
@@ -601,7 +812,8 @@ int validate(const MechParams* p, int64_t n, int32_t dims[3])
         return fail(MECH_E_INVALID, "precision %d unknown", p->precision);
     if (p->ab2_start != MECH_AB2_ZERO_HISTORY && p->ab2_start != MECH_AB2_EULER_START)
         return fail(MECH_E_INVALID, "ab2_start %d unknown", p->ab2_start);
-    if (p->flags & ~MECH_FLAG_NO_GRAPH) return fail(MECH_E_INVALID, "unknown flags 0x%x", p->flags);
+    if (p->flags & ~(MECH_FLAG_NO_GRAPH | MECH_FLAG_SIMPLE_FORCE))
+        return fail(MECH_E_INVALID, "unknown flags 0x%x", p->flags);
     if (p->reserved != 0) return fail(MECH_E_INVALID, "reserved field must be 0");
     if (n < 0 || n >= (int64_t(1) << 31)) return fail(MECH_E_INVALID, "n_cells %lld out of range", (long long)n);
     if (!(std::isfinite(p->voxel_size) && p->voxel_size > 0))
@@ -666,6 +878,7 @@ struct MechPopulation {
     int64_t n = 0;
     int32_t dims[3] = {1, 1, 1};
     uint32_t V = 1, n_tiles = 1;
+    uint32_t force_grid = 1024;  // workgroups of the persistent force kernel
     GridArgs grid{};
     PhysArgs phys{};
     hipStream_t stream = nullptr;
@@ -698,7 +911,8 @@ void enqueue_binning(MechPopulation* P)
     hipLaunchKernelGGL(k_scan_reduce, dim3(P->n_tiles), dim3(BLOCK), 0, P->stream,
                        P->at<uint32_t>(L.count), P->V, P->at<uint64_t>(L.tsum));
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(BLOCK), 0, P->stream, P->at<uint64_t>(L.tsum),
-                       P->n_tiles, P->at<uint32_t>(L.start), P->V, P->at<uint32_t>(L.n_occ));
+                       P->n_tiles, P->at<uint32_t>(L.start), P->V, P->at<uint32_t>(L.n_occ),
+                       P->at<uint32_t>(L.n_occ) + 1);
     hipLaunchKernelGGL(k_scan_down, dim3(P->n_tiles), dim3(BLOCK), 0, P->stream,
                        P->at<uint32_t>(L.count), P->V, P->at<uint64_t>(L.tsum),
                        P->at<uint32_t>(L.start), P->at<uint32_t>(L.occ));
@@ -747,11 +961,24 @@ void enqueue_force(MechPopulation* P, int parity_after_sort, int euler)
     a.cadh_f = P->at<float>(L.cadh_f);
     a.stats = P->at<unsigned long long>(L.stats);
     a.euler = euler;
-    const uint32_t nb = blocks_for(n, BLOCK);
+    if (P->prm.flags & MECH_FLAG_SIMPLE_FORCE) {
+        const uint32_t nb = blocks_for(n, BLOCK);
+        if (P->prm.n_types > 1)
+            hipLaunchKernelGGL((k_force_rows<PREC, true, VPT>), dim3(nb), dim3(BLOCK), 0, P->stream, n, P->phys, a);
+        else
+            hipLaunchKernelGGL((k_force_rows<PREC, false, VPT>), dim3(nb), dim3(BLOCK), 0, P->stream, n, P->phys, a);
+        return;
+    }
+    // persistent grid of fixed size (graph-safe); waves take occupied voxels until none is left
+    const uint32_t* occ = P->at<uint32_t>(L.occ);
+    const uint32_t* m = P->at<uint32_t>(L.n_occ);
+    uint32_t* ctr = P->at<uint32_t>(L.n_occ) + 1;
     if (P->prm.n_types > 1)
-        hipLaunchKernelGGL((k_force_rows<PREC, true, VPT>), dim3(nb), dim3(BLOCK), 0, P->stream, n, P->phys, a);
+        hipLaunchKernelGGL((k_force_lds<PREC, true, VPT>), dim3(P->force_grid), dim3(FL_WAVES * WAVE), 0,
+                           P->stream, P->phys, a, occ, m, ctr);
     else
-        hipLaunchKernelGGL((k_force_rows<PREC, false, VPT>), dim3(nb), dim3(BLOCK), 0, P->stream, n, P->phys, a);
+        hipLaunchKernelGGL((k_force_lds<PREC, false, VPT>), dim3(P->force_grid), dim3(FL_WAVES * WAVE), 0,
+                           P->stream, P->phys, a, occ, m, ctr);
 }
 
 // One full step a1..a7 from the current parity; flips nothing on the host.
@@ -837,6 +1064,12 @@ int create_impl(const MechParams* params, int64_t n, const double* pos, const do
         P->phys.hi[a] = params->domain_hi[a];
     }
     P->grid.inv_h = 1.0 / params->voxel_size;
+    {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, P->device) != hipSuccess || cus < 1)
+            cus = 256;
+        P->force_grid = (uint32_t)cus * 4u;  // a few resident workgroups per CU
+    }
     P->grid.V = P->V;
     P->phys.dt = params->dt;
     P->phys.c_rep = params->c_rep;

@@ -1,7 +1,11 @@
 """Shared helpers of the GPU parity tests (not collected: no test_ prefix)."""
+import json
+import os
 import sys
 
 import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 from paper_2306_11544_amd import binding as B
 
@@ -39,6 +43,29 @@ def run_gpu(pop, steps, precision=B.MECH_FP64, ab2_start=B.MECH_AB2_ZERO_HISTORY
     if per_step:
         out["per_step"] = np.array(per, dtype=np.int64)
     return out
+
+
+def record(case, err, **extra):
+    """Append a parity error to gpurun_out/parity_errors.jsonl (the error table)."""
+    out = os.environ.get("MECH_PARITY_LOG", os.path.join(ROOT, "gpurun_out", "parity_errors.jsonl"))
+    if os.path.isdir(os.path.dirname(out)):
+        with open(out, "a") as f:
+            f.write(json.dumps({"case": case, "err": float(err), **extra}) + "\n")
+
+
+def assert_well_posed(orc, pop, steps, bar=1e-10):
+    """The oracle's own trajectory moves by far less than the bar when every input
+    coordinate is nudged by one ulp, and when the cells are relabelled (which changes
+    the order of every force sum).  Otherwise the case is chaotic at this horizon and
+    no implementation that sums in another order could be held to the bar."""
+    p = orc.params_of(pop)
+    a = orc.run(p, pop.pos, pop.radius, pop.type, steps=steps)["pos"]
+    b = orc.run(p, np.nextafter(pop.pos, 0.0), pop.radius, pop.type, steps=steps)["pos"]
+    perm = np.random.default_rng(0).permutation(pop.n)
+    c = np.empty_like(a)
+    c[perm] = orc.run(p, pop.pos[perm], pop.radius[perm], pop.type[perm], steps=steps)["pos"]
+    sens = max(pos_err(a, b, pop.half_width), pos_err(a, c, pop.half_width))
+    assert sens <= bar / 100, f"ill-posed case: sensitivity {sens:.2e}"
 
 
 def pos_err(a, b, S):

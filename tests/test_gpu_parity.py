@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import workloads
-from gpu_helpers import pos_err, require_gpu, run_gpu, say
+from gpu_helpers import assert_well_posed, pos_err, record, require_gpu, run_gpu, say
 from paper_2306_11544_amd import binding as B
 
 pytestmark = pytest.mark.gpu
@@ -42,10 +42,12 @@ def _scaled_tumour(n, seed):
 def test_fp64_trajectory(orc, name, maker, steps):
     require_gpu()
     pop = maker()
+    assert_well_posed(orc, pop, steps)
     say("fp64", name, pop.n, steps)
     want = orc.run_pop(pop, steps=steps, per_step=True)
     got = run_gpu(pop, steps, per_step=True)
     err = pos_err(got["pos"], want["pos"], pop.half_width)
+    record(f"fp64 {name} {steps} steps", err)
     assert err <= FP64_TOL, err
     # v_prev after the last step is that step's velocity
     assert np.abs(got["vel"] - want["vprev"]).max() <= 1e-9 * max(1.0, np.abs(want["vprev"]).max())
@@ -62,7 +64,8 @@ def test_fp64_spheroid_full_1000_steps(orc):
     got = run_gpu(pop, pop.steps)
     want = _oracle_full(orc, "sph100k")
     err = pos_err(got["pos"], want["pos"], pop.half_width)
-    say("fp64 sph100k err", err, "inter", got["interactions"], want["interactions"])
+    record("fp64 sph100k 1000 steps", err, interactions=got["interactions"],
+           oracle_interactions=want["interactions"])
     assert err <= FP64_TOL, err
     assert abs(got["interactions"] - want["interactions"]) <= 1e-9 * want["interactions"] + 2
 
@@ -75,7 +78,8 @@ def test_fp32_spheroid_full_1000_steps(orc, precision):
     got = run_gpu(pop, pop.steps, precision=precision)
     want = _oracle_full(orc, "sph100k")
     err = pos_err(got["pos"], want["pos"], pop.half_width)
-    say("fp32 err vs fp64 oracle", err)
+    record(f"{'fp32k' if precision == B.MECH_FP32_KAHAN else 'fp32'} sph100k 1000 steps "
+           "vs fp64 oracle", err)
     assert err <= FP32_TOL, err
 
 
@@ -106,6 +110,10 @@ def test_tumour1m_first_step_sampled(orc):
     v32, _ = orc.velocity_sampled(p, pop.pos, pop.radius, pop.type, ids, orc.FP32_KAHAN)
     v64, _ = orc.velocity_sampled(p, pop.pos, pop.radius, pop.type, ids, orc.FP64)
     scale = np.abs(v64).max()
+    record("fp32k tumour1m step-1 velocity vs fp32k oracle (rel. to max|v|)",
+           np.abs(got["vel"][ids] - v32).max() / scale)
+    record("fp32k tumour1m step-1 velocity vs fp64 oracle (rel. to max|v|)",
+           np.abs(got["vel"][ids] - v64).max() / scale)
     assert np.abs(got["vel"][ids] - v32).max() <= 2e-5 * scale
     assert np.abs(got["vel"][ids] - v64).max() <= 1e-4 * scale
     _, inter, cand = orc.velocity_voxel(p, pop.pos, pop.radius, pop.type, orc.FP32_KAHAN)
@@ -133,7 +141,9 @@ def test_euler_start(orc):
     say("euler start")
     got = run_gpu(pop, 100, ab2_start=B.MECH_AB2_EULER_START)
     want = orc.run_pop(pop, steps=100, euler_first=True)
-    assert pos_err(got["pos"], want["pos"], pop.half_width) <= FP64_TOL
+    err = pos_err(got["pos"], want["pos"], pop.half_width)
+    record("fp64 plain1k euler start 100 steps", err)
+    assert err <= FP64_TOL
     zero = orc.run_pop(pop, steps=100)
     assert pos_err(zero["pos"], want["pos"], pop.half_width) > 1e-8  # the start matters
 

@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 import workloads
-from gpu_helpers import pos_err, require_gpu, run_gpu, say
+from gpu_helpers import assert_well_posed, pos_err, record, require_gpu, run_gpu, say
 from paper_2306_11544_amd import binding as B
 
 pytestmark = pytest.mark.gpu
@@ -113,29 +113,46 @@ def test_coincident_pile(orc):
     rng = np.random.default_rng(39)
     pop.pos = rng.uniform(-2.0, 2.0, size=(pop.n, 3))
     say("pile jitter")
-    want = orc.run_pop(pop, steps=5)
-    got = run_gpu(pop, 5)
-    assert pos_err(got["pos"], want["pos"], pop.half_width) <= 1e-10
+    # 4000 cells inside 4 um: each velocity is a sum of ~4000 terms of size up to c_rep
+    # that nearly cancel, so its rounding depends on the summation order and the
+    # trajectory is chaotic from the first steps (a relabelling of the cells changes it
+    # at O(1) in the oracle alone).  What the definition fixes is compared instead:
+    # the exact pair count, and step-1 velocities to the rounding of such sums.
+    want = orc.run_pop(pop, steps=1)
+    got = run_gpu(pop, 1)
     assert got["interactions"] == want["interactions"]
+    n_terms = pop.n - 1
+    bound = 4 * n_terms * np.finfo(np.float64).eps * pop.c_rep * n_terms ** 0.5
+    assert np.abs(got["vel"] - want["vprev"]).max() <= bound
+    assert np.abs(got["vel"].sum(axis=0)).max() <= pop.n * bound
 
 
 def test_walls_and_flat_domain(orc):
+    """Cells pressed on walls, and a flat (2D) domain.  Densities stay near the 1k-cell
+    workload's: far denser packings are chaotic, and a one-ulp change of the input then
+    grows past the FP64 bar within tens of steps in the oracle alone."""
     require_gpu()
-    pop = workloads.plain(3000, seed=40, half=60.0)
-    pop.pos[:200, 0] = pop.hi[0]
-    pop.pos[200:400, 2] = pop.lo[2]
+    pop = workloads.plain(600, seed=40, half=60.0)
+    pop.pos[:100, 0] = pop.hi[0]
+    pop.pos[100:200, 2] = pop.lo[2]
+    assert_well_posed(orc, pop, 50)
     say("walls")
     want = orc.run_pop(pop, steps=50)
     got = run_gpu(pop, 50)
-    assert pos_err(got["pos"], want["pos"], pop.half_width) <= 1e-10
-    flat = workloads.plain(1500, seed=41)
+    err = pos_err(got["pos"], want["pos"], pop.half_width)
+    record("fp64 walls600 50 steps", err)
+    assert err <= 1e-10
+    flat = workloads.plain(300, seed=41)
     flat.lo = (flat.lo[0], flat.lo[1], 0.0)
     flat.hi = (flat.hi[0], flat.hi[1], 0.0)
     flat.pos[:, 2] = 0.0
+    assert_well_posed(orc, flat, 50)
     say("flat")
     want = orc.run_pop(flat, steps=50)
     got = run_gpu(flat, 50)
-    assert pos_err(got["pos"], want["pos"], flat.half_width) <= 1e-10
+    err = pos_err(got["pos"], want["pos"], flat.half_width)
+    record("fp64 flat300 50 steps", err)
+    assert err <= 1e-10
     assert np.all(got["pos"][:, 2] == 0.0)
 
 
