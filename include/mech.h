@@ -63,9 +63,13 @@ enum { MECH_AB2_ZERO_HISTORY = 0, MECH_AB2_EULER_START = 1 };
 /* MechParams.flags bits */
 enum {
     MECH_FLAG_NO_GRAPH = 1,       /* launch each step's kernels directly (no HIP graph) */
-    MECH_FLAG_SIMPLE_FORCE = 2    /* one thread per cell reading neighbours from global
-                                     memory, instead of the LDS-staged wave-per-voxel
-                                     force kernel (same results up to summation order) */
+    MECH_FLAG_SIMPLE_FORCE = 2,   /* force kernel variant: one thread per cell evaluating
+                                     every candidate inline (no in-range lists)          */
+    MECH_FLAG_VOXEL_FORCE = 4     /* force kernel variant: one wave per occupied voxel with
+                                     the neighbourhood staged in LDS.  Without either
+                                     flag: one thread per cell with in-range lists.  All
+                                     variants give the same results up to summation
+                                     order and are each deterministic.                   */
 };
 
 typedef struct MechParams {

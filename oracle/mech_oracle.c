@@ -38,7 +38,8 @@
  * FP32 variant (an approximation; it fixes what the FP32 kernels compute): positions
  * and radii are rounded to float once per step, the pair arithmetic runs in float with
  * d2 = fma(dz, dz, fma(dy, dy, dx*dx)) (two fused multiply-adds, correctly rounded),
- * the force sum is plain float or Kahan-compensated per component, and the update in
+ * the force sum is plain float or Kahan-compensated per component (the compensated
+ * result being sum - c, the running sum less its carried correction), and the update in
  * step 4 runs in double on the float velocity; v_prev holds the float velocity.
  *
  * Everything is compiled with -ffp-contract=off so that d2 and the in-range decision
@@ -186,7 +187,7 @@ float oracle_sum_f32(const float* x, int64_t n, int32_t kahan)
 {
     float s = 0.0f, c = 0.0f;
     for (int64_t i = 0; i < n; ++i) accumulate_f32(&s, &c, x[i], kahan);
-    return s;
+    return s - c;
 }
 
 /* ------------------------------------------------------------------ velocities */
@@ -225,7 +226,7 @@ int32_t oracle_velocity_allpairs(const OracleParams* p, int64_t n, const double*
                 inter += pair_f32(p, pf + 3 * i, rf[i], ti, pf + 3 * j, rf[j],
                                   type ? type[j] : 0, &acc, precision == OR_FP32_KAHAN);
             }
-            for (int c = 0; c < 3; ++c) vel[3 * i + c] = (double)acc.s[c];
+            for (int c = 0; c < 3; ++c) vel[3 * i + c] = (double)(acc.s[c] - acc.c[c]);
         }
     }
     free(pf);
@@ -294,7 +295,7 @@ int32_t oracle_velocity_voxel(const OracleParams* p, int64_t n, const double* po
                     }
                 }
         for (int c = 0; c < 3; ++c)
-            vel[3 * i + c] = (precision == OR_FP64) ? acc[c] : (double)accf.s[c];
+            vel[3 * i + c] = (precision == OR_FP64) ? acc[c] : (double)(accf.s[c] - accf.c[c]);
     }
     if (interactions) *interactions = inter;
     if (candidates) *candidates = cand;
@@ -410,7 +411,7 @@ int32_t oracle_velocity_sampled(const OracleParams* p, int64_t n, const double* 
                     }
                 }
         for (int c = 0; c < 3; ++c)
-            vel[3 * k + c] = (precision == OR_FP64) ? acc[c] : (double)accf.s[c];
+            vel[3 * k + c] = (precision == OR_FP64) ? acc[c] : (double)(accf.s[c] - accf.c[c]);
     }
     if (interactions) *interactions = inter;
 done:

@@ -194,12 +194,10 @@ __global__ __launch_bounds__(BLOCK) void k_scan_reduce(const uint32_t* __restric
 
 __global__ __launch_bounds__(BLOCK) void k_scan_top(uint64_t* __restrict__ tsum, uint32_t nt,
                                                     uint32_t* __restrict__ voxel_start,
-                                                    uint32_t V, uint32_t* __restrict__ n_occ,
-                                                    uint32_t* __restrict__ work_counter)
+                                                    uint32_t V, uint32_t* __restrict__ n_occ)
 {
     __shared__ uint64_t sh[BLOCK / WAVE];
     uint64_t carry = 0;
-    if (threadIdx.x == 0) *work_counter = 0u;  // the force kernel of this step hands out voxels
     for (uint32_t base = 0; base < nt; base += BLOCK) {
         uint32_t i = base + threadIdx.x;
         uint64_t x = i < nt ? tsum[i] : 0;
@@ -432,13 +430,18 @@ __device__ __forceinline__ bool pair32(float xi, float yi, float zi, float ri, f
     return true;
 }
 
+// Running counters are spread over STAT_SLOTS pairs (summed when read): device-scope
+// atomics on one address from every wave of the GPU serialise at the memory side.
+constexpr uint32_t STAT_SLOTS = 1024;
+
 __device__ __forceinline__ void add_stats(unsigned long long* stats, uint32_t inter, uint32_t cand)
 {
     unsigned long long a = wave_sum<unsigned long long>(inter);
     unsigned long long b = wave_sum<unsigned long long>(cand);
-    if ((threadIdx.x & (WAVE - 1)) == 0) {
-        atomicAdd(&stats[0], a);
-        atomicAdd(&stats[1], b);
+    if ((threadIdx.x & (WAVE - 1)) == 0 && (a | b)) {
+        const uint32_t slot = (blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE) % STAT_SLOTS;
+        atomicAdd(&stats[2 * slot], a);
+        atomicAdd(&stats[2 * slot + 1], b);
     }
 }
 
@@ -522,6 +525,147 @@ __global__ __launch_bounds__(BLOCK) void k_force_rows(uint32_t n, PhysArgs P, Fo
     add_stats(a.stats, inter, cand);
 }
 
+// ------------------------------------------------------------------------ a6 + a7, per-cell lists
+
+// In-range decision only (the term is computed later from a list); the same
+// expressions, uncontracted, as in pair64 / pair32.
+__device__ __forceinline__ bool in_range64(const double4& me, const double4& c, double alpha)
+{
+#pragma clang fp contract(off)
+    const double dx = me.x - c.x, dy = me.y - c.y, dz = me.z - c.z;
+    const double d2 = dx * dx + dy * dy + dz * dz;
+    const double RA = alpha * (me.w + c.w);
+    return d2 > 0.0 && d2 < RA * RA;
+}
+
+__device__ __forceinline__ bool in_range32(const float4& me, const float4& c, float alpha)
+{
+#pragma clang fp contract(off)
+    const float dx = me.x - c.x, dy = me.y - c.y, dz = me.z - c.z;
+    const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
+    const float RA = alpha * (me.w + c.w);
+    return d2 > 0.0f && d2 < RA * RA;
+}
+
+constexpr int FC_LIST = 16;    // in-range candidates a lane holds before a flush
+constexpr int FC_UNROLL = 4;   // candidates tested per loop trip (independent loads in flight)
+
+template <int PREC, bool MULTI, typename VPT>
+struct CellView {
+    using T = typename std::conditional<PREC == 0, double4, float4>::type;
+    __device__ __forceinline__ static T load(const ForceArgs<VPT>& a, uint32_t j)
+    {
+        if constexpr (PREC == 0)
+            return make_double4(a.XS[0][j], a.XS[1][j], a.XS[2][j], a.R[j]);
+        else
+            return a.SH[j];
+    }
+    __device__ __forceinline__ static bool test(const T& me, const T& c, const PhysArgs& P)
+    {
+        if constexpr (PREC == 0)
+            return in_range64(me, c, P.alpha);
+        else
+            return in_range32(me, c, P.alpha_f);
+    }
+};
+
+// One thread per cell in voxel order, as k_force_rows, but the rare in-range pairs do
+// not make the wave diverge: each lane only tests candidates (four loads in flight per
+// trip) and appends the index of an in-range one to its LDS list; the lists are
+// evaluated together when one fills up and at the end, in candidate order, so the sum
+// of each cell is still taken in the fixed neighbour order (rows dz, dy; ascending
+// voxel order inside a row).  Lanes of one voxel read the same candidate at the same
+// time, which one cache line serves.
+template <int PREC, bool MULTI, typename VPT>
+__global__ __launch_bounds__(BLOCK) void k_force_cells(uint32_t n, PhysArgs P, ForceArgs<VPT> a)
+{
+    using View = CellView<PREC, MULTI, VPT>;
+    using CT = typename View::T;
+    using Real = typename std::conditional<PREC == 0, double, float>::type;
+    __shared__ uint32_t s_list[BLOCK / WAVE][FC_LIST][WAVE];
+
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int w = threadIdx.x / WAVE;
+    const uint32_t i = xcd_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
+    const bool valid = i < n;
+    const uint32_t ii = valid ? i : n - 1;  // n >= 1: idle lanes mirror the last cell
+    const uint32_t vox = a.vid_sorted[ii];
+    const int kx = (int)(vox % (uint32_t)P.nx);
+    const int ky = (int)((vox / (uint32_t)P.nx) % (uint32_t)P.ny);
+    const int kz = (int)(vox / ((uint32_t)P.nx * (uint32_t)P.ny));
+    const int x0 = kx > 0 ? kx - 1 : 0;
+    const int x1 = kx < P.nx - 1 ? kx + 1 : P.nx - 1;
+    const CT me = View::load(a, ii);
+    const int ti = MULTI ? a.T[ii] : 0;
+    Real acc[3] = {0, 0, 0}, cmp[3] = {0, 0, 0};
+    uint32_t cnt = 0, inter = 0, cand = 0;
+    uint32_t* list = &s_list[w][0][lane];
+
+    auto flush = [&]() {
+        inter += cnt;
+        for (uint32_t q = 0; q < (uint32_t)FC_LIST; ++q) {
+            if (!__any(q < cnt)) break;
+            if (q < cnt) {
+                const uint32_t j = list[q * WAVE];
+                const CT c = View::load(a, j);
+                if constexpr (PREC == 0) {
+                    const double cadh = MULTI ? a.cadh[ti * P.n_types + a.T[j]] : P.c_adh0;
+                    pair64(me.x, me.y, me.z, me.w, c.x, c.y, c.z, c.w, P.alpha, P.c_rep, cadh,
+                           acc[0], acc[1], acc[2]);
+                } else {
+                    const float cadh = MULTI ? a.cadh_f[ti * P.n_types + a.T[j]] : P.c_adh0_f;
+                    pair32<PREC == 2>(me.x, me.y, me.z, me.w, c, P.alpha_f, P.c_rep_f, cadh, acc, cmp);
+                }
+            }
+        }
+        cnt = 0;
+    };
+    auto append = [&](bool in, uint32_t j) {
+        if (in) {
+            list[cnt * WAVE] = j;
+            ++cnt;
+        }
+    };
+
+    for (int q = 0; q < 9; ++q) {
+        const int y = ky + (q % 3) - 1, z = kz + (q / 3) - 1;
+        if (!valid || y < 0 || y >= P.ny || z < 0 || z >= P.nz) continue;
+        const uint32_t row = (uint32_t)P.nx * ((uint32_t)y + (uint32_t)P.ny * (uint32_t)z);
+        uint32_t j = a.voxel_start[row + x0];
+        const uint32_t e = a.voxel_start[row + x1 + 1];
+        cand += e - j;
+        for (; j + FC_UNROLL <= e; j += FC_UNROLL) {
+            CT c[FC_UNROLL];
+#pragma unroll
+            for (int u = 0; u < FC_UNROLL; ++u) c[u] = View::load(a, j + u);
+            bool in[FC_UNROLL];
+#pragma unroll
+            for (int u = 0; u < FC_UNROLL; ++u) in[u] = View::test(me, c[u], P);
+#pragma unroll
+            for (int u = 0; u < FC_UNROLL; ++u) append(in[u], j + u);
+            if (__any(cnt > (uint32_t)(FC_LIST - FC_UNROLL))) flush();
+        }
+        for (; j < e; ++j) {
+            append(View::test(me, View::load(a, j), P), j);
+            if (__any(cnt > (uint32_t)(FC_LIST - FC_UNROLL))) flush();
+        }
+    }
+    flush();
+    if (valid) {
+        cand -= 1;  // the cell itself
+        const double xs[3] = {a.XS[0][i], a.XS[1][i], a.XS[2][i]};
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double v = (double)(acc[c] - cmp[c]);
+            const double vp = a.euler ? v : (double)a.VP[c][i];
+            const double xn = xs[c] + P.dt * (1.5 * v - 0.5 * vp);
+            a.X[c][i] = reflect(xn, P.lo[c], P.hi[c]);
+            a.VP[c][i] = (VPT)v;
+        }
+    }
+    add_stats(a.stats, inter, cand);
+}
+
 // ------------------------------------------------------------------------ a6 + a7, LDS-staged
 
 // Per-wave LDS: the candidates of one chunk of the 27-voxel neighbourhood (x, y, z, r),
@@ -542,27 +686,8 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// In-range decision only (the term is computed later from the list).
-__device__ __forceinline__ bool in_range64(const double4& me, const double4& c, double alpha)
-{
-#pragma clang fp contract(off)
-    const double dx = me.x - c.x, dy = me.y - c.y, dz = me.z - c.z;
-    const double d2 = dx * dx + dy * dy + dz * dz;
-    const double RA = alpha * (me.w + c.w);
-    return d2 > 0.0 && d2 < RA * RA;
-}
-
-__device__ __forceinline__ bool in_range32(const float4& me, const float4& c, float alpha)
-{
-#pragma clang fp contract(off)
-    const float dx = me.x - c.x, dy = me.y - c.y, dz = me.z - c.z;
-    const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
-    const float RA = alpha * (me.w + c.w);
-    return d2 > 0.0f && d2 < RA * RA;
-}
-
-// One wave per occupied voxel, taken from a global counter (fine-grained dynamic
-// schedule over non-empty voxels).  The wave stages its 27-voxel neighbourhood in LDS
+// One wave per occupied voxel: the waves of the grid walk the non-empty voxel list with
+// a fixed stride (empty voxels cost nothing).  The wave stages its 27-voxel neighbourhood in LDS
 // (9 rows, each a contiguous range of the voxel-ordered arrays) and splits its lanes
 // as (target, slice): target t of r = min(64, remaining) takes lanes t, t + r, ...,
 // so all 64 lanes test candidates.  A lane appends the in-range candidates of its slice
@@ -572,8 +697,7 @@ __device__ __forceinline__ bool in_range32(const float4& me, const float4& c, fl
 template <int PREC, bool MULTI, typename VPT>
 __global__ __launch_bounds__(FL_WAVES * WAVE) void k_force_lds(PhysArgs P, ForceArgs<VPT> a,
                                                                const uint32_t* __restrict__ occ,
-                                                               const uint32_t* __restrict__ n_occ,
-                                                               uint32_t* __restrict__ counter)
+                                                               const uint32_t* __restrict__ n_occ)
 {
     using CT = typename Stage<PREC>::T;
     using Real = typename std::conditional<PREC == 0, double, float>::type;
@@ -588,11 +712,10 @@ __global__ __launch_bounds__(FL_WAVES * WAVE) void k_force_lds(PhysArgs P, Force
     const uint32_t M = *n_occ;
     uint32_t inter = 0, cand = 0;
 
-    for (;;) {
-        uint32_t o = 0;
-        if (lane == 0) o = atomicAdd(counter, 1u);
-        o = __builtin_amdgcn_readfirstlane(__shfl(o, 0, WAVE));
-        if (o >= M) break;
+    // wave q of the (XCD-renumbered) grid takes occupied voxels q, q + W, q + 2W, ...
+    const uint32_t nwaves = gridDim.x * FL_WAVES;
+    const uint32_t q0 = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * FL_WAVES + w);
+    for (uint32_t o = q0; o < M; o += nwaves) {
         const uint32_t vox = __builtin_amdgcn_readfirstlane(occ[o]);
         const int kx = (int)(vox % (uint32_t)P.nx);
         const int ky = (int)((vox / (uint32_t)P.nx) % (uint32_t)P.ny);
@@ -795,7 +918,7 @@ Layout make_layout(const MechParams& p, int64_t n, uint64_t V)
     L.occ = take(V * 4);
     L.n_occ = take(16);
     L.tsum = take((size_t)blocks_for(V, SCAN_TILE) * 8);
-    L.stats = take(64);
+    L.stats = take(STAT_SLOTS * 16);
     L.cadh = take(64 * 8);
     L.cadh_f = take(64 * 4);
     L.stage = take(nn * 48);
@@ -812,7 +935,7 @@ int validate(const MechParams* p, int64_t n, int32_t dims[3])
         return fail(MECH_E_INVALID, "precision %d unknown", p->precision);
     if (p->ab2_start != MECH_AB2_ZERO_HISTORY && p->ab2_start != MECH_AB2_EULER_START)
         return fail(MECH_E_INVALID, "ab2_start %d unknown", p->ab2_start);
-    if (p->flags & ~(MECH_FLAG_NO_GRAPH | MECH_FLAG_SIMPLE_FORCE))
+    if (p->flags & ~(MECH_FLAG_NO_GRAPH | MECH_FLAG_SIMPLE_FORCE | MECH_FLAG_VOXEL_FORCE))
         return fail(MECH_E_INVALID, "unknown flags 0x%x", p->flags);
     if (p->reserved != 0) return fail(MECH_E_INVALID, "reserved field must be 0");
     if (n < 0 || n >= (int64_t(1) << 31)) return fail(MECH_E_INVALID, "n_cells %lld out of range", (long long)n);
@@ -911,8 +1034,7 @@ void enqueue_binning(MechPopulation* P)
     hipLaunchKernelGGL(k_scan_reduce, dim3(P->n_tiles), dim3(BLOCK), 0, P->stream,
                        P->at<uint32_t>(L.count), P->V, P->at<uint64_t>(L.tsum));
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(BLOCK), 0, P->stream, P->at<uint64_t>(L.tsum),
-                       P->n_tiles, P->at<uint32_t>(L.start), P->V, P->at<uint32_t>(L.n_occ),
-                       P->at<uint32_t>(L.n_occ) + 1);
+                       P->n_tiles, P->at<uint32_t>(L.start), P->V, P->at<uint32_t>(L.n_occ));
     hipLaunchKernelGGL(k_scan_down, dim3(P->n_tiles), dim3(BLOCK), 0, P->stream,
                        P->at<uint32_t>(L.count), P->V, P->at<uint64_t>(L.tsum),
                        P->at<uint32_t>(L.start), P->at<uint32_t>(L.occ));
@@ -969,16 +1091,23 @@ void enqueue_force(MechPopulation* P, int parity_after_sort, int euler)
             hipLaunchKernelGGL((k_force_rows<PREC, false, VPT>), dim3(nb), dim3(BLOCK), 0, P->stream, n, P->phys, a);
         return;
     }
-    // persistent grid of fixed size (graph-safe); waves take occupied voxels until none is left
+    if (!(P->prm.flags & MECH_FLAG_VOXEL_FORCE)) {
+        const uint32_t nb = blocks_for(n, BLOCK);
+        if (P->prm.n_types > 1)
+            hipLaunchKernelGGL((k_force_cells<PREC, true, VPT>), dim3(nb), dim3(BLOCK), 0, P->stream, n, P->phys, a);
+        else
+            hipLaunchKernelGGL((k_force_cells<PREC, false, VPT>), dim3(nb), dim3(BLOCK), 0, P->stream, n, P->phys, a);
+        return;
+    }
+    // persistent grid of fixed size (graph-safe); waves walk the occupied-voxel list
     const uint32_t* occ = P->at<uint32_t>(L.occ);
     const uint32_t* m = P->at<uint32_t>(L.n_occ);
-    uint32_t* ctr = P->at<uint32_t>(L.n_occ) + 1;
     if (P->prm.n_types > 1)
         hipLaunchKernelGGL((k_force_lds<PREC, true, VPT>), dim3(P->force_grid), dim3(FL_WAVES * WAVE), 0,
-                           P->stream, P->phys, a, occ, m, ctr);
+                           P->stream, P->phys, a, occ, m);
     else
         hipLaunchKernelGGL((k_force_lds<PREC, false, VPT>), dim3(P->force_grid), dim3(FL_WAVES * WAVE), 0,
-                           P->stream, P->phys, a, occ, m, ctr);
+                           P->stream, P->phys, a, occ, m);
 }
 
 // One full step a1..a7 from the current parity; flips nothing on the host.
@@ -1160,7 +1289,7 @@ int create_impl(const MechParams* params, int64_t n, const double* pos, const do
     H2D(L.cadh_f, cf, sizeof cf);
     if (e) return bail(fail(MECH_E_DEVICE, "host to device copy failed"));
     if (hipMemsetAsync(P->arena + L.count, 0, (size_t)P->V * 4, s) != hipSuccess ||
-        hipMemsetAsync(P->arena + L.stats, 0, 64, s) != hipSuccess ||
+        hipMemsetAsync(P->arena + L.stats, 0, STAT_SLOTS * 16, s) != hipSuccess ||
         hipMemsetAsync(P->arena + L.start, 0, ((size_t)P->V + 1) * 4, s) != hipSuccess ||
         hipMemsetAsync(P->arena + L.n_occ, 0, 16, s) != hipSuccess)
         return bail(fail(MECH_E_DEVICE, "hipMemsetAsync failed"));
@@ -1381,8 +1510,13 @@ int read_stats(MechPopulation* P, int64_t* steps, int64_t* interactions, int64_t
     HIP_TRY(hipSetDevice(P->device));
     int rc = sync_check(P);
     if (rc) return rc;
+    std::vector<unsigned long long> slots(2 * STAT_SLOTS);
+    HIP_TRY(hipMemcpy(slots.data(), P->arena + P->L.stats, slots.size() * 8, hipMemcpyDeviceToHost));
     unsigned long long st[2] = {0, 0};
-    HIP_TRY(hipMemcpy(st, P->arena + P->L.stats, sizeof st, hipMemcpyDeviceToHost));
+    for (uint32_t k = 0; k < STAT_SLOTS; ++k) {
+        st[0] += slots[2 * k];
+        st[1] += slots[2 * k + 1];
+    }
     if (steps) *steps = P->steps;
     if (interactions) *interactions = (int64_t)st[0];
     if (candidates) *candidates = (int64_t)st[1];
