@@ -63,13 +63,12 @@ enum { MECH_AB2_ZERO_HISTORY = 0, MECH_AB2_EULER_START = 1 };
 /* MechParams.flags bits */
 enum {
     MECH_FLAG_NO_GRAPH = 1,       /* launch each step's kernels directly (no HIP graph) */
-    MECH_FLAG_SIMPLE_FORCE = 2,   /* force kernel variant: one thread per cell evaluating
-                                     every candidate inline (no in-range lists)          */
-    MECH_FLAG_VOXEL_FORCE = 4     /* force kernel variant: one wave per occupied voxel with
-                                     the neighbourhood staged in LDS.  Without either
-                                     flag: one thread per cell with in-range lists.  All
-                                     variants give the same results up to summation
-                                     order and are each deterministic.                   */
+    /* Force-kernel variant (at most one; all give the same results up to summation order
+       and each is deterministic).  Without either: one thread per cell, candidates
+       prefiltered four at a time, in-range lists evaluated in batches. */
+    MECH_FLAG_SIMPLE_FORCE = 2,   /* one thread per cell, every candidate evaluated inline */
+    MECH_FLAG_VOXEL_FORCE = 4,    /* one wave per occupied voxel, neighbourhood in LDS     */
+    MECH_FORCE_KERNEL_MASK = 6
 };
 
 typedef struct MechParams {

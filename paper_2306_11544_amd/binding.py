@@ -22,6 +22,7 @@ MECH_AB2_ZERO_HISTORY, MECH_AB2_EULER_START = 0, 1
 MECH_FLAG_NO_GRAPH = 1
 MECH_FLAG_SIMPLE_FORCE = 2
 MECH_FLAG_VOXEL_FORCE = 4
+FORCE_KERNELS = {"cells": 0, "rows": MECH_FLAG_SIMPLE_FORCE, "voxel": MECH_FLAG_VOXEL_FORCE}
 MECH_ABI_VERSION = 1
 
 PRECISIONS = {"fp64": MECH_FP64, "fp32": MECH_FP32, "fp32k": MECH_FP32_KAHAN}

@@ -83,7 +83,8 @@ struct GridArgs {
 struct PhysArgs {
     double lo[3], hi[3];
     double dt, c_rep, alpha, c_adh0;
-    float c_rep_f, alpha_f, c_adh0_f, pad_;
+    double r_max;              // largest radius of the population
+    float c_rep_f, alpha_f, c_adh0_f, r_max_f;
     int32_t n_types;
     int32_t nx, ny, nz;
 };
@@ -547,40 +548,22 @@ __device__ __forceinline__ bool in_range32(const float4& me, const float4& c, fl
     return d2 > 0.0f && d2 < RA * RA;
 }
 
-constexpr int FC_LIST = 16;    // in-range candidates a lane holds before a flush
+constexpr int FC_LIST = 16;    // listed candidates a lane holds before a flush
 constexpr int FC_UNROLL = 4;   // candidates tested per loop trip (independent loads in flight)
 
-template <int PREC, bool MULTI, typename VPT>
-struct CellView {
-    using T = typename std::conditional<PREC == 0, double4, float4>::type;
-    __device__ __forceinline__ static T load(const ForceArgs<VPT>& a, uint32_t j)
-    {
-        if constexpr (PREC == 0)
-            return make_double4(a.XS[0][j], a.XS[1][j], a.XS[2][j], a.R[j]);
-        else
-            return a.SH[j];
-    }
-    __device__ __forceinline__ static bool test(const T& me, const T& c, const PhysArgs& P)
-    {
-        if constexpr (PREC == 0)
-            return in_range64(me, c, P.alpha);
-        else
-            return in_range32(me, c, P.alpha_f);
-    }
-};
-
-// One thread per cell in voxel order, as k_force_rows, but the rare in-range pairs do
-// not make the wave diverge: each lane only tests candidates (four loads in flight per
-// trip) and appends the index of an in-range one to its LDS list; the lists are
-// evaluated together when one fills up and at the end, in candidate order, so the sum
-// of each cell is still taken in the fixed neighbour order (rows dz, dy; ascending
-// voxel order inside a row).  Lanes of one voxel read the same candidate at the same
-// time, which one cache line serves.
+// One thread per cell in voxel order.  Each lane walks its 9 neighbour rows (dz, dy;
+// the three voxels of a row are adjacent in voxel order) and only prefilters the
+// candidates, four loads in flight per trip: a candidate is listed in LDS when
+//   d2 < (alpha (r_i + r_max))^2,
+// which every interacting pair satisfies (r_j <= r_max and rounding is monotonic; d2
+// is the same expression as in the exact test).  When a list fills, and at the end,
+// the lanes evaluate their listed candidates together with the exact decision and
+// pair term of pair64 / pair32, in candidate order, so each sum is still taken in the
+// fixed neighbour order and the rare interacting pairs do not make the wave diverge.
+// Lanes of one voxel read the same candidate at the same time (one cache line).
 template <int PREC, bool MULTI, typename VPT>
 __global__ __launch_bounds__(BLOCK) void k_force_cells(uint32_t n, PhysArgs P, ForceArgs<VPT> a)
 {
-    using View = CellView<PREC, MULTI, VPT>;
-    using CT = typename View::T;
     using Real = typename std::conditional<PREC == 0, double, float>::type;
     __shared__ uint32_t s_list[BLOCK / WAVE][FC_LIST][WAVE];
 
@@ -595,36 +578,61 @@ __global__ __launch_bounds__(BLOCK) void k_force_cells(uint32_t n, PhysArgs P, F
     const int kz = (int)(vox / ((uint32_t)P.nx * (uint32_t)P.ny));
     const int x0 = kx > 0 ? kx - 1 : 0;
     const int x1 = kx < P.nx - 1 ? kx + 1 : P.nx - 1;
-    const CT me = View::load(a, ii);
+    Real xi, yi, zi, ri;
+    if constexpr (PREC == 0) {
+        xi = a.XS[0][ii];
+        yi = a.XS[1][ii];
+        zi = a.XS[2][ii];
+        ri = a.R[ii];
+    } else {
+        const float4 m = a.SH[ii];
+        xi = m.x;
+        yi = m.y;
+        zi = m.z;
+        ri = m.w;
+    }
+    Real T;
+    {
+#pragma clang fp contract(off)
+        const Real reach = (PREC == 0 ? (Real)P.alpha : (Real)P.alpha_f) *
+                           (ri + (PREC == 0 ? (Real)P.r_max : (Real)P.r_max_f));
+        T = reach * reach;
+    }
     const int ti = MULTI ? a.T[ii] : 0;
     Real acc[3] = {0, 0, 0}, cmp[3] = {0, 0, 0};
-    uint32_t cnt = 0, inter = 0, cand = 0;
-    uint32_t* list = &s_list[w][0][lane];
+    uint32_t inter = 0, cand = 0;
+    uint32_t* const list0 = &s_list[w][0][lane];
+    uint32_t* const list_hi = list0 + (FC_LIST - FC_UNROLL) * WAVE;
+    uint32_t* lp = list0;
 
+    auto near = [&](Real cx, Real cy, Real cz) -> bool {
+#pragma clang fp contract(off)
+        const Real dx = xi - cx, dy = yi - cy, dz = zi - cz;
+        Real d2;
+        if constexpr (PREC == 0)
+            d2 = dx * dx + dy * dy + dz * dz;
+        else
+            d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
+        return d2 < T;
+    };
     auto flush = [&]() {
-        inter += cnt;
+        const uint32_t cnt = (uint32_t)(lp - list0) / WAVE;
         for (uint32_t q = 0; q < (uint32_t)FC_LIST; ++q) {
             if (!__any(q < cnt)) break;
             if (q < cnt) {
-                const uint32_t j = list[q * WAVE];
-                const CT c = View::load(a, j);
+                const uint32_t j = list0[q * WAVE];
                 if constexpr (PREC == 0) {
                     const double cadh = MULTI ? a.cadh[ti * P.n_types + a.T[j]] : P.c_adh0;
-                    pair64(me.x, me.y, me.z, me.w, c.x, c.y, c.z, c.w, P.alpha, P.c_rep, cadh,
-                           acc[0], acc[1], acc[2]);
+                    inter += pair64(xi, yi, zi, ri, a.XS[0][j], a.XS[1][j], a.XS[2][j], a.R[j],
+                                    P.alpha, P.c_rep, cadh, acc[0], acc[1], acc[2]);
                 } else {
                     const float cadh = MULTI ? a.cadh_f[ti * P.n_types + a.T[j]] : P.c_adh0_f;
-                    pair32<PREC == 2>(me.x, me.y, me.z, me.w, c, P.alpha_f, P.c_rep_f, cadh, acc, cmp);
+                    inter += pair32<PREC == 2>(xi, yi, zi, ri, a.SH[j], P.alpha_f, P.c_rep_f, cadh,
+                                               acc, cmp);
                 }
             }
         }
-        cnt = 0;
-    };
-    auto append = [&](bool in, uint32_t j) {
-        if (in) {
-            list[cnt * WAVE] = j;
-            ++cnt;
-        }
+        lp = list0;
     };
 
     for (int q = 0; q < 9; ++q) {
@@ -634,20 +642,55 @@ __global__ __launch_bounds__(BLOCK) void k_force_cells(uint32_t n, PhysArgs P, F
         uint32_t j = a.voxel_start[row + x0];
         const uint32_t e = a.voxel_start[row + x1 + 1];
         cand += e - j;
-        for (; j + FC_UNROLL <= e; j += FC_UNROLL) {
-            CT c[FC_UNROLL];
+        if constexpr (PREC == 0) {
+            const double* px = a.XS[0] + j;
+            const double* py = a.XS[1] + j;
+            const double* pz = a.XS[2] + j;
+            for (; j + FC_UNROLL <= e; j += FC_UNROLL, px += FC_UNROLL, py += FC_UNROLL, pz += FC_UNROLL) {
+                double cx[FC_UNROLL], cy[FC_UNROLL], cz[FC_UNROLL];
 #pragma unroll
-            for (int u = 0; u < FC_UNROLL; ++u) c[u] = View::load(a, j + u);
-            bool in[FC_UNROLL];
+                for (int u = 0; u < FC_UNROLL; ++u) {
+                    cx[u] = px[u];
+                    cy[u] = py[u];
+                    cz[u] = pz[u];
+                }
 #pragma unroll
-            for (int u = 0; u < FC_UNROLL; ++u) in[u] = View::test(me, c[u], P);
+                for (int u = 0; u < FC_UNROLL; ++u)
+                    if (near(cx[u], cy[u], cz[u])) {
+                        *lp = j + u;
+                        lp += WAVE;
+                    }
+                if (__any(lp > list_hi)) flush();
+            }
+            for (; j < e; ++j, ++px, ++py, ++pz) {
+                if (near(*px, *py, *pz)) {
+                    *lp = j;
+                    lp += WAVE;
+                }
+                if (__any(lp > list_hi)) flush();
+            }
+        } else {
+            const float4* sp = a.SH + j;
+            for (; j + FC_UNROLL <= e; j += FC_UNROLL, sp += FC_UNROLL) {
+                float4 c[FC_UNROLL];
 #pragma unroll
-            for (int u = 0; u < FC_UNROLL; ++u) append(in[u], j + u);
-            if (__any(cnt > (uint32_t)(FC_LIST - FC_UNROLL))) flush();
-        }
-        for (; j < e; ++j) {
-            append(View::test(me, View::load(a, j), P), j);
-            if (__any(cnt > (uint32_t)(FC_LIST - FC_UNROLL))) flush();
+                for (int u = 0; u < FC_UNROLL; ++u) c[u] = sp[u];
+#pragma unroll
+                for (int u = 0; u < FC_UNROLL; ++u)
+                    if (near(c[u].x, c[u].y, c[u].z)) {
+                        *lp = j + u;
+                        lp += WAVE;
+                    }
+                if (__any(lp > list_hi)) flush();
+            }
+            for (; j < e; ++j, ++sp) {
+                const float4 c = *sp;
+                if (near(c.x, c.y, c.z)) {
+                    *lp = j;
+                    lp += WAVE;
+                }
+                if (__any(lp > list_hi)) flush();
+            }
         }
     }
     flush();
@@ -935,8 +978,12 @@ int validate(const MechParams* p, int64_t n, int32_t dims[3])
         return fail(MECH_E_INVALID, "precision %d unknown", p->precision);
     if (p->ab2_start != MECH_AB2_ZERO_HISTORY && p->ab2_start != MECH_AB2_EULER_START)
         return fail(MECH_E_INVALID, "ab2_start %d unknown", p->ab2_start);
-    if (p->flags & ~(MECH_FLAG_NO_GRAPH | MECH_FLAG_SIMPLE_FORCE | MECH_FLAG_VOXEL_FORCE))
+    if (p->flags & ~(MECH_FLAG_NO_GRAPH | MECH_FORCE_KERNEL_MASK))
         return fail(MECH_E_INVALID, "unknown flags 0x%x", p->flags);
+    {
+        const int k = p->flags & MECH_FORCE_KERNEL_MASK;
+        if (k & (k - 1)) return fail(MECH_E_INVALID, "at most one force-kernel flag may be set");
+    }
     if (p->reserved != 0) return fail(MECH_E_INVALID, "reserved field must be 0");
     if (n < 0 || n >= (int64_t(1) << 31)) return fail(MECH_E_INVALID, "n_cells %lld out of range", (long long)n);
     if (!(std::isfinite(p->voxel_size) && p->voxel_size > 0))
@@ -1207,6 +1254,12 @@ int create_impl(const MechParams* params, int64_t n, const double* pos, const do
     P->phys.c_rep_f = (float)params->c_rep;
     P->phys.alpha_f = (float)params->rel_adh_distance;
     P->phys.c_adh0_f = (float)params->c_adh[0];
+    {
+        double rmax = 0.0;
+        for (int64_t k = 0; k < n; ++k) rmax = std::max(rmax, radius[k]);
+        P->phys.r_max = rmax;
+        P->phys.r_max_f = (float)rmax;
+    }
     P->phys.n_types = params->n_types;
     P->phys.nx = dims[0];
     P->phys.ny = dims[1];
