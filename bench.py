@@ -74,6 +74,72 @@ def cpu_baseline(pop, precision: str, budget_s: float = 12.0):
                       f"{precision} oracle, {t_total:.1f} s"}
 
 
+def bench_batch(args):
+    """256 independent spheroids of log-uniform size in [1k, 100k] advanced in one batch
+    (FP32, every kernel of a step launched once for all of them from a captured graph),
+    against the plain FP64 path that runs the same simulations one population at a time."""
+    import torch
+
+    import workloads
+    from paper_2306_11544_amd import binding as B
+
+    n_sims = args.sims
+    pops = workloads.batch(n_sims, steps=args.steps)
+    prec = args.precision or "fp32"
+    p = B.make_params((0, 0, 0), (1, 1, 1), c_adh=workloads.C_ADH_2,
+                      precision=B.PRECISIONS[prec], flags=B.FORCE_KERNELS[args.force])
+    cells = sum(x.n for x in pops)
+    vox = sum(B.batch_request_voxels(p, x.lo, x.hi) for x in pops)
+    log(f"batch: {n_sims} simulations, {cells} cells, {vox} voxels, {prec}")
+    torch.cuda.init()
+    with B.Batch(p, cells, vox, n_sims) as bt:
+        slots = [bt.admit_pop(x, n_steps=-1) for x in pops]
+        bt.step(args.warmup)
+        B.batch_sync(bt)
+        _, i0, _ = bt.stats()
+        t0 = time.perf_counter()
+        lat = []
+        for _ in range(args.steps):
+            ts = time.perf_counter()
+            bt.step(1)
+            B.batch_sync(bt)
+            lat.append((time.perf_counter() - ts) * 1e3)
+        wall = time.perf_counter() - t0
+        _, i1, _ = bt.stats()
+        bin_ms, force_ms = bt.profile(5)
+        del slots
+    # the plain FP64 path: the same simulations, one population at a time, a few steps each
+    sample = pops[:: max(1, n_sims // 16)]
+    pstep = 20
+    t_fp64 = 0.0
+    c_fp64 = 0
+    for x in sample:
+        with B.Population(B.params_of(x, B.MECH_FP64), x.pos, x.radius, x.type) as P:
+            P.step(2)
+            P.stats()
+            ts = time.perf_counter()
+            P.step(pstep)
+            P.stats()
+            t_fp64 += time.perf_counter() - ts
+            c_fp64 += x.n * pstep
+    out = {
+        "metric": "batched cell-steps/s (FP32, one launch per kernel for all simulations)",
+        "value": cells * args.steps / wall, "unit": "cell-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"batch{n_sims}", "simulations": n_sims, "cells": cells,
+                   "voxels": vox, "precision": prec, "force_kernel": args.force},
+        "interactions_per_s": (i1 - i0) / wall,
+        "step_latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+        "phase_ms": {"binning_reorder": bin_ms, "force_update": force_ms},
+        "fp64_per_simulation_path": {"cell_steps_per_s": c_fp64 / t_fp64,
+                                     "sample": f"{len(sample)} of the simulations, {pstep} steps each"},
+        "speedup_vs_fp64_per_simulation": (cells * args.steps / wall) / (c_fp64 / t_fp64),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,12 +149,17 @@ def main():
     ap.add_argument("--precision", default=None)
     ap.add_argument("--profile-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sims", type=int, default=256, help="batch workload: simulations")
+    ap.add_argument("--force", default="cells", help="force kernel: cells | rows | voxel")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build runs the mechanics step on a single "
               "MI355X and has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch":
+        bench_batch(args)
+        return
 
     import torch
 
@@ -98,7 +169,7 @@ def main():
     precision = args.precision or {"tumour1m": "fp32k", "sph100k": "fp64",
                                    "plain1k": "fp64"}[args.workload]
     pop = workloads.config(args.workload)
-    prm = B.params_of(pop, B.PRECISIONS[precision])
+    prm = B.params_of(pop, B.PRECISIONS[precision], flags=B.FORCE_KERNELS[args.force])
     log(f"workload {pop.name} n={pop.n} precision={precision} steps={args.steps} "
         f"warmup={args.warmup}")
 
@@ -178,7 +249,7 @@ def main():
         "step_latency_ms": {"p50": float(np.percentile(lat, 50)),
                             "p99": float(np.percentile(lat, 99))},
         "phase_ms": {"binning_reorder": bin_ms, "force_update": force_ms},
-        "roofline": {"bound": "alu", "kernel": "k_force_rows", "achieved": achieved_tflops,
+        "roofline": {"bound": "alu", "kernel": f"k_force_{args.force}", "achieved": achieved_tflops,
                      "peak": peak, "unit": "TFLOP/s", "frac": achieved_tflops / peak,
                      "traffic": None,
                      "hbm_algorithmic_GBs": force_gbs,

@@ -167,6 +167,86 @@ void* population_stream(MechPopulation* pop);
 /* Wait for the stream and free everything the population owns.  NULL is a no-op. */
 int destroy_population(MechPopulation* pop);
 
+/* ------------------------------------------------------------------------------------
+ * Batches: many independent simulations of uneven sizes advanced together, each kernel
+ * of a step launched once for all of them (one captured HIP graph per step).  Every
+ * simulation ("slot") has its own cells, domain and voxel grid; the physics in the
+ * batch's MechParams (precision, dt, c_rep, rel_adh_distance, adhesion matrix, voxel
+ * size, flags) is shared.  A simulation's results are bitwise the same alone (as a
+ * population) and inside any batch.  Slots are admitted and retired while others run
+ * (continuous batching): admission copies overlap queued steps, and retired slots'
+ * space is reclaimed by compaction at a later admission.
+ * ------------------------------------------------------------------------------------ */
+typedef struct MechBatch MechBatch;
+
+/* Device bytes of a batch arena for up to max_cells cells, max_voxels voxels (summed
+ * over the slots' grids) and max_slots slots; negative MECH_E_* on bad arguments. */
+int64_t batch_workspace_bytes(const MechParams* params, int64_t max_cells, int64_t max_voxels,
+                              int32_t max_slots);
+
+/* Voxels a simulation with this domain needs in a batch (product over the axes of
+ * ceil((hi - lo) / voxel_size), at least 1 each), or a negative MECH_E_* code. */
+int64_t batch_request_voxels(const MechParams* params, const double domain_lo[3],
+                             const double domain_hi[3]);
+
+/* Create an empty batch on the current device.  params: the shared physics; its domain
+ * fields are not used.  hip_stream as in create_population. */
+int create_batch(const MechParams* params, int64_t max_cells, int64_t max_voxels,
+                 int32_t max_slots, void* hip_stream, MechBatch** out);
+
+/* Same, with the arena carved from the caller's 256-byte aligned device buffer. */
+int create_batch_in(const MechParams* params, int64_t max_cells, int64_t max_voxels,
+                    int32_t max_slots, void* hip_stream, void* workspace,
+                    int64_t workspace_bytes, MechBatch** out);
+
+/* Admit one simulation (arrays as in create_population, domain given here).  It runs
+ * n_steps steps of the following batch_step calls and then stays frozen until read and
+ * retired; n_steps < 0 runs until retired.  *slot_out receives its slot id.
+ * MECH_E_FULL: no free slot.  MECH_E_BUDGET: its cells or voxels exceed what the arena
+ * has free once retired slots are dropped (the batch is left unchanged). */
+int batch_admit(MechBatch* batch, const double domain_lo[3], const double domain_hi[3],
+                int64_t n_cells, const double* pos, const double* radius, const int32_t* type,
+                const double* prev_velocity, int64_t n_steps, int32_t* slot_out);
+
+/* Enqueue n_steps steps of every running slot (asynchronous). */
+int batch_step(MechBatch* batch, int64_t n_steps);
+
+/* Slots whose last step has completed on the device since the previous poll (without
+ * waiting): up to `capacity` ids go to done_slots, *n_done gets how many completed. */
+int batch_poll(MechBatch* batch, int32_t* done_slots, int32_t capacity, int32_t* n_done);
+
+/* Wait for the stream and copy one slot's state out in its own id order (as
+ * read_state). */
+int batch_read(MechBatch* batch, int32_t slot, double* pos, double* vel, int64_t n_cells);
+
+/* Stop a slot and free its id; its arena space is reclaimed at a later admission. */
+int batch_retire(MechBatch* batch, int32_t slot);
+
+/* Size of a slot and the steps it still has to run (< 0: no limit). */
+int batch_slot_info(MechBatch* batch, int32_t slot, int64_t* n_cells, int64_t* steps_left);
+
+/* Cells and voxels in the arena (retired slots included), running slots, and the
+ * cells and voxels free once retired slots are dropped. */
+int batch_info(MechBatch* batch, int64_t* n_cells, int64_t* n_voxels, int32_t* n_live,
+               int64_t* free_cells, int64_t* free_voxels);
+
+/* As read_stats and profile_step, for all slots together. */
+int batch_stats(MechBatch* batch, int64_t* steps, int64_t* interactions, int64_t* candidates);
+int batch_profile(MechBatch* batch, int64_t n_steps, double* phase_ms);
+
+/* Replace the batch's MechParams.flags (force-kernel variant, graph use): the tuner's
+ * hook.  Waits for the stream; the step graph is captured again on the next step. */
+int batch_set_flags(MechBatch* batch, int32_t flags);
+
+/* Wait until every step enqueued so far has completed on the device. */
+int batch_sync(MechBatch* batch);
+
+/* hipStream_t the batch runs on. */
+void* batch_stream(MechBatch* batch);
+
+/* Wait for the stream and free everything the batch owns.  NULL is a no-op. */
+int destroy_batch(MechBatch* batch);
+
 #ifdef __cplusplus
 }
 #endif

@@ -31,7 +31,11 @@ PRECISIONS = {"fp64": MECH_FP64, "fp32": MECH_FP32, "fp32k": MECH_FP32_KAHAN}
 EXPORTS = ("mech_last_error", "mech_abi_version", "mech_device_count",
            "population_workspace_bytes", "create_population", "create_population_in",
            "step_mechanics", "read_state", "read_binning", "read_stats", "profile_step",
-           "population_info", "population_stream", "destroy_population")
+           "population_info", "population_stream", "destroy_population",
+           "batch_workspace_bytes", "batch_request_voxels", "create_batch", "create_batch_in",
+           "batch_admit", "batch_step", "batch_poll", "batch_read", "batch_retire",
+           "batch_slot_info", "batch_info", "batch_stats", "batch_profile", "batch_set_flags",
+           "batch_sync", "batch_stream", "destroy_batch")
 
 
 class MechError(RuntimeError):
@@ -83,6 +87,24 @@ def lib():
             "population_info": (C.c_int, [vp, lp, ip]),
             "population_stream": (C.c_void_p, [vp]),
             "destroy_population": (C.c_int, [vp]),
+            "batch_workspace_bytes": (C.c_int64, [P(MechParams), C.c_int64, C.c_int64, C.c_int32]),
+            "batch_request_voxels": (C.c_int64, [P(MechParams), dp, dp]),
+            "create_batch": (C.c_int, [P(MechParams), C.c_int64, C.c_int64, C.c_int32, vp, P(vp)]),
+            "create_batch_in": (C.c_int, [P(MechParams), C.c_int64, C.c_int64, C.c_int32, vp, vp,
+                                          C.c_int64, P(vp)]),
+            "batch_admit": (C.c_int, [vp, dp, dp, C.c_int64, dp, dp, ip, dp, C.c_int64, ip]),
+            "batch_step": (C.c_int, [vp, C.c_int64]),
+            "batch_poll": (C.c_int, [vp, ip, C.c_int32, ip]),
+            "batch_read": (C.c_int, [vp, C.c_int32, dp, dp, C.c_int64]),
+            "batch_retire": (C.c_int, [vp, C.c_int32]),
+            "batch_slot_info": (C.c_int, [vp, C.c_int32, lp, lp]),
+            "batch_info": (C.c_int, [vp, lp, lp, ip, lp, lp]),
+            "batch_stats": (C.c_int, [vp, lp, lp, lp]),
+            "batch_profile": (C.c_int, [vp, C.c_int64, dp]),
+            "batch_set_flags": (C.c_int, [vp, C.c_int32]),
+            "batch_sync": (C.c_int, [vp]),
+            "batch_stream": (C.c_void_p, [vp]),
+            "destroy_batch": (C.c_int, [vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -269,6 +291,136 @@ class Population:
     def close(self):
         if self.h:
             destroy_population(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------- batches
+
+def batch_workspace_bytes(params: MechParams, max_cells: int, max_voxels: int,
+                          max_slots: int) -> int:
+    r = int(lib().batch_workspace_bytes(C.byref(params), int(max_cells), int(max_voxels),
+                                        int(max_slots)))
+    if r < 0:
+        raise MechError(r, mech_last_error())
+    return r
+
+
+def batch_request_voxels(params: MechParams, lo, hi) -> int:
+    lo = np.ascontiguousarray(lo, dtype=np.float64)
+    hi = np.ascontiguousarray(hi, dtype=np.float64)
+    r = int(lib().batch_request_voxels(C.byref(params), _d(lo), _d(hi)))
+    if r < 0:
+        raise MechError(r, mech_last_error())
+    return r
+
+
+def batch_sync(batch) -> None:
+    """Wait until every step enqueued on the batch has completed."""
+    _ck(lib().batch_sync(batch.h))
+
+
+class Batch:
+    """Many independent simulations advanced together (see include/mech.h)."""
+
+    def __init__(self, params: MechParams, max_cells: int, max_voxels: int, max_slots: int,
+                 stream=None, workspace=None):
+        self.params = params
+        self._ws = workspace
+        h = C.c_void_p()
+        if workspace is not None:
+            _ck(lib().create_batch_in(C.byref(params), int(max_cells), int(max_voxels),
+                                      int(max_slots), stream, C.c_void_p(int(workspace.data_ptr())),
+                                      int(workspace.numel() * workspace.element_size()),
+                                      C.byref(h)))
+        else:
+            _ck(lib().create_batch(C.byref(params), int(max_cells), int(max_voxels),
+                                   int(max_slots), stream, C.byref(h)))
+        self.h = h
+        self.max_slots = int(max_slots)
+        self.sizes = {}
+
+    def admit(self, lo, hi, pos, radius, type=None, prev_velocity=None, n_steps=-1) -> int:
+        pos, radius, t, vp = _cells(pos, radius, type, prev_velocity)
+        lo = np.ascontiguousarray(lo, dtype=np.float64)
+        hi = np.ascontiguousarray(hi, dtype=np.float64)
+        slot = C.c_int32(-1)
+        _ck(lib().batch_admit(self.h, _d(lo), _d(hi), pos.shape[0], _d(pos), _d(radius),
+                              None if t is None else t.ctypes.data_as(C.POINTER(C.c_int32)),
+                              _d(vp), int(n_steps), C.byref(slot)))
+        self.sizes[slot.value] = pos.shape[0]
+        return slot.value
+
+    def admit_pop(self, pop, n_steps=None, prev_velocity=None) -> int:
+        return self.admit(pop.lo, pop.hi, pop.pos, pop.radius, pop.type, prev_velocity,
+                          pop.steps if n_steps is None else n_steps)
+
+    def step(self, n_steps=1):
+        _ck(lib().batch_step(self.h, int(n_steps)))
+        return self
+
+    def poll(self):
+        out = np.zeros(self.max_slots, np.int32)
+        n = C.c_int32(0)
+        _ck(lib().batch_poll(self.h, out.ctypes.data_as(C.POINTER(C.c_int32)), self.max_slots,
+                             C.byref(n)))
+        return [int(x) for x in out[:n.value]]
+
+    def read(self, slot, with_velocity=True):
+        n = self.sizes[slot]
+        pos = np.empty((n, 3), np.float64)
+        vel = np.empty((n, 3), np.float64) if with_velocity else None
+        _ck(lib().batch_read(self.h, int(slot), _d(pos), _d(vel), n))
+        return pos, vel
+
+    def retire(self, slot):
+        _ck(lib().batch_retire(self.h, int(slot)))
+        self.sizes.pop(slot, None)
+
+    def slot_info(self, slot):
+        n, s = C.c_int64(), C.c_int64()
+        _ck(lib().batch_slot_info(self.h, int(slot), C.byref(n), C.byref(s)))
+        return int(n.value), int(s.value)
+
+    def info(self):
+        a, b, fc, fv = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()
+        nl = C.c_int32()
+        _ck(lib().batch_info(self.h, C.byref(a), C.byref(b), C.byref(nl), C.byref(fc), C.byref(fv)))
+        return dict(n_cells=a.value, n_voxels=b.value, n_live=nl.value, free_cells=fc.value,
+                    free_voxels=fv.value)
+
+    def stats(self):
+        s, i, c = C.c_int64(), C.c_int64(), C.c_int64()
+        _ck(lib().batch_stats(self.h, C.byref(s), C.byref(i), C.byref(c)))
+        return int(s.value), int(i.value), int(c.value)
+
+    def profile(self, n_steps=1):
+        ms = np.zeros(2, np.float64)
+        _ck(lib().batch_profile(self.h, int(n_steps), _d(ms)))
+        return float(ms[0]), float(ms[1])
+
+    def set_flags(self, flags: int):
+        _ck(lib().batch_set_flags(self.h, int(flags)))
+        self.params.flags = int(flags)
+
+    @property
+    def stream(self) -> int:
+        return int(lib().batch_stream(self.h) or 0)
+
+    def close(self):
+        if getattr(self, "h", None):
+            _ck(lib().destroy_batch(self.h))
             self.h = None
 
     def __enter__(self):

@@ -1,6 +1,6 @@
 // mech.hip -- gfx950 kernels and C-ABI runtime of the agent-mechanics step (libmech.so).
 //
-// One step, all on the device, on the population's stream:
+// One step, all on the device, on the batch's stream:
 //   k_bin          a1+a2  voxel of every cell (FP64 key) and an integer-atomic histogram
 //   k_scan_reduce  a3     per-tile sums of (count, occupied) packed in 64 bits
 //   k_scan_top            exclusive scan of the tile sums (one workgroup)
@@ -9,18 +9,31 @@
 //   k_rank_gather  a4+a5  rank inside the segment by ascending id -> final slot; gather of
 //                         the cell state into voxel order (+ the float shadow)
 //   k_force_*      a6+a7  27-voxel neighbour forces -> velocity, Adams-Bashforth, walls
+//   k_step_end            per-simulation step counters
 // The paper measures the mechanics "update velocity" loop as the region that degrades
 // when cells sit in memory in creation order rather than next to their neighbours in
 // space (Section 5.4); here every step re-sorts cells by voxel, so the force kernel
 // always reads neighbours that are contiguous in memory, and it visits only occupied
 // voxels' cells (Section 5.4: skip empty voxels).
 //
-// State layout (structure of arrays, one entry per cell):
+// Batches.  Every kernel serves a batch of independent simulations ("slots"): slot k
+// owns the cell range [cell_off, cell_off + n_cells) and the voxel range
+// [voxel_off, voxel_off + nx*ny*nz) of one arena, and its own domain and grid
+// (SlotDesc).  Global voxel ids are voxel_off + the slot's own voxel id and global cell
+// ids are cell_off + the slot's own cell id, so one global counting sort keeps every
+// slot's cells inside its range and orders them exactly as the slot alone would be
+// ordered: a simulation gives bitwise the same result alone and inside a batch.  The
+// live sizes sit in a device header that the kernels read, so the captured step graph
+// stays valid while slots are admitted and retired.  A single population is a batch of
+// one slot.
+//
+// State layout (structure of arrays, one entry per cell, capacity-sized):
 //   X[3]    f64  positions in the order of the last sort (integration output, binning input)
 //   XS[3]   f64  positions gathered into this step's voxel order (force input)
 //   R[2]    f64  radius, T[2] i32 type, ID[2] u32 cell id, VP[2][3] v_prev (f64 or f32):
 //                double-buffered; parity p holds them in the order of X
 //   SH      float4 (x, y, z, r) in voxel order, FP32 variants only
+//   slot_of u32  slot of the cell at each index (constant between repacks)
 // Binning scratch: vid_cur, off, tmp_key, tmp_src, vid_sorted (u32 per cell);
 // count, voxel_start, occ (u32 per voxel); tile sums (u64 per 2048 voxels).
 
@@ -70,45 +83,58 @@ constexpr int WAVE = 64;
 constexpr int SCAN_PER_THREAD = 8;
 constexpr int SCAN_TILE = BLOCK * SCAN_PER_THREAD;
 constexpr uint32_t N_XCD = 8;              // MI355X: 8 accelerator complex dies
+constexpr uint32_t STAT_SLOTS = 1024;      // spread of the running counters
+
+// device header words
+constexpr int H_CELLS = 0, H_VOXELS = 1, H_OCC = 2;
 
 // ------------------------------------------------------------------------ kernel args
 
-struct GridArgs {
-    double lo[3];
-    double inv_h;
-    int32_t n[3];
-    uint32_t V;
+// One simulation of a batch (device table, indexed by slot id).
+struct SlotDesc {
+    double lo[3], hi[3];       // domain (reflecting walls), um
+    double inv_h;              // 1 / voxel edge
+    double r_max;              // largest radius of the slot's cells
+    float r_max_f;
+    int32_t nx, ny, nz;        // voxels per axis
+    uint32_t voxel_off;        // first global voxel of the slot
+    uint32_t cell_off;         // first cell index of the slot
+    uint32_t prev_cell_off;    // cell_off before a repack (repack only)
+    uint32_t n_cells;          // 0 marks a retired slot during a repack
+    int32_t steps_left;        // > 0 steps to run, < 0 no limit, 0 frozen
+    int32_t euler;             // the next step takes v_prev = v
+    int32_t pad_[2];
 };
+static_assert(sizeof(SlotDesc) % 16 == 0, "SlotDesc alignment");
 
+// Physics shared by the slots of a batch.
 struct PhysArgs {
-    double lo[3], hi[3];
     double dt, c_rep, alpha, c_adh0;
-    double r_max;              // largest radius of the population
-    float c_rep_f, alpha_f, c_adh0_f, r_max_f;
-    int32_t n_types;
-    int32_t nx, ny, nz;
+    float c_rep_f, alpha_f, c_adh0_f, pad_;
+    int32_t n_types, pad2_;
 };
 
-// Workgroups are dealt to the 8 XCDs round robin; renumber them so that each XCD gets a
-// contiguous run of the voxel-ordered cells and its own L2 keeps the shared neighbours.
+// Workgroups are dealt to the 8 XCDs round robin; renumber the first nb of them so that
+// each XCD gets a contiguous run of the voxel-ordered cells and its own L2 keeps the
+// shared neighbours.
 __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb)
 {
     uint32_t xcd = b % N_XCD, k = b / N_XCD, q = nb / N_XCD, r = nb % N_XCD;
     return xcd < r ? xcd * (q + 1) + k : r * (q + 1) + (xcd - r) * q + k;
 }
 
-// a1: voxel of a position.  (x - lo) * (1/h) is a subtraction then a product, so no
-// fused form exists and the result is the IEEE value of the written expression.
-__device__ __forceinline__ uint32_t voxel_key(double x, double y, double z, const GridArgs& g)
+// a1: voxel of a position in its slot's grid.  (x - lo) * (1/h) is a subtraction then a
+// product, so no fused form exists and the result is the IEEE value of the expression.
+__device__ __forceinline__ uint32_t voxel_key(double x, double y, double z, const SlotDesc& d)
 {
-    double f0 = floor((x - g.lo[0]) * g.inv_h);
-    double f1 = floor((y - g.lo[1]) * g.inv_h);
-    double f2 = floor((z - g.lo[2]) * g.inv_h);
-    f0 = fmin(fmax(f0, 0.0), (double)(g.n[0] - 1));
-    f1 = fmin(fmax(f1, 0.0), (double)(g.n[1] - 1));
-    f2 = fmin(fmax(f2, 0.0), (double)(g.n[2] - 1));
+    double f0 = floor((x - d.lo[0]) * d.inv_h);
+    double f1 = floor((y - d.lo[1]) * d.inv_h);
+    double f2 = floor((z - d.lo[2]) * d.inv_h);
+    f0 = fmin(fmax(f0, 0.0), (double)(d.nx - 1));
+    f1 = fmin(fmax(f1, 0.0), (double)(d.ny - 1));
+    f2 = fmin(fmax(f2, 0.0), (double)(d.nz - 1));
     uint32_t k0 = (uint32_t)f0, k1 = (uint32_t)f1, k2 = (uint32_t)f2;
-    return k0 + (uint32_t)g.n[0] * (k1 + (uint32_t)g.n[1] * k2);
+    return k0 + (uint32_t)d.nx * (k1 + (uint32_t)d.ny * k2);
 }
 
 // ------------------------------------------------------------------------ wave / block helpers
@@ -148,20 +174,33 @@ __device__ __forceinline__ uint64_t block_excl_scan(uint64_t x, uint64_t* sh, ui
     return off + inc - x;
 }
 
+// Orders this wave's LDS accesses: writes by one lane are seen by the others after it.
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // ------------------------------------------------------------------------ a1 + a2
 
 __global__ __launch_bounds__(BLOCK) void k_bin(const double* __restrict__ px,
                                                const double* __restrict__ py,
-                                               const double* __restrict__ pz, uint32_t n,
-                                               GridArgs g, uint32_t* __restrict__ count,
+                                               const double* __restrict__ pz,
+                                               const uint32_t* __restrict__ slot_of,
+                                               const SlotDesc* __restrict__ slots,
+                                               const uint32_t* __restrict__ hdr,
+                                               uint32_t* __restrict__ count,
                                                uint32_t* __restrict__ vid,
                                                uint32_t* __restrict__ off)
 {
-    uint32_t s = blockIdx.x * BLOCK + threadIdx.x;
-    if (s >= n) return;
-    uint32_t v = voxel_key(px[s], py[s], pz[s], g);
-    off[s] = atomicAdd(&count[v], 1u);
-    vid[s] = v;
+    const uint32_t n = hdr[H_CELLS];
+    for (uint32_t s = blockIdx.x * BLOCK + threadIdx.x; s < n; s += gridDim.x * BLOCK) {
+        const SlotDesc& d = slots[slot_of[s]];
+        const uint32_t v = d.voxel_off + voxel_key(px[s], py[s], pz[s], d);
+        off[s] = atomicAdd(&count[v], 1u);
+        vid[s] = v;
+    }
 }
 
 // ------------------------------------------------------------------------ a3
@@ -173,31 +212,39 @@ __device__ __forceinline__ uint64_t pack_count(uint32_t c)
 }
 
 __global__ __launch_bounds__(BLOCK) void k_scan_reduce(const uint32_t* __restrict__ count,
-                                                       uint32_t V, uint64_t* __restrict__ tsum)
+                                                       const uint32_t* __restrict__ hdr,
+                                                       uint64_t* __restrict__ tsum)
 {
     __shared__ uint64_t sh[BLOCK / WAVE];
-    const uint32_t base = blockIdx.x * SCAN_TILE;
-    uint64_t acc = 0;
+    const uint32_t V = hdr[H_VOXELS];
+    const uint32_t nt = (V + SCAN_TILE - 1) / SCAN_TILE;
+    for (uint32_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
+        const uint32_t base = tile * SCAN_TILE;
+        uint64_t acc = 0;
 #pragma unroll
-    for (int k = 0; k < SCAN_PER_THREAD; ++k) {
-        uint32_t v = base + k * BLOCK + threadIdx.x;
-        if (v < V) acc += pack_count(count[v]);
-    }
-    acc = wave_sum(acc);
-    if ((threadIdx.x & (WAVE - 1)) == 0) sh[threadIdx.x / WAVE] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint64_t t = 0;
-        for (int i = 0; i < BLOCK / WAVE; ++i) t += sh[i];
-        tsum[blockIdx.x] = t;
+        for (int k = 0; k < SCAN_PER_THREAD; ++k) {
+            uint32_t v = base + k * BLOCK + threadIdx.x;
+            if (v < V) acc += pack_count(count[v]);
+        }
+        acc = wave_sum(acc);
+        if ((threadIdx.x & (WAVE - 1)) == 0) sh[threadIdx.x / WAVE] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint64_t t = 0;
+            for (int i = 0; i < BLOCK / WAVE; ++i) t += sh[i];
+            tsum[tile] = t;
+        }
+        __syncthreads();
     }
 }
 
-__global__ __launch_bounds__(BLOCK) void k_scan_top(uint64_t* __restrict__ tsum, uint32_t nt,
+__global__ __launch_bounds__(BLOCK) void k_scan_top(uint64_t* __restrict__ tsum,
                                                     uint32_t* __restrict__ voxel_start,
-                                                    uint32_t V, uint32_t* __restrict__ n_occ)
+                                                    uint32_t* __restrict__ hdr)
 {
     __shared__ uint64_t sh[BLOCK / WAVE];
+    const uint32_t V = hdr[H_VOXELS];
+    const uint32_t nt = (V + SCAN_TILE - 1) / SCAN_TILE;
     uint64_t carry = 0;
     for (uint32_t base = 0; base < nt; base += BLOCK) {
         uint32_t i = base + threadIdx.x;
@@ -209,64 +256,72 @@ __global__ __launch_bounds__(BLOCK) void k_scan_top(uint64_t* __restrict__ tsum,
     }
     if (threadIdx.x == 0) {
         voxel_start[V] = (uint32_t)carry;
-        *n_occ = (uint32_t)(carry >> 32);
+        hdr[H_OCC] = (uint32_t)(carry >> 32);
     }
 }
 
-__global__ __launch_bounds__(BLOCK) void k_scan_down(uint32_t* __restrict__ count, uint32_t V,
+__global__ __launch_bounds__(BLOCK) void k_scan_down(uint32_t* __restrict__ count,
+                                                     const uint32_t* __restrict__ hdr,
                                                      const uint64_t* __restrict__ toff,
                                                      uint32_t* __restrict__ voxel_start,
                                                      uint32_t* __restrict__ occ)
 {
     __shared__ uint32_t tile[SCAN_TILE];
     __shared__ uint64_t sh[BLOCK / WAVE];
-    const uint32_t base = blockIdx.x * SCAN_TILE;
+    const uint32_t V = hdr[H_VOXELS];
+    const uint32_t nt = (V + SCAN_TILE - 1) / SCAN_TILE;
+    for (uint32_t ti = blockIdx.x; ti < nt; ti += gridDim.x) {
+        const uint32_t base = ti * SCAN_TILE;
 #pragma unroll
-    for (int k = 0; k < SCAN_PER_THREAD; ++k) {
-        uint32_t v = base + k * BLOCK + threadIdx.x;
-        tile[k * BLOCK + threadIdx.x] = v < V ? count[v] : 0u;
-    }
-    __syncthreads();
-    uint64_t loc[SCAN_PER_THREAD];
-    uint64_t sum = 0;
-#pragma unroll
-    for (int k = 0; k < SCAN_PER_THREAD; ++k) {
-        loc[k] = sum;
-        sum += pack_count(tile[threadIdx.x * SCAN_PER_THREAD + k]);
-    }
-    uint64_t tot;
-    uint64_t off = toff[blockIdx.x] + block_excl_scan(sum, sh, &tot);
-#pragma unroll
-    for (int k = 0; k < SCAN_PER_THREAD; ++k) {
-        uint32_t v = base + threadIdx.x * SCAN_PER_THREAD + k;
-        if (v < V) {
-            uint64_t e = off + loc[k];
-            voxel_start[v] = (uint32_t)e;
-            if (tile[threadIdx.x * SCAN_PER_THREAD + k]) occ[(uint32_t)(e >> 32)] = v;
+        for (int k = 0; k < SCAN_PER_THREAD; ++k) {
+            uint32_t v = base + k * BLOCK + threadIdx.x;
+            tile[k * BLOCK + threadIdx.x] = v < V ? count[v] : 0u;
         }
-    }
-    // the histogram of the next step starts from zero
+        __syncthreads();
+        uint64_t loc[SCAN_PER_THREAD];
+        uint64_t sum = 0;
 #pragma unroll
-    for (int k = 0; k < SCAN_PER_THREAD; ++k) {
-        uint32_t v = base + k * BLOCK + threadIdx.x;
-        if (v < V) count[v] = 0u;
+        for (int k = 0; k < SCAN_PER_THREAD; ++k) {
+            loc[k] = sum;
+            sum += pack_count(tile[threadIdx.x * SCAN_PER_THREAD + k]);
+        }
+        uint64_t tot;
+        uint64_t off = toff[ti] + block_excl_scan(sum, sh, &tot);
+#pragma unroll
+        for (int k = 0; k < SCAN_PER_THREAD; ++k) {
+            uint32_t v = base + threadIdx.x * SCAN_PER_THREAD + k;
+            if (v < V) {
+                uint64_t e = off + loc[k];
+                voxel_start[v] = (uint32_t)e;
+                if (tile[threadIdx.x * SCAN_PER_THREAD + k]) occ[(uint32_t)(e >> 32)] = v;
+            }
+        }
+        // the histogram of the next step starts from zero
+#pragma unroll
+        for (int k = 0; k < SCAN_PER_THREAD; ++k) {
+            uint32_t v = base + k * BLOCK + threadIdx.x;
+            if (v < V) count[v] = 0u;
+        }
+        __syncthreads();
     }
 }
 
 // ------------------------------------------------------------------------ a4 + a5
 
-__global__ __launch_bounds__(BLOCK) void k_scatter(uint32_t n, const uint32_t* __restrict__ vid,
+__global__ __launch_bounds__(BLOCK) void k_scatter(const uint32_t* __restrict__ hdr,
+                                                   const uint32_t* __restrict__ vid,
                                                    const uint32_t* __restrict__ off,
                                                    const uint32_t* __restrict__ voxel_start,
                                                    const uint32_t* __restrict__ id_cur,
                                                    uint32_t* __restrict__ tmp_key,
                                                    uint32_t* __restrict__ tmp_src)
 {
-    uint32_t s = blockIdx.x * BLOCK + threadIdx.x;
-    if (s >= n) return;
-    uint32_t p = voxel_start[vid[s]] + off[s];
-    tmp_key[p] = id_cur[s];
-    tmp_src[p] = s;
+    const uint32_t n = hdr[H_CELLS];
+    for (uint32_t s = blockIdx.x * BLOCK + threadIdx.x; s < n; s += gridDim.x * BLOCK) {
+        uint32_t p = voxel_start[vid[s]] + off[s];
+        tmp_key[p] = id_cur[s];
+        tmp_src[p] = s;
+    }
 }
 
 template <typename VPT>
@@ -291,29 +346,30 @@ struct GatherArgs {
 // Segments are short (tens of cells), so each cell counts the smaller ids of its own
 // segment directly; the cost is below that of the force loop over the same cells.
 template <typename VPT>
-__global__ __launch_bounds__(BLOCK) void k_rank_gather(uint32_t n, GatherArgs<VPT> a)
+__global__ __launch_bounds__(BLOCK) void k_rank_gather(const uint32_t* __restrict__ hdr, GatherArgs<VPT> a)
 {
-    uint32_t p = blockIdx.x * BLOCK + threadIdx.x;
-    if (p >= n) return;
-    const uint32_t s = a.tmp_src[p];
-    const uint32_t key = a.tmp_key[p];
-    const uint32_t v = a.vid_cur[s];
-    const uint32_t b = a.voxel_start[v], e = a.voxel_start[v + 1];
-    uint32_t rank = 0;
-    for (uint32_t q = b; q < e; ++q) rank += a.tmp_key[q] < key;
-    const uint32_t d = b + rank;
-    double x = a.X[0][s], y = a.X[1][s], z = a.X[2][s];
-    double r = a.R_cur[s];
-    a.XS[0][d] = x;
-    a.XS[1][d] = y;
-    a.XS[2][d] = z;
-    a.R_new[d] = r;
-    a.T_new[d] = a.T_cur[s];
-    a.ID_new[d] = key;
+    const uint32_t n = hdr[H_CELLS];
+    for (uint32_t p = blockIdx.x * BLOCK + threadIdx.x; p < n; p += gridDim.x * BLOCK) {
+        const uint32_t s = a.tmp_src[p];
+        const uint32_t key = a.tmp_key[p];
+        const uint32_t v = a.vid_cur[s];
+        const uint32_t b = a.voxel_start[v], e = a.voxel_start[v + 1];
+        uint32_t rank = 0;
+        for (uint32_t q = b; q < e; ++q) rank += a.tmp_key[q] < key;
+        const uint32_t d = b + rank;
+        double x = a.X[0][s], y = a.X[1][s], z = a.X[2][s];
+        double r = a.R_cur[s];
+        a.XS[0][d] = x;
+        a.XS[1][d] = y;
+        a.XS[2][d] = z;
+        a.R_new[d] = r;
+        a.T_new[d] = a.T_cur[s];
+        a.ID_new[d] = key;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) a.VP_new[c][d] = a.VP_cur[c][s];
-    a.vid_sorted[d] = v;
-    if (a.SH) a.SH[d] = make_float4((float)x, (float)y, (float)z, (float)r);
+        for (int c = 0; c < 3; ++c) a.VP_new[c][d] = a.VP_cur[c][s];
+        a.vid_sorted[d] = v;
+        if (a.SH) a.SH[d] = make_float4((float)x, (float)y, (float)z, (float)r);
+    }
 }
 
 __global__ __launch_bounds__(BLOCK) void k_copy_positions(uint32_t n, const double* __restrict__ a0,
@@ -330,7 +386,7 @@ __global__ __launch_bounds__(BLOCK) void k_copy_positions(uint32_t n, const doub
     b2[s] = a2[s];
 }
 
-// ------------------------------------------------------------------------ a6 + a7
+// ------------------------------------------------------------------------ a6 + a7 (shared)
 
 __device__ __forceinline__ double reflect(double x, double lo, double hi)
 {
@@ -347,13 +403,39 @@ struct ForceArgs {
     const float4* SH;
     const uint32_t* vid_sorted;
     const uint32_t* voxel_start;
+    const uint32_t* slot_of;
+    const SlotDesc* slots;
+    const uint32_t* hdr;
     const double* cadh;        // n_types^2 (FP64)
     const float* cadh_f;       // n_types^2 (FP32)
     VPT* VP[3];                // read v_prev, write v (in place, own element)
     double* X[3];              // new positions
-    unsigned long long* stats; // [0] interactions, [1] candidates
-    int euler;
+    unsigned long long* stats; // STAT_SLOTS pairs (interactions, candidates)
 };
+
+// a7 for one cell: two-step Adams-Bashforth from the gathered position, reflecting
+// walls of its slot, history <- v.
+template <typename VPT>
+__device__ __forceinline__ void integrate(const ForceArgs<VPT>& a, const PhysArgs& P, const SlotDesc& d,
+                                          uint32_t i, const double v[3])
+{
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double vp = d.euler ? v[c] : (double)a.VP[c][i];
+        const double xn = a.XS[c][i] + P.dt * (1.5 * v[c] - 0.5 * vp);
+        a.X[c][i] = reflect(xn, d.lo[c], d.hi[c]);
+        a.VP[c][i] = (VPT)v[c];
+    }
+}
+
+// A frozen slot (its steps are done) keeps its state: the gathered position is copied
+// back and the gathered history is left as it is.
+template <typename VPT>
+__device__ __forceinline__ void hold(const ForceArgs<VPT>& a, uint32_t i)
+{
+#pragma unroll
+    for (int c = 0; c < 3; ++c) a.X[c][i] = a.XS[c][i];
+}
 
 // FP64 pair term.  d2 and the in-range test are evaluated without contraction so the
 // decision is the exact IEEE result of d2 = dx*dx + dy*dy + dz*dz < (alpha (ri+rj))^2.
@@ -431,105 +513,7 @@ __device__ __forceinline__ bool pair32(float xi, float yi, float zi, float ri, f
     return true;
 }
 
-// Running counters are spread over STAT_SLOTS pairs (summed when read): device-scope
-// atomics on one address from every wave of the GPU serialise at the memory side.
-constexpr uint32_t STAT_SLOTS = 1024;
-
-__device__ __forceinline__ void add_stats(unsigned long long* stats, uint32_t inter, uint32_t cand)
-{
-    unsigned long long a = wave_sum<unsigned long long>(inter);
-    unsigned long long b = wave_sum<unsigned long long>(cand);
-    if ((threadIdx.x & (WAVE - 1)) == 0 && (a | b)) {
-        const uint32_t slot = (blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE) % STAT_SLOTS;
-        atomicAdd(&stats[2 * slot], a);
-        atomicAdd(&stats[2 * slot + 1], b);
-    }
-}
-
-// One thread per cell in voxel order.  The 27 neighbour voxels are visited as 9 rows
-// (dz, dy); the three voxels of a row (dx = -1, 0, 1) are adjacent in voxel order, so a
-// row is one contiguous range of the sorted arrays, read in the oracle's order.
-// PREC: 0 FP64, 1 FP32, 2 FP32 + Kahan.  MULTI: more than one cell type.
-template <int PREC, bool MULTI, typename VPT>
-__global__ __launch_bounds__(BLOCK) void k_force_rows(uint32_t n, PhysArgs P, ForceArgs<VPT> a)
-{
-    const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
-    const uint32_t i = blk * BLOCK + threadIdx.x;
-    uint32_t inter = 0, cand = 0;
-    if (i < n) {
-        const uint32_t vox = a.vid_sorted[i];
-        const int kx = (int)(vox % (uint32_t)P.nx);
-        const int ky = (int)((vox / (uint32_t)P.nx) % (uint32_t)P.ny);
-        const int kz = (int)(vox / ((uint32_t)P.nx * (uint32_t)P.ny));
-        const int x0 = kx > 0 ? kx - 1 : 0;
-        const int x1 = kx < P.nx - 1 ? kx + 1 : P.nx - 1;
-        const int ti = MULTI ? a.T[i] : 0;
-        const double xi = a.XS[0][i], yi = a.XS[1][i], zi = a.XS[2][i];
-        double vx, vy, vz;
-        if (PREC == 0) {
-            const double ri = a.R[i];
-            double ax = 0.0, ay = 0.0, az = 0.0;
-            for (int dz = -1; dz <= 1; ++dz) {
-                const int z = kz + dz;
-                if (z < 0 || z >= P.nz) continue;
-                for (int dy = -1; dy <= 1; ++dy) {
-                    const int y = ky + dy;
-                    if (y < 0 || y >= P.ny) continue;
-                    const uint32_t row = (uint32_t)P.nx * ((uint32_t)y + (uint32_t)P.ny * (uint32_t)z);
-                    const uint32_t b = a.voxel_start[row + x0], e = a.voxel_start[row + x1 + 1];
-                    cand += e - b;
-                    for (uint32_t j = b; j < e; ++j) {
-                        const double c = MULTI ? a.cadh[ti * P.n_types + a.T[j]] : P.c_adh0;
-                        inter += pair64(xi, yi, zi, ri, a.XS[0][j], a.XS[1][j], a.XS[2][j],
-                                        a.R[j], P.alpha, P.c_rep, c, ax, ay, az);
-                    }
-                }
-            }
-            vx = ax;
-            vy = ay;
-            vz = az;
-        } else {
-            const float4 me = a.SH[i];
-            float acc[3] = {0.f, 0.f, 0.f}, cmp[3] = {0.f, 0.f, 0.f};
-            for (int dz = -1; dz <= 1; ++dz) {
-                const int z = kz + dz;
-                if (z < 0 || z >= P.nz) continue;
-                for (int dy = -1; dy <= 1; ++dy) {
-                    const int y = ky + dy;
-                    if (y < 0 || y >= P.ny) continue;
-                    const uint32_t row = (uint32_t)P.nx * ((uint32_t)y + (uint32_t)P.ny * (uint32_t)z);
-                    const uint32_t b = a.voxel_start[row + x0], e = a.voxel_start[row + x1 + 1];
-                    cand += e - b;
-                    for (uint32_t j = b; j < e; ++j) {
-                        const float c = MULTI ? a.cadh_f[ti * P.n_types + a.T[j]] : P.c_adh0_f;
-                        inter += pair32<PREC == 2>(me.x, me.y, me.z, me.w, a.SH[j], P.alpha_f,
-                                                   P.c_rep_f, c, acc, cmp);
-                    }
-                }
-            }
-            vx = acc[0];
-            vy = acc[1];
-            vz = acc[2];
-        }
-        cand -= 1;  // the cell itself
-        // a7: two-step Adams-Bashforth, reflecting walls, history
-        const double v[3] = {vx, vy, vz};
-        const double x[3] = {xi, yi, zi};
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const double vp = a.euler ? v[c] : (double)a.VP[c][i];
-            const double xn = x[c] + P.dt * (1.5 * v[c] - 0.5 * vp);
-            a.X[c][i] = reflect(xn, P.lo[c], P.hi[c]);
-            a.VP[c][i] = (VPT)v[c];
-        }
-    }
-    add_stats(a.stats, inter, cand);
-}
-
-// ------------------------------------------------------------------------ a6 + a7, per-cell lists
-
-// In-range decision only (the term is computed later from a list); the same
-// expressions, uncontracted, as in pair64 / pair32.
+// In-range decision only, with the same expressions, uncontracted, as pair64 / pair32.
 __device__ __forceinline__ bool in_range64(const double4& me, const double4& c, double alpha)
 {
 #pragma clang fp contract(off)
@@ -548,12 +532,130 @@ __device__ __forceinline__ bool in_range32(const float4& me, const float4& c, fl
     return d2 > 0.0f && d2 < RA * RA;
 }
 
+// Running counters are spread over STAT_SLOTS pairs (summed when read): device-scope
+// atomics on one address from every wave of the GPU serialise at the memory side.
+__device__ __forceinline__ void add_stats(unsigned long long* stats, uint32_t inter, uint32_t cand)
+{
+    unsigned long long a = wave_sum<unsigned long long>(inter);
+    unsigned long long b = wave_sum<unsigned long long>(cand);
+    if ((threadIdx.x & (WAVE - 1)) == 0 && (a | b)) {
+        const uint32_t slot = (blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE) % STAT_SLOTS;
+        atomicAdd(&stats[2 * slot], a);
+        atomicAdd(&stats[2 * slot + 1], b);
+    }
+}
+
+// Neighbour geometry of a cell: its voxel coordinates in its slot and the x-range of
+// the three voxels of each neighbour row.
+struct Cellgeo {
+    int kx, ky, kz, x0, x1;
+};
+
+__device__ __forceinline__ Cellgeo cell_geo(uint32_t gvox, const SlotDesc& d)
+{
+    Cellgeo g;
+    const uint32_t v = gvox - d.voxel_off;
+    g.kx = (int)(v % (uint32_t)d.nx);
+    g.ky = (int)((v / (uint32_t)d.nx) % (uint32_t)d.ny);
+    g.kz = (int)(v / ((uint32_t)d.nx * (uint32_t)d.ny));
+    g.x0 = g.kx > 0 ? g.kx - 1 : 0;
+    g.x1 = g.kx < d.nx - 1 ? g.kx + 1 : d.nx - 1;
+    return g;
+}
+
+// Global voxel id of the first voxel of neighbour row q (dz = q/3 - 1, dy = q%3 - 1),
+// or -1 when the row lies outside the slot's grid.
+__device__ __forceinline__ int64_t row_first(const Cellgeo& g, const SlotDesc& d, int q)
+{
+    const int y = g.ky + (q % 3) - 1, z = g.kz + (q / 3) - 1;
+    if (y < 0 || y >= d.ny || z < 0 || z >= d.nz) return -1;
+    return (int64_t)d.voxel_off + (int64_t)d.nx * ((int64_t)y + (int64_t)d.ny * z) + g.x0;
+}
+
+// ------------------------------------------------------------------------ a6 + a7, row kernel
+
+// One thread per cell in voxel order.  The 27 neighbour voxels are visited as 9 rows
+// (dz, dy); the three voxels of a row (dx = -1, 0, 1) are adjacent in voxel order, so a
+// row is one contiguous range of the sorted arrays, read in the oracle's order.
+// PREC: 0 FP64, 1 FP32, 2 FP32 + Kahan.  MULTI: more than one cell type.
+template <int PREC, bool MULTI, typename VPT>
+__device__ __forceinline__ void force_rows_cell(const PhysArgs& P, const ForceArgs<VPT>& a, uint32_t i,
+                                                uint32_t& inter, uint32_t& cand)
+{
+    {
+        const SlotDesc& d = a.slots[a.slot_of[i]];
+        if (d.steps_left == 0) {
+            hold(a, i);
+        } else {
+            const Cellgeo g = cell_geo(a.vid_sorted[i], d);
+            const int ti = MULTI ? a.T[i] : 0;
+            double v[3];
+            if (PREC == 0) {
+                const double xi = a.XS[0][i], yi = a.XS[1][i], zi = a.XS[2][i];
+                const double ri = a.R[i];
+                double ax = 0.0, ay = 0.0, az = 0.0;
+                for (int q = 0; q < 9; ++q) {
+                    const int64_t r0 = row_first(g, d, q);
+                    if (r0 < 0) continue;
+                    const uint32_t b = a.voxel_start[r0], e = a.voxel_start[r0 + (g.x1 - g.x0) + 1];
+                    cand += e - b;
+                    for (uint32_t j = b; j < e; ++j) {
+                        const double c = MULTI ? a.cadh[ti * P.n_types + a.T[j]] : P.c_adh0;
+                        inter += pair64(xi, yi, zi, ri, a.XS[0][j], a.XS[1][j], a.XS[2][j],
+                                        a.R[j], P.alpha, P.c_rep, c, ax, ay, az);
+                    }
+                }
+                v[0] = ax;
+                v[1] = ay;
+                v[2] = az;
+            } else {
+                const float4 me = a.SH[i];
+                float acc[3] = {0.f, 0.f, 0.f}, cmp[3] = {0.f, 0.f, 0.f};
+                for (int q = 0; q < 9; ++q) {
+                    const int64_t r0 = row_first(g, d, q);
+                    if (r0 < 0) continue;
+                    const uint32_t b = a.voxel_start[r0], e = a.voxel_start[r0 + (g.x1 - g.x0) + 1];
+                    cand += e - b;
+                    for (uint32_t j = b; j < e; ++j) {
+                        const float c = MULTI ? a.cadh_f[ti * P.n_types + a.T[j]] : P.c_adh0_f;
+                        inter += pair32<PREC == 2>(me.x, me.y, me.z, me.w, a.SH[j], P.alpha_f,
+                                                   P.c_rep_f, c, acc, cmp);
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < 3; ++c) v[c] = (double)(acc[c] - cmp[c]);
+            }
+            cand -= 1;  // the cell itself
+            integrate(a, P, d, i, v);
+        }
+    }
+}
+
+// The cells of the batch in blocks of BLOCK, taken in rounds of gridDim.x blocks; in
+// each round the active blocks are renumbered so that each XCD gets a contiguous run.
+template <int PREC, bool MULTI, typename VPT>
+__global__ __launch_bounds__(BLOCK) void k_force_rows(PhysArgs P, ForceArgs<VPT> a)
+{
+    const uint32_t n = a.hdr[H_CELLS];
+    const uint32_t nb = (n + BLOCK - 1) / BLOCK;
+    uint32_t inter = 0, cand = 0;
+    for (uint32_t lb0 = 0; lb0 < nb; lb0 += gridDim.x) {
+        const uint32_t active = min(gridDim.x, nb - lb0);
+        if (blockIdx.x >= active) break;
+        const uint32_t i = (lb0 + xcd_block(blockIdx.x, active)) * BLOCK + threadIdx.x;
+        if (i < n) force_rows_cell<PREC, MULTI, VPT>(P, a, i, inter, cand);
+    }
+    add_stats(a.stats, inter, cand);
+}
+
+// ------------------------------------------------------------------------ a6 + a7, list kernel
+
 constexpr int FC_LIST = 16;    // listed candidates a lane holds before a flush
 constexpr int FC_UNROLL = 4;   // candidates tested per loop trip (independent loads in flight)
 
-// One thread per cell in voxel order.  Each lane walks its 9 neighbour rows (dz, dy;
-// the three voxels of a row are adjacent in voxel order) and only prefilters the
-// candidates, four loads in flight per trip: a candidate is listed in LDS when
+// One thread per cell in voxel order.  Each lane walks its 9 neighbour rows and only
+// prefilters the candidates, four loads in flight per trip: a candidate is listed in
+// LDS when
 //   d2 < (alpha (r_i + r_max))^2,
 // which every interacting pair satisfies (r_j <= r_max and rounding is monotonic; d2
 // is the same expression as in the exact test).  When a list fills, and at the end,
@@ -562,22 +664,16 @@ constexpr int FC_UNROLL = 4;   // candidates tested per loop trip (independent l
 // fixed neighbour order and the rare interacting pairs do not make the wave diverge.
 // Lanes of one voxel read the same candidate at the same time (one cache line).
 template <int PREC, bool MULTI, typename VPT>
-__global__ __launch_bounds__(BLOCK) void k_force_cells(uint32_t n, PhysArgs P, ForceArgs<VPT> a)
+__device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceArgs<VPT>& a, uint32_t i,
+                                                 uint32_t n, uint32_t* const list0, uint32_t& inter,
+                                                 uint32_t& cand)
 {
     using Real = typename std::conditional<PREC == 0, double, float>::type;
-    __shared__ uint32_t s_list[BLOCK / WAVE][FC_LIST][WAVE];
-
-    const int lane = threadIdx.x & (WAVE - 1);
-    const int w = threadIdx.x / WAVE;
-    const uint32_t i = xcd_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
-    const bool valid = i < n;
-    const uint32_t ii = valid ? i : n - 1;  // n >= 1: idle lanes mirror the last cell
-    const uint32_t vox = a.vid_sorted[ii];
-    const int kx = (int)(vox % (uint32_t)P.nx);
-    const int ky = (int)((vox / (uint32_t)P.nx) % (uint32_t)P.ny);
-    const int kz = (int)(vox / ((uint32_t)P.nx * (uint32_t)P.ny));
-    const int x0 = kx > 0 ? kx - 1 : 0;
-    const int x1 = kx < P.nx - 1 ? kx + 1 : P.nx - 1;
+    const bool in_pop = i < n;
+    const uint32_t ii = in_pop ? i : n - 1;  // idle lanes mirror the last cell
+    const SlotDesc& d = a.slots[a.slot_of[ii]];
+    const bool valid = in_pop && d.steps_left != 0;
+    const Cellgeo g = cell_geo(a.vid_sorted[ii], d);
     Real xi, yi, zi, ri;
     if constexpr (PREC == 0) {
         xi = a.XS[0][ii];
@@ -595,13 +691,11 @@ __global__ __launch_bounds__(BLOCK) void k_force_cells(uint32_t n, PhysArgs P, F
     {
 #pragma clang fp contract(off)
         const Real reach = (PREC == 0 ? (Real)P.alpha : (Real)P.alpha_f) *
-                           (ri + (PREC == 0 ? (Real)P.r_max : (Real)P.r_max_f));
+                           (ri + (PREC == 0 ? (Real)d.r_max : (Real)d.r_max_f));
         T = reach * reach;
     }
     const int ti = MULTI ? a.T[ii] : 0;
     Real acc[3] = {0, 0, 0}, cmp[3] = {0, 0, 0};
-    uint32_t inter = 0, cand = 0;
-    uint32_t* const list0 = &s_list[w][0][lane];
     uint32_t* const list_hi = list0 + (FC_LIST - FC_UNROLL) * WAVE;
     uint32_t* lp = list0;
 
@@ -636,11 +730,10 @@ __global__ __launch_bounds__(BLOCK) void k_force_cells(uint32_t n, PhysArgs P, F
     };
 
     for (int q = 0; q < 9; ++q) {
-        const int y = ky + (q % 3) - 1, z = kz + (q / 3) - 1;
-        if (!valid || y < 0 || y >= P.ny || z < 0 || z >= P.nz) continue;
-        const uint32_t row = (uint32_t)P.nx * ((uint32_t)y + (uint32_t)P.ny * (uint32_t)z);
-        uint32_t j = a.voxel_start[row + x0];
-        const uint32_t e = a.voxel_start[row + x1 + 1];
+        const int64_t r0 = valid ? row_first(g, d, q) : -1;
+        if (r0 < 0) continue;
+        uint32_t j = a.voxel_start[r0];
+        const uint32_t e = a.voxel_start[r0 + (g.x1 - g.x0) + 1];
         cand += e - j;
         if constexpr (PREC == 0) {
             const double* px = a.XS[0] + j;
@@ -696,20 +789,34 @@ __global__ __launch_bounds__(BLOCK) void k_force_cells(uint32_t n, PhysArgs P, F
     flush();
     if (valid) {
         cand -= 1;  // the cell itself
-        const double xs[3] = {a.XS[0][i], a.XS[1][i], a.XS[2][i]};
+        double v[3];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const double v = (double)(acc[c] - cmp[c]);
-            const double vp = a.euler ? v : (double)a.VP[c][i];
-            const double xn = xs[c] + P.dt * (1.5 * v - 0.5 * vp);
-            a.X[c][i] = reflect(xn, P.lo[c], P.hi[c]);
-            a.VP[c][i] = (VPT)v;
-        }
+        for (int c = 0; c < 3; ++c) v[c] = (double)(acc[c] - cmp[c]);
+        integrate(a, P, d, i, v);
+    } else if (in_pop) {
+        hold(a, i);
+    }
+}
+
+template <int PREC, bool MULTI, typename VPT>
+__global__ __launch_bounds__(BLOCK) void k_force_cells(PhysArgs P, ForceArgs<VPT> a)
+{
+    __shared__ uint32_t s_list[BLOCK / WAVE][FC_LIST][WAVE];
+    const uint32_t n = a.hdr[H_CELLS];
+    const uint32_t nb = (n + BLOCK - 1) / BLOCK;
+    uint32_t* const list0 = &s_list[threadIdx.x / WAVE][0][threadIdx.x & (WAVE - 1)];
+    uint32_t inter = 0, cand = 0;
+    // rounds of gridDim.x blocks, renumbered per round as in k_force_rows
+    for (uint32_t lb0 = 0; lb0 < nb; lb0 += gridDim.x) {
+        const uint32_t active = min(gridDim.x, nb - lb0);
+        if (blockIdx.x >= active) break;
+        const uint32_t i = (lb0 + xcd_block(blockIdx.x, active)) * BLOCK + threadIdx.x;
+        force_cells_cell<PREC, MULTI, VPT>(P, a, i, n, list0, inter, cand);
     }
     add_stats(a.stats, inter, cand);
 }
 
-// ------------------------------------------------------------------------ a6 + a7, LDS-staged
+// ------------------------------------------------------------------------ a6 + a7, voxel kernel
 
 // Per-wave LDS: the candidates of one chunk of the 27-voxel neighbourhood (x, y, z, r),
 // their types, and per-lane lists of in-range candidate indices.
@@ -721,26 +828,17 @@ template <> struct Stage<0> { using T = double4; static constexpr int CAP = 256;
 template <> struct Stage<1> { using T = float4; static constexpr int CAP = 512; };
 template <> struct Stage<2> { using T = float4; static constexpr int CAP = 512; };
 
-// Orders this wave's LDS accesses: writes by one lane are seen by the others after it.
-__device__ __forceinline__ void wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // One wave per occupied voxel: the waves of the grid walk the non-empty voxel list with
-// a fixed stride (empty voxels cost nothing).  The wave stages its 27-voxel neighbourhood in LDS
-// (9 rows, each a contiguous range of the voxel-ordered arrays) and splits its lanes
-// as (target, slice): target t of r = min(64, remaining) takes lanes t, t + r, ...,
-// so all 64 lanes test candidates.  A lane appends the in-range candidates of its slice
-// to an LDS list and evaluates them in a batch, so the force arithmetic does not
-// diverge on the rare in-range branch.  Slices are combined in a fixed order: results
-// are bitwise reproducible.
+// a fixed stride (empty voxels cost nothing).  The wave stages its 27-voxel
+// neighbourhood in LDS (9 rows, each a contiguous range of the voxel-ordered arrays)
+// and splits its lanes as (target, slice): target t of r = min(64, remaining) takes
+// lanes t, t + r, ..., so all 64 lanes test candidates.  A lane appends the in-range
+// candidates of its slice to an LDS list and evaluates them in a batch, so the force
+// arithmetic does not diverge on the rare in-range branch.  Slices are combined in a
+// fixed order: results are bitwise reproducible.
 template <int PREC, bool MULTI, typename VPT>
 __global__ __launch_bounds__(FL_WAVES * WAVE) void k_force_lds(PhysArgs P, ForceArgs<VPT> a,
-                                                               const uint32_t* __restrict__ occ,
-                                                               const uint32_t* __restrict__ n_occ)
+                                                               const uint32_t* __restrict__ occ)
 {
     using CT = typename Stage<PREC>::T;
     using Real = typename std::conditional<PREC == 0, double, float>::type;
@@ -752,7 +850,7 @@ __global__ __launch_bounds__(FL_WAVES * WAVE) void k_force_lds(PhysArgs P, Force
     const int lane = threadIdx.x & (WAVE - 1);
     const int w = threadIdx.x / WAVE;
     CT* stage = s_stage[w];
-    const uint32_t M = *n_occ;
+    const uint32_t M = a.hdr[H_OCC];
     uint32_t inter = 0, cand = 0;
 
     // wave q of the (XCD-renumbered) grid takes occupied voxels q, q + W, q + 2W, ...
@@ -760,28 +858,28 @@ __global__ __launch_bounds__(FL_WAVES * WAVE) void k_force_lds(PhysArgs P, Force
     const uint32_t q0 = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * FL_WAVES + w);
     for (uint32_t o = q0; o < M; o += nwaves) {
         const uint32_t vox = __builtin_amdgcn_readfirstlane(occ[o]);
-        const int kx = (int)(vox % (uint32_t)P.nx);
-        const int ky = (int)((vox / (uint32_t)P.nx) % (uint32_t)P.ny);
-        const int kz = (int)(vox / ((uint32_t)P.nx * (uint32_t)P.ny));
-        const int x0 = kx > 0 ? kx - 1 : 0;
-        const int x1 = kx < P.nx - 1 ? kx + 1 : P.nx - 1;
+        const uint32_t vb = a.voxel_start[vox], k = a.voxel_start[vox + 1] - vb;
+        const SlotDesc& d = a.slots[__builtin_amdgcn_readfirstlane(a.slot_of[vb])];
+        if (d.steps_left == 0) {
+            for (uint32_t t = lane; t < k; t += WAVE) hold(a, vb + t);
+            continue;
+        }
+        const Cellgeo g = cell_geo(vox, d);
         // the 9 rows in (dz, dy) order; rows outside the grid are empty
         uint32_t rb[9], pre[10];
         pre[0] = 0;
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
-            const int y = ky + (q % 3) - 1, z = kz + (q / 3) - 1;
+            const int64_t r0 = row_first(g, d, q);
             uint32_t b = 0, e = 0;
-            if (y >= 0 && y < P.ny && z >= 0 && z < P.nz) {
-                const uint32_t row = (uint32_t)P.nx * ((uint32_t)y + (uint32_t)P.ny * (uint32_t)z);
-                b = a.voxel_start[row + x0];
-                e = a.voxel_start[row + x1 + 1];
+            if (r0 >= 0) {
+                b = a.voxel_start[r0];
+                e = a.voxel_start[r0 + (g.x1 - g.x0) + 1];
             }
             rb[q] = b;
             pre[q + 1] = pre[q] + (e - b);
         }
         const uint32_t C = pre[9];
-        const uint32_t vb = a.voxel_start[vox], k = a.voxel_start[vox + 1] - vb;
 
         for (uint32_t t0 = 0; t0 < k; t0 += WAVE) {
             const uint32_t r = min((uint32_t)WAVE, k - t0);
@@ -823,16 +921,16 @@ __global__ __launch_bounds__(FL_WAVES * WAVE) void k_force_lds(PhysArgs P, Force
                 wave_sync();
                 for (uint32_t f = lane; f < len; f += WAVE) {
                     const uint32_t ff = cb + f;
-                    uint32_t g = ff + rb[0];
+                    uint32_t gi = ff + rb[0];
 #pragma unroll
                     for (int q = 1; q < 9; ++q)
-                        if (ff >= pre[q]) g = ff - pre[q] + rb[q];
+                        if (ff >= pre[q]) gi = ff - pre[q] + rb[q];
                     if constexpr (PREC == 0) {
-                        stage[f] = make_double4(a.XS[0][g], a.XS[1][g], a.XS[2][g], a.R[g]);
+                        stage[f] = make_double4(a.XS[0][gi], a.XS[1][gi], a.XS[2][gi], a.R[gi]);
                     } else {
-                        stage[f] = a.SH[g];
+                        stage[f] = a.SH[gi];
                     }
-                    if (MULTI) s_type[w][f] = (uint8_t)a.T[g];
+                    if (MULTI) s_type[w][f] = (uint8_t)a.T[gi];
                 }
                 wave_sync();
                 for (uint32_t m = s; m < len; m += St) {
@@ -880,15 +978,10 @@ __global__ __launch_bounds__(FL_WAVES * WAVE) void k_force_lds(PhysArgs P, Force
                     }
                 }
                 cand += C - 1;
-                const double xs[3] = {a.XS[0][i], a.XS[1][i], a.XS[2][i]};
+                double v[3];
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    const double v = (double)tot[c];
-                    const double vp = a.euler ? v : (double)a.VP[c][i];
-                    const double xn = xs[c] + P.dt * (1.5 * v - 0.5 * vp);
-                    a.X[c][i] = reflect(xn, (&P.lo[0])[c], (&P.hi[0])[c]);
-                    a.VP[c][i] = (VPT)v;
-                }
+                for (int c = 0; c < 3; ++c) v[c] = (double)(tot[c] - tc[c]);
+                integrate(a, P, d, i, v);
             }
             wave_sync();
         }
@@ -896,9 +989,76 @@ __global__ __launch_bounds__(FL_WAVES * WAVE) void k_force_lds(PhysArgs P, Force
     add_stats(a.stats, inter, cand);
 }
 
-// read_state: voxel order -> id order, interleaved xyz.
+// ------------------------------------------------------------------------ step end, slots
+
+// Counts down the steps of every slot still running; a slot that reaches 0 is frozen
+// from the next step on.  The first step has been taken, so no slot starts with Euler.
+__global__ __launch_bounds__(BLOCK) void k_step_end(SlotDesc* __restrict__ slots, uint32_t n_slots)
+{
+    const uint32_t t = blockIdx.x * BLOCK + threadIdx.x;
+    if (t >= n_slots) return;
+    if (slots[t].steps_left > 0) slots[t].steps_left -= 1;
+    slots[t].euler = 0;
+}
+
+__global__ void k_set_slot(SlotDesc* __restrict__ slots, uint32_t id, SlotDesc d) { slots[id] = d; }
+
+__global__ void k_set_header(uint32_t* __restrict__ hdr, uint32_t n_cells, uint32_t n_voxels)
+{
+    hdr[H_CELLS] = n_cells;
+    hdr[H_VOXELS] = n_voxels;
+}
+
+// Moves the cells of the live slots to their new offsets (the slot table holds the old
+// and new offsets; n_cells == 0 marks a retired slot, whose cells are dropped).
 template <typename VPT>
-__global__ __launch_bounds__(BLOCK) void k_unpermute(uint32_t n, const uint32_t* __restrict__ id,
+struct RepackArgs {
+    const double* X[3];
+    double* XS[3];
+    const double* R_cur;
+    double* R_new;
+    const int32_t* T_cur;
+    int32_t* T_new;
+    const uint32_t* ID_cur;
+    uint32_t* ID_new;
+    const VPT* VP_cur[3];
+    VPT* VP_new[3];
+    const uint32_t* slot_of;
+    uint32_t* slot_new;
+    const SlotDesc* slots;
+};
+
+template <typename VPT>
+__global__ __launch_bounds__(BLOCK) void k_repack(uint32_t n_old, RepackArgs<VPT> a)
+{
+    const uint32_t s = blockIdx.x * BLOCK + threadIdx.x;
+    if (s >= n_old) return;
+    const uint32_t k = a.slot_of[s];
+    const SlotDesc& d = a.slots[k];
+    if (d.n_cells == 0) return;
+    const uint32_t t = d.cell_off + (s - d.prev_cell_off);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        a.XS[c][t] = a.X[c][s];
+        a.VP_new[c][t] = a.VP_cur[c][s];
+    }
+    a.R_new[t] = a.R_cur[s];
+    a.T_new[t] = a.T_cur[s];
+    a.ID_new[t] = a.ID_cur[s] - d.prev_cell_off + d.cell_off;
+    a.slot_new[t] = k;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_copy_u32(uint32_t n, const uint32_t* __restrict__ a,
+                                                    uint32_t* __restrict__ b)
+{
+    const uint32_t s = blockIdx.x * BLOCK + threadIdx.x;
+    if (s < n) b[s] = a[s];
+}
+
+// read-back of one slot: voxel order -> the slot's own id order, interleaved xyz.
+template <typename VPT>
+__global__ __launch_bounds__(BLOCK) void k_unpermute(uint32_t cell_off, uint32_t n,
+                                                     const uint32_t* __restrict__ id,
                                                      const double* __restrict__ x0,
                                                      const double* __restrict__ x1,
                                                      const double* __restrict__ x2,
@@ -908,9 +1068,10 @@ __global__ __launch_bounds__(BLOCK) void k_unpermute(uint32_t n, const uint32_t*
                                                      double* __restrict__ pos,
                                                      double* __restrict__ vel)
 {
-    uint32_t s = blockIdx.x * BLOCK + threadIdx.x;
-    if (s >= n) return;
-    uint32_t k = id[s];
+    const uint32_t t = blockIdx.x * BLOCK + threadIdx.x;
+    if (t >= n) return;
+    const uint32_t s = cell_off + t;
+    const uint32_t k = id[s] - cell_off;
     pos[3 * k + 0] = x0[s];
     pos[3 * k + 1] = x1[s];
     pos[3 * k + 2] = x2[s];
@@ -924,14 +1085,14 @@ __global__ __launch_bounds__(BLOCK) void k_unpermute(uint32_t n, const uint32_t*
 inline uint32_t blocks_for(uint64_t n, uint32_t per) { return (uint32_t)((n + per - 1) / per); }
 
 struct Layout {
-    size_t X[3], XS[3], R[2], T[2], ID[2], VP[2][3], SH, vid_cur, off, tmp_key, tmp_src,
-        vid_sorted, count, start, occ, n_occ, tsum, stats, cadh, cadh_f, stage;
+    size_t X[3], XS[3], R[2], T[2], ID[2], VP[2][3], SH, slot_of, vid_cur, off, tmp_key,
+        tmp_src, vid_sorted, count, start, occ, hdr, tsum, stats, cadh, cadh_f, slots, stage;
     size_t total;
 };
 
 bool is_fp32(const MechParams& p) { return p.precision != MECH_FP64; }
 
-Layout make_layout(const MechParams& p, int64_t n, uint64_t V)
+Layout make_layout(const MechParams& p, int64_t ncap, uint64_t vcap, int32_t scap)
 {
     Layout L{};
     size_t cur = 0;
@@ -940,7 +1101,8 @@ Layout make_layout(const MechParams& p, int64_t n, uint64_t V)
         cur += (bytes + 255) & ~size_t(255);
         return o;
     };
-    const size_t nn = (size_t)std::max<int64_t>(n, 1);
+    const size_t nn = (size_t)std::max<int64_t>(ncap, 1);
+    const size_t vv = (size_t)std::max<uint64_t>(vcap, 1);
     const size_t vpb = is_fp32(p) ? sizeof(float) : sizeof(double);
     for (int c = 0; c < 3; ++c) L.X[c] = take(nn * 8);
     for (int c = 0; c < 3; ++c) L.XS[c] = take(nn * 8);
@@ -951,25 +1113,28 @@ Layout make_layout(const MechParams& p, int64_t n, uint64_t V)
         for (int c = 0; c < 3; ++c) L.VP[k][c] = take(nn * vpb);
     }
     L.SH = is_fp32(p) ? take(nn * 16) : 0;
+    L.slot_of = take(nn * 4);
     L.vid_cur = take(nn * 4);
     L.off = take(nn * 4);
     L.tmp_key = take(nn * 4);
     L.tmp_src = take(nn * 4);
     L.vid_sorted = take(nn * 4);
-    L.count = take(V * 4);
-    L.start = take((V + 1) * 4);
-    L.occ = take(V * 4);
-    L.n_occ = take(16);
-    L.tsum = take((size_t)blocks_for(V, SCAN_TILE) * 8);
+    L.count = take(vv * 4);
+    L.start = take((vv + 1) * 4);
+    L.occ = take(vv * 4);
+    L.hdr = take(16);
+    L.tsum = take((size_t)blocks_for(vv, SCAN_TILE) * 8);
     L.stats = take(STAT_SLOTS * 16);
     L.cadh = take(64 * 8);
     L.cadh_f = take(64 * 4);
+    L.slots = take((size_t)std::max(scap, 1) * sizeof(SlotDesc));
     L.stage = take(nn * 48);
     L.total = cur;
     return L;
 }
 
-int validate(const MechParams* p, int64_t n, int32_t dims[3])
+// Parameters shared by the slots of a batch (the domain fields are not used here).
+int validate_physics(const MechParams* p)
 {
     if (!p) return fail(MECH_E_INVALID, "params is NULL");
     if (p->abi_version != MECH_ABI_VERSION)
@@ -985,7 +1150,6 @@ int validate(const MechParams* p, int64_t n, int32_t dims[3])
         if (k & (k - 1)) return fail(MECH_E_INVALID, "at most one force-kernel flag may be set");
     }
     if (p->reserved != 0) return fail(MECH_E_INVALID, "reserved field must be 0");
-    if (n < 0 || n >= (int64_t(1) << 31)) return fail(MECH_E_INVALID, "n_cells %lld out of range", (long long)n);
     if (!(std::isfinite(p->voxel_size) && p->voxel_size > 0))
         return fail(MECH_E_INVALID, "voxel_size must be finite and > 0");
     if (!(std::isfinite(p->dt) && p->dt > 0)) return fail(MECH_E_INVALID, "dt must be finite and > 0");
@@ -999,23 +1163,30 @@ int validate(const MechParams* p, int64_t n, int32_t dims[3])
             if (!std::isfinite(a) || a < 0) return fail(MECH_E_INVALID, "c_adh[%d][%d] must be finite and >= 0", i, j);
             if (a != b) return fail(MECH_E_INVALID, "c_adh is not symmetric at [%d][%d]", i, j);
         }
-    uint64_t V = 1;
-    for (int a = 0; a < 3; ++a) {
-        double lo = p->domain_lo[a], hi = p->domain_hi[a];
-        if (!(std::isfinite(lo) && std::isfinite(hi) && hi >= lo))
-            return fail(MECH_E_INVALID, "domain axis %d: need finite lo <= hi", a);
-        double cells = std::ceil((hi - lo) / p->voxel_size);
-        if (cells > 2147483647.0) return fail(MECH_E_INVALID, "too many voxels on axis %d", a);
-        dims[a] = std::max(1, (int)cells);
-        V *= (uint64_t)dims[a];
-    }
-    if (V >= (uint64_t(1) << 31)) return fail(MECH_E_INVALID, "grid of %llu voxels is too large", (unsigned long long)V);
     return MECH_OK;
 }
 
-int validate_cells(const MechParams* p, int64_t n, const double* pos, const double* radius,
-                   const int32_t* type, const double* vprev)
+int validate_domain(const double lo[3], const double hi[3], double h, int32_t dims[3], uint64_t* V)
 {
+    uint64_t v = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (!(std::isfinite(lo[a]) && std::isfinite(hi[a]) && hi[a] >= lo[a]))
+            return fail(MECH_E_INVALID, "domain axis %d: need finite lo <= hi", a);
+        double cells = std::ceil((hi[a] - lo[a]) / h);
+        if (cells > 2147483647.0) return fail(MECH_E_INVALID, "too many voxels on axis %d", a);
+        dims[a] = std::max(1, (int)cells);
+        v *= (uint64_t)dims[a];
+    }
+    if (v >= (uint64_t(1) << 31)) return fail(MECH_E_INVALID, "grid of %llu voxels is too large", (unsigned long long)v);
+    *V = v;
+    return MECH_OK;
+}
+
+int validate_cells(const MechParams* p, const double lo[3], const double hi[3], int64_t n,
+                   const double* pos, const double* radius, const int32_t* type,
+                   const double* vprev, double* rmax_out)
+{
+    if (n < 0 || n >= (int64_t(1) << 31)) return fail(MECH_E_INVALID, "n_cells %lld out of range", (long long)n);
     if (n > 0 && (!pos || !radius)) return fail(MECH_E_INVALID, "pos and radius are required");
     double rmax = 0.0;
     for (int64_t i = 0; i < n; ++i) {
@@ -1025,7 +1196,7 @@ int validate_cells(const MechParams* p, int64_t n, const double* pos, const doub
         for (int a = 0; a < 3; ++a) {
             double x = pos[3 * i + a];
             if (!std::isfinite(x)) return fail(MECH_E_INVALID, "pos[%lld] is not finite", (long long)i);
-            if (x < p->domain_lo[a] || x > p->domain_hi[a])
+            if (x < lo[a] || x > hi[a])
                 return fail(MECH_E_OUT_OF_DOMAIN, "cell %lld lies outside the domain on axis %d", (long long)i, a);
             if (vprev && !std::isfinite(vprev[3 * i + a]))
                 return fail(MECH_E_INVALID, "prev_velocity[%lld] is not finite", (long long)i);
@@ -1037,28 +1208,41 @@ int validate_cells(const MechParams* p, int64_t n, const double* pos, const doub
     if (p->voxel_size < p->rel_adh_distance * 2.0 * rmax)
         return fail(MECH_E_VOXEL_TOO_SMALL, "voxel_size %.17g < %.17g (rel_adh_distance * 2 * max radius)",
                     p->voxel_size, p->rel_adh_distance * 2.0 * rmax);
+    *rmax_out = rmax;
     return MECH_OK;
 }
 
+// Host view of one slot.
+struct HostSlot {
+    SlotDesc d{};
+    bool used = false;       // holds a simulation (running, frozen or retired)
+    bool retired = false;    // cells still in the arena until the next repack
+    bool reported = false;   // completion already returned by batch_poll
+    int64_t steps_total = 0; // steps requested (< 0: no limit)
+    hipEvent_t done = nullptr;  // recorded after the step that froze the slot
+    bool done_recorded = false;
+};
+
 }  // namespace
 
-struct MechPopulation {
-    MechParams prm;
-    int device = 0;
-    int64_t n = 0;
-    int32_t dims[3] = {1, 1, 1};
-    uint32_t V = 1, n_tiles = 1;
-    uint32_t force_grid = 1024;  // workgroups of the persistent force kernel
-    GridArgs grid{};
+struct MechBatch {
+    MechParams prm{};
     PhysArgs phys{};
-    hipStream_t stream = nullptr;
+    int device = 0;
+    hipStream_t stream = nullptr, copy_stream = nullptr;
     bool own_stream = false;
+    hipEvent_t copy_done = nullptr;
     char* arena = nullptr;
     bool own_arena = false;
     Layout L{};
+    int64_t cap_cells = 0, cap_voxels = 0;
+    int32_t cap_slots = 0;
+    uint32_t n_cells = 0, n_voxels = 0;   // host mirror of the header
+    std::vector<HostSlot> slots;
+    std::vector<int32_t> order;           // used slots in arena order
     int parity = 0;
     int64_t steps = 0;
-    bool euler_pending = false;
+    uint32_t force_grid = 1024;
     bool graphs_ready = false;
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
 
@@ -1066,303 +1250,625 @@ struct MechPopulation {
     T* at(size_t off) const { return reinterpret_cast<T*>(arena + off); }
 };
 
+struct MechPopulation {
+    MechBatch* b = nullptr;
+    int64_t n = 0;
+};
+
 namespace {
 
-template <typename VPT>
-void enqueue_binning(MechPopulation* P)
+// ------------------------------------------------------------------------ enqueue
+
+// Launch grids are fixed per batch (the captured graph never changes) and bounded: the
+// kernels loop over what the device header says is live, so a large arena costs no
+// empty workgroups.
+constexpr uint32_t CELL_GRID_MAX = 8192;   // workgroups of 256 for per-cell kernels
+constexpr uint32_t TILE_GRID_MAX = 2048;   // workgroups for the voxel-scan kernels
+
+uint32_t cell_grid(const MechBatch* B)
 {
-    const uint32_t n = (uint32_t)P->n;
-    const Layout& L = P->L;
-    const int cur = P->parity, nxt = cur ^ 1;
-    const uint32_t nb = blocks_for(n, BLOCK);
-    hipLaunchKernelGGL(k_bin, dim3(nb), dim3(BLOCK), 0, P->stream, P->at<double>(L.X[0]),
-                       P->at<double>(L.X[1]), P->at<double>(L.X[2]), n, P->grid,
-                       P->at<uint32_t>(L.count), P->at<uint32_t>(L.vid_cur), P->at<uint32_t>(L.off));
-    hipLaunchKernelGGL(k_scan_reduce, dim3(P->n_tiles), dim3(BLOCK), 0, P->stream,
-                       P->at<uint32_t>(L.count), P->V, P->at<uint64_t>(L.tsum));
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(BLOCK), 0, P->stream, P->at<uint64_t>(L.tsum),
-                       P->n_tiles, P->at<uint32_t>(L.start), P->V, P->at<uint32_t>(L.n_occ));
-    hipLaunchKernelGGL(k_scan_down, dim3(P->n_tiles), dim3(BLOCK), 0, P->stream,
-                       P->at<uint32_t>(L.count), P->V, P->at<uint64_t>(L.tsum),
-                       P->at<uint32_t>(L.start), P->at<uint32_t>(L.occ));
-    hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(BLOCK), 0, P->stream, n, P->at<uint32_t>(L.vid_cur),
-                       P->at<uint32_t>(L.off), P->at<uint32_t>(L.start), P->at<uint32_t>(L.ID[cur]),
-                       P->at<uint32_t>(L.tmp_key), P->at<uint32_t>(L.tmp_src));
+    return std::max<uint32_t>(1, std::min<uint32_t>(blocks_for((uint64_t)B->cap_cells, BLOCK), CELL_GRID_MAX));
+}
+
+template <typename VPT>
+void enqueue_binning(MechBatch* B)
+{
+    const Layout& L = B->L;
+    const int cur = B->parity, nxt = cur ^ 1;
+    const uint32_t nbc = cell_grid(B);
+    const uint32_t nbt = std::min<uint32_t>(blocks_for((uint64_t)B->cap_voxels, SCAN_TILE), TILE_GRID_MAX);
+    const uint32_t* hdr = B->at<uint32_t>(L.hdr);
+    hipLaunchKernelGGL(k_bin, dim3(nbc), dim3(BLOCK), 0, B->stream, B->at<double>(L.X[0]),
+                       B->at<double>(L.X[1]), B->at<double>(L.X[2]), B->at<uint32_t>(L.slot_of),
+                       B->at<SlotDesc>(L.slots), hdr, B->at<uint32_t>(L.count), B->at<uint32_t>(L.vid_cur),
+                       B->at<uint32_t>(L.off));
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nbt), dim3(BLOCK), 0, B->stream, B->at<uint32_t>(L.count), hdr,
+                       B->at<uint64_t>(L.tsum));
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(BLOCK), 0, B->stream, B->at<uint64_t>(L.tsum),
+                       B->at<uint32_t>(L.start), B->at<uint32_t>(L.hdr));
+    hipLaunchKernelGGL(k_scan_down, dim3(nbt), dim3(BLOCK), 0, B->stream, B->at<uint32_t>(L.count), hdr,
+                       B->at<uint64_t>(L.tsum), B->at<uint32_t>(L.start), B->at<uint32_t>(L.occ));
+    hipLaunchKernelGGL(k_scatter, dim3(nbc), dim3(BLOCK), 0, B->stream, hdr, B->at<uint32_t>(L.vid_cur),
+                       B->at<uint32_t>(L.off), B->at<uint32_t>(L.start), B->at<uint32_t>(L.ID[cur]),
+                       B->at<uint32_t>(L.tmp_key), B->at<uint32_t>(L.tmp_src));
     GatherArgs<VPT> g{};
     for (int c = 0; c < 3; ++c) {
-        g.X[c] = P->at<double>(L.X[c]);
-        g.XS[c] = P->at<double>(L.XS[c]);
-        g.VP_cur[c] = P->at<VPT>(L.VP[cur][c]);
-        g.VP_new[c] = P->at<VPT>(L.VP[nxt][c]);
+        g.X[c] = B->at<double>(L.X[c]);
+        g.XS[c] = B->at<double>(L.XS[c]);
+        g.VP_cur[c] = B->at<VPT>(L.VP[cur][c]);
+        g.VP_new[c] = B->at<VPT>(L.VP[nxt][c]);
     }
-    g.R_cur = P->at<double>(L.R[cur]);
-    g.R_new = P->at<double>(L.R[nxt]);
-    g.T_cur = P->at<int32_t>(L.T[cur]);
-    g.T_new = P->at<int32_t>(L.T[nxt]);
-    g.ID_new = P->at<uint32_t>(L.ID[nxt]);
-    g.SH = is_fp32(P->prm) ? P->at<float4>(L.SH) : nullptr;
-    g.vid_cur = P->at<uint32_t>(L.vid_cur);
-    g.tmp_key = P->at<uint32_t>(L.tmp_key);
-    g.tmp_src = P->at<uint32_t>(L.tmp_src);
-    g.voxel_start = P->at<uint32_t>(L.start);
-    g.vid_sorted = P->at<uint32_t>(L.vid_sorted);
-    hipLaunchKernelGGL(k_rank_gather<VPT>, dim3(nb), dim3(BLOCK), 0, P->stream, n, g);
+    g.R_cur = B->at<double>(L.R[cur]);
+    g.R_new = B->at<double>(L.R[nxt]);
+    g.T_cur = B->at<int32_t>(L.T[cur]);
+    g.T_new = B->at<int32_t>(L.T[nxt]);
+    g.ID_new = B->at<uint32_t>(L.ID[nxt]);
+    g.SH = is_fp32(B->prm) ? B->at<float4>(L.SH) : nullptr;
+    g.vid_cur = B->at<uint32_t>(L.vid_cur);
+    g.tmp_key = B->at<uint32_t>(L.tmp_key);
+    g.tmp_src = B->at<uint32_t>(L.tmp_src);
+    g.voxel_start = B->at<uint32_t>(L.start);
+    g.vid_sorted = B->at<uint32_t>(L.vid_sorted);
+    hipLaunchKernelGGL(k_rank_gather<VPT>, dim3(nbc), dim3(BLOCK), 0, B->stream, hdr, g);
 }
 
 template <int PREC, typename VPT>
-void enqueue_force(MechPopulation* P, int parity_after_sort, int euler)
+void enqueue_force(MechBatch* B, int parity_after_sort)
 {
-    const uint32_t n = (uint32_t)P->n;
-    const Layout& L = P->L;
+    const Layout& L = B->L;
     const int p = parity_after_sort;
     ForceArgs<VPT> a{};
     for (int c = 0; c < 3; ++c) {
-        a.XS[c] = P->at<double>(L.XS[c]);
-        a.X[c] = P->at<double>(L.X[c]);
-        a.VP[c] = P->at<VPT>(L.VP[p][c]);
+        a.XS[c] = B->at<double>(L.XS[c]);
+        a.X[c] = B->at<double>(L.X[c]);
+        a.VP[c] = B->at<VPT>(L.VP[p][c]);
     }
-    a.R = P->at<double>(L.R[p]);
-    a.T = P->at<int32_t>(L.T[p]);
-    a.SH = is_fp32(P->prm) ? P->at<float4>(L.SH) : nullptr;
-    a.vid_sorted = P->at<uint32_t>(L.vid_sorted);
-    a.voxel_start = P->at<uint32_t>(L.start);
-    a.cadh = P->at<double>(L.cadh);
-    a.cadh_f = P->at<float>(L.cadh_f);
-    a.stats = P->at<unsigned long long>(L.stats);
-    a.euler = euler;
-    if (P->prm.flags & MECH_FLAG_SIMPLE_FORCE) {
-        const uint32_t nb = blocks_for(n, BLOCK);
-        if (P->prm.n_types > 1)
-            hipLaunchKernelGGL((k_force_rows<PREC, true, VPT>), dim3(nb), dim3(BLOCK), 0, P->stream, n, P->phys, a);
+    a.R = B->at<double>(L.R[p]);
+    a.T = B->at<int32_t>(L.T[p]);
+    a.SH = is_fp32(B->prm) ? B->at<float4>(L.SH) : nullptr;
+    a.vid_sorted = B->at<uint32_t>(L.vid_sorted);
+    a.voxel_start = B->at<uint32_t>(L.start);
+    a.slot_of = B->at<uint32_t>(L.slot_of);
+    a.slots = B->at<SlotDesc>(L.slots);
+    a.hdr = B->at<uint32_t>(L.hdr);
+    a.cadh = B->at<double>(L.cadh);
+    a.cadh_f = B->at<float>(L.cadh_f);
+    a.stats = B->at<unsigned long long>(L.stats);
+    const bool multi = B->prm.n_types > 1;
+    const uint32_t nbc = cell_grid(B);
+    if (B->prm.flags & MECH_FLAG_SIMPLE_FORCE) {
+        if (multi)
+            hipLaunchKernelGGL((k_force_rows<PREC, true, VPT>), dim3(nbc), dim3(BLOCK), 0, B->stream, B->phys, a);
         else
-            hipLaunchKernelGGL((k_force_rows<PREC, false, VPT>), dim3(nb), dim3(BLOCK), 0, P->stream, n, P->phys, a);
-        return;
-    }
-    if (!(P->prm.flags & MECH_FLAG_VOXEL_FORCE)) {
-        const uint32_t nb = blocks_for(n, BLOCK);
-        if (P->prm.n_types > 1)
-            hipLaunchKernelGGL((k_force_cells<PREC, true, VPT>), dim3(nb), dim3(BLOCK), 0, P->stream, n, P->phys, a);
+            hipLaunchKernelGGL((k_force_rows<PREC, false, VPT>), dim3(nbc), dim3(BLOCK), 0, B->stream, B->phys, a);
+    } else if (B->prm.flags & MECH_FLAG_VOXEL_FORCE) {
+        const uint32_t* occ = B->at<uint32_t>(L.occ);
+        if (multi)
+            hipLaunchKernelGGL((k_force_lds<PREC, true, VPT>), dim3(B->force_grid), dim3(FL_WAVES * WAVE), 0,
+                               B->stream, B->phys, a, occ);
         else
-            hipLaunchKernelGGL((k_force_cells<PREC, false, VPT>), dim3(nb), dim3(BLOCK), 0, P->stream, n, P->phys, a);
-        return;
+            hipLaunchKernelGGL((k_force_lds<PREC, false, VPT>), dim3(B->force_grid), dim3(FL_WAVES * WAVE), 0,
+                               B->stream, B->phys, a, occ);
+    } else {
+        if (multi)
+            hipLaunchKernelGGL((k_force_cells<PREC, true, VPT>), dim3(nbc), dim3(BLOCK), 0, B->stream, B->phys, a);
+        else
+            hipLaunchKernelGGL((k_force_cells<PREC, false, VPT>), dim3(nbc), dim3(BLOCK), 0, B->stream, B->phys, a);
     }
-    // persistent grid of fixed size (graph-safe); waves walk the occupied-voxel list
-    const uint32_t* occ = P->at<uint32_t>(L.occ);
-    const uint32_t* m = P->at<uint32_t>(L.n_occ);
-    if (P->prm.n_types > 1)
-        hipLaunchKernelGGL((k_force_lds<PREC, true, VPT>), dim3(P->force_grid), dim3(FL_WAVES * WAVE), 0,
-                           P->stream, P->phys, a, occ, m);
+}
+
+void enqueue_binning_any(MechBatch* B)
+{
+    if (is_fp32(B->prm))
+        enqueue_binning<float>(B);
     else
-        hipLaunchKernelGGL((k_force_lds<PREC, false, VPT>), dim3(P->force_grid), dim3(FL_WAVES * WAVE), 0,
-                           P->stream, P->phys, a, occ, m);
+        enqueue_binning<double>(B);
 }
 
-// One full step a1..a7 from the current parity; flips nothing on the host.
-void enqueue_step(MechPopulation* P, int parity, int euler)
+void enqueue_force_any(MechBatch* B, int parity_after_sort)
 {
-    const int saved = P->parity;
-    P->parity = parity;
-    switch (P->prm.precision) {
-    case MECH_FP64:
-        enqueue_binning<double>(P);
-        enqueue_force<0, double>(P, parity ^ 1, euler);
-        break;
-    case MECH_FP32:
-        enqueue_binning<float>(P);
-        enqueue_force<1, float>(P, parity ^ 1, euler);
-        break;
-    default:
-        enqueue_binning<float>(P);
-        enqueue_force<2, float>(P, parity ^ 1, euler);
-        break;
+    switch (B->prm.precision) {
+    case MECH_FP64: enqueue_force<0, double>(B, parity_after_sort); break;
+    case MECH_FP32: enqueue_force<1, float>(B, parity_after_sort); break;
+    default: enqueue_force<2, float>(B, parity_after_sort); break;
     }
-    P->parity = saved;
 }
 
-int sync_check(MechPopulation* P)
+void enqueue_step_end(MechBatch* B)
 {
-    HIP_TRY(hipStreamSynchronize(P->stream));
+    hipLaunchKernelGGL(k_step_end, dim3(blocks_for((uint64_t)B->cap_slots, BLOCK)), dim3(BLOCK), 0, B->stream,
+                       B->at<SlotDesc>(B->L.slots), (uint32_t)B->cap_slots);
+}
+
+// One full step a1..a7 from `parity`; flips nothing on the host.
+void enqueue_step(MechBatch* B, int parity)
+{
+    const int saved = B->parity;
+    B->parity = parity;
+    enqueue_binning_any(B);
+    enqueue_force_any(B, parity ^ 1);
+    enqueue_step_end(B);
+    B->parity = saved;
+}
+
+int sync_check(MechBatch* B)
+{
+    HIP_TRY(hipStreamSynchronize(B->stream));
     HIP_TRY(hipGetLastError());
     return MECH_OK;
 }
 
-int build_graphs(MechPopulation* P)
+int drop_graphs(MechBatch* B)
 {
-    for (int p = 0; p < 2; ++p) {
-        hipGraph_t g = nullptr;
-        HIP_TRY(hipStreamBeginCapture(P->stream, hipStreamCaptureModeThreadLocal));
-        enqueue_step(P, p, 0);
-        hipError_t e = hipStreamEndCapture(P->stream, &g);
-        if (e != hipSuccess) return fail(MECH_E_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
-        e = hipGraphInstantiate(&P->gexec[p], g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        if (e != hipSuccess) return fail(MECH_E_DEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
-    }
-    P->graphs_ready = true;
+    for (int p = 0; p < 2; ++p)
+        if (B->gexec[p]) {
+            (void)hipGraphExecDestroy(B->gexec[p]);
+            B->gexec[p] = nullptr;
+        }
+    B->graphs_ready = false;
     return MECH_OK;
 }
 
-void release(MechPopulation* P)
+int build_graphs(MechBatch* B)
 {
-    if (!P) return;
-    (void)hipSetDevice(P->device);
-    if (P->stream) (void)hipStreamSynchronize(P->stream);
-    for (int p = 0; p < 2; ++p)
-        if (P->gexec[p]) (void)hipGraphExecDestroy(P->gexec[p]);
-    if (P->own_arena && P->arena) (void)hipFree(P->arena);
-    if (P->own_stream && P->stream) (void)hipStreamDestroy(P->stream);
-    delete P;
+    for (int p = 0; p < 2; ++p) {
+        hipGraph_t g = nullptr;
+        HIP_TRY(hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal));
+        enqueue_step(B, p);
+        hipError_t e = hipStreamEndCapture(B->stream, &g);
+        if (e != hipSuccess) return fail(MECH_E_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
+        e = hipGraphInstantiate(&B->gexec[p], g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return fail(MECH_E_DEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
+    }
+    B->graphs_ready = true;
+    return MECH_OK;
 }
 
-int create_impl(const MechParams* params, int64_t n, const double* pos, const double* radius,
-                const int32_t* type, const double* vprev, void* stream, void* workspace,
-                int64_t ws_bytes, MechPopulation** out)
+void release(MechBatch* B)
+{
+    if (!B) return;
+    (void)hipSetDevice(B->device);
+    if (B->stream) (void)hipStreamSynchronize(B->stream);
+    if (B->copy_stream) (void)hipStreamSynchronize(B->copy_stream);
+    drop_graphs(B);
+    for (auto& s : B->slots)
+        if (s.done) (void)hipEventDestroy(s.done);
+    if (B->copy_done) (void)hipEventDestroy(B->copy_done);
+    if (B->own_arena && B->arena) (void)hipFree(B->arena);
+    if (B->copy_stream) (void)hipStreamDestroy(B->copy_stream);
+    if (B->own_stream && B->stream) (void)hipStreamDestroy(B->stream);
+    delete B;
+}
+
+void push_header(MechBatch* B)
+{
+    hipLaunchKernelGGL(k_set_header, dim3(1), dim3(1), 0, B->stream, B->at<uint32_t>(B->L.hdr), B->n_cells,
+                       B->n_voxels);
+}
+
+void push_slot(MechBatch* B, int32_t id)
+{
+    hipLaunchKernelGGL(k_set_slot, dim3(1), dim3(1), 0, B->stream, B->at<SlotDesc>(B->L.slots), (uint32_t)id,
+                       B->slots[id].d);
+}
+
+int create_batch_impl(const MechParams* params, int64_t max_cells, int64_t max_voxels, int32_t max_slots,
+                      void* stream, void* workspace, int64_t ws_bytes, MechBatch** out)
 {
     if (!out) return fail(MECH_E_INVALID, "out is NULL");
     *out = nullptr;
-    int32_t dims[3];
-    int rc = validate(params, n, dims);
+    int rc = validate_physics(params);
     if (rc) return rc;
-    rc = validate_cells(params, n, pos, radius, type, vprev);
-    if (rc) return rc;
+    if (max_cells < 0 || max_cells >= (int64_t(1) << 31)) return fail(MECH_E_INVALID, "max_cells out of range");
+    if (max_voxels < 1 || max_voxels >= (int64_t(1) << 31)) return fail(MECH_E_INVALID, "max_voxels out of range");
+    if (max_slots < 1 || max_slots > 65536) return fail(MECH_E_INVALID, "max_slots out of range");
 
-    MechPopulation* P = new MechPopulation();
-    P->prm = *params;
-    P->n = n;
-    HIP_TRY(hipGetDevice(&P->device));
-    for (int a = 0; a < 3; ++a) P->dims[a] = dims[a];
-    P->V = (uint32_t)((uint64_t)dims[0] * dims[1] * dims[2]);
-    P->n_tiles = blocks_for(P->V, SCAN_TILE);
-    for (int a = 0; a < 3; ++a) {
-        P->grid.lo[a] = params->domain_lo[a];
-        P->grid.n[a] = dims[a];
-        P->phys.lo[a] = params->domain_lo[a];
-        P->phys.hi[a] = params->domain_hi[a];
-    }
-    P->grid.inv_h = 1.0 / params->voxel_size;
-    {
-        int cus = 0;
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, P->device) != hipSuccess || cus < 1)
-            cus = 256;
-        P->force_grid = (uint32_t)cus * 4u;  // a few resident workgroups per CU
-    }
-    P->grid.V = P->V;
-    P->phys.dt = params->dt;
-    P->phys.c_rep = params->c_rep;
-    P->phys.alpha = params->rel_adh_distance;
-    P->phys.c_adh0 = params->c_adh[0];
-    P->phys.c_rep_f = (float)params->c_rep;
-    P->phys.alpha_f = (float)params->rel_adh_distance;
-    P->phys.c_adh0_f = (float)params->c_adh[0];
-    {
-        double rmax = 0.0;
-        for (int64_t k = 0; k < n; ++k) rmax = std::max(rmax, radius[k]);
-        P->phys.r_max = rmax;
-        P->phys.r_max_f = (float)rmax;
-    }
-    P->phys.n_types = params->n_types;
-    P->phys.nx = dims[0];
-    P->phys.ny = dims[1];
-    P->phys.nz = dims[2];
-    P->L = make_layout(*params, n, P->V);
-    P->euler_pending = (params->ab2_start == MECH_AB2_EULER_START) && vprev == nullptr;
-
+    MechBatch* B = new MechBatch();
+    B->prm = *params;
+    B->cap_cells = max_cells;
+    B->cap_voxels = max_voxels;
+    B->cap_slots = max_slots;
+    B->slots.resize((size_t)max_slots);
+    B->phys.dt = params->dt;
+    B->phys.c_rep = params->c_rep;
+    B->phys.alpha = params->rel_adh_distance;
+    B->phys.c_adh0 = params->c_adh[0];
+    B->phys.c_rep_f = (float)params->c_rep;
+    B->phys.alpha_f = (float)params->rel_adh_distance;
+    B->phys.c_adh0_f = (float)params->c_adh[0];
+    B->phys.n_types = params->n_types;
+    B->L = make_layout(*params, max_cells, (uint64_t)max_voxels, max_slots);
     auto bail = [&](int code) {
-        release(P);
+        release(B);
         return code;
     };
-    if (stream) {
-        P->stream = (hipStream_t)stream;
-    } else {
-        if (hipStreamCreateWithFlags(&P->stream, hipStreamNonBlocking) != hipSuccess)
-            return bail(fail(MECH_E_DEVICE, "hipStreamCreate failed"));
-        P->own_stream = true;
+    if (hipGetDevice(&B->device) != hipSuccess) return bail(fail(MECH_E_DEVICE, "no HIP device"));
+    {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, B->device) != hipSuccess || cus < 1)
+            cus = 256;
+        B->force_grid = (uint32_t)cus * 4u;
     }
+    if (stream) {
+        B->stream = (hipStream_t)stream;
+    } else {
+        if (hipStreamCreateWithFlags(&B->stream, hipStreamNonBlocking) != hipSuccess)
+            return bail(fail(MECH_E_DEVICE, "hipStreamCreate failed"));
+        B->own_stream = true;
+    }
+    if (hipStreamCreateWithFlags(&B->copy_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&B->copy_done, hipEventDisableTiming) != hipSuccess)
+        return bail(fail(MECH_E_DEVICE, "stream or event creation failed"));
+    for (auto& s : B->slots)
+        if (hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess)
+            return bail(fail(MECH_E_DEVICE, "hipEventCreate failed"));
     if (workspace) {
-        if (ws_bytes < (int64_t)P->L.total)
-            return bail(fail(MECH_E_NOMEM, "workspace of %lld bytes < %zu needed", (long long)ws_bytes, P->L.total));
+        if (ws_bytes < (int64_t)B->L.total)
+            return bail(fail(MECH_E_NOMEM, "workspace of %lld bytes < %zu needed", (long long)ws_bytes, B->L.total));
         if (((uintptr_t)workspace & 255u) != 0)
             return bail(fail(MECH_E_INVALID, "workspace must be 256-byte aligned"));
-        P->arena = (char*)workspace;
+        B->arena = (char*)workspace;
     } else {
-        if (hipMalloc(&P->arena, P->L.total) != hipSuccess) {
-            P->arena = nullptr;
+        if (hipMalloc(&B->arena, B->L.total) != hipSuccess) {
+            B->arena = nullptr;
             (void)hipGetLastError();
-            return bail(fail(MECH_E_NOMEM, "hipMalloc of %zu bytes failed", P->L.total));
+            return bail(fail(MECH_E_NOMEM, "hipMalloc of %zu bytes failed", B->L.total));
         }
-        P->own_arena = true;
+        B->own_arena = true;
     }
-
-    // host-side staging: structure of arrays, v_prev in the variant's precision
-    const size_t nn = (size_t)n;
-    std::vector<double> soa(3 * nn);
-    std::vector<uint32_t> ids(nn);
-    std::vector<int32_t> tz;
-    for (size_t i = 0; i < nn; ++i) {
-        for (int c = 0; c < 3; ++c) soa[c * nn + i] = pos[3 * i + c];
-        ids[i] = (uint32_t)i;
-    }
-    const Layout& L = P->L;
-    hipStream_t s = P->stream;
-    int e = 0;
-    auto H2D = [&](size_t off, const void* src, size_t bytes) {
-        if (bytes && hipMemcpyAsync(P->arena + off, src, bytes, hipMemcpyHostToDevice, s) != hipSuccess) e = 1;
-    };
-    for (int c = 0; c < 3; ++c) H2D(L.X[c], soa.data() + c * nn, nn * 8);
-    H2D(L.R[0], radius, nn * 8);
-    if (type) {
-        H2D(L.T[0], type, nn * 4);
-    } else {
-        tz.assign(nn, 0);
-        H2D(L.T[0], tz.data(), nn * 4);
-    }
-    H2D(L.ID[0], ids.data(), nn * 4);
-    std::vector<double> vp64;
-    std::vector<float> vp32;
-    if (is_fp32(*params)) {
-        vp32.assign(3 * nn, 0.f);
-        if (vprev)
-            for (size_t i = 0; i < nn; ++i)
-                for (int c = 0; c < 3; ++c) vp32[c * nn + i] = (float)vprev[3 * i + c];
-        for (int c = 0; c < 3; ++c) H2D(L.VP[0][c], vp32.data() + c * nn, nn * 4);
-    } else {
-        vp64.assign(3 * nn, 0.0);
-        if (vprev)
-            for (size_t i = 0; i < nn; ++i)
-                for (int c = 0; c < 3; ++c) vp64[c * nn + i] = vprev[3 * i + c];
-        for (int c = 0; c < 3; ++c) H2D(L.VP[0][c], vp64.data() + c * nn, nn * 8);
-    }
+    const Layout& L = B->L;
     double cd[64];
     float cf[64];
     for (int k = 0; k < 64; ++k) {
         cd[k] = params->c_adh[k];
         cf[k] = (float)params->c_adh[k];
     }
-    H2D(L.cadh, cd, sizeof cd);
-    H2D(L.cadh_f, cf, sizeof cf);
-    if (e) return bail(fail(MECH_E_DEVICE, "host to device copy failed"));
-    if (hipMemsetAsync(P->arena + L.count, 0, (size_t)P->V * 4, s) != hipSuccess ||
-        hipMemsetAsync(P->arena + L.stats, 0, STAT_SLOTS * 16, s) != hipSuccess ||
-        hipMemsetAsync(P->arena + L.start, 0, ((size_t)P->V + 1) * 4, s) != hipSuccess ||
-        hipMemsetAsync(P->arena + L.n_occ, 0, 16, s) != hipSuccess)
-        return bail(fail(MECH_E_DEVICE, "hipMemsetAsync failed"));
-
-    // initial binning (parity 0 -> 1); positions in voxel order become the state
-    if (n > 0) {
-        P->parity = 0;
-        if (is_fp32(*params))
-            enqueue_binning<float>(P);
-        else
-            enqueue_binning<double>(P);
-        hipLaunchKernelGGL(k_copy_positions, dim3(blocks_for(n, BLOCK)), dim3(BLOCK), 0, s, (uint32_t)n,
-                           P->at<double>(L.XS[0]), P->at<double>(L.XS[1]), P->at<double>(L.XS[2]),
-                           P->at<double>(L.X[0]), P->at<double>(L.X[1]), P->at<double>(L.X[2]));
-        P->parity = 1;
-    }
-    rc = sync_check(P);
+    if (hipMemcpy(B->arena + L.cadh, cd, sizeof cd, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(B->arena + L.cadh_f, cf, sizeof cf, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemsetAsync(B->arena + L.count, 0, (size_t)max_voxels * 4, B->stream) != hipSuccess ||
+        hipMemsetAsync(B->arena + L.stats, 0, STAT_SLOTS * 16, B->stream) != hipSuccess ||
+        hipMemsetAsync(B->arena + L.start, 0, ((size_t)max_voxels + 1) * 4, B->stream) != hipSuccess ||
+        hipMemsetAsync(B->arena + L.hdr, 0, 16, B->stream) != hipSuccess ||
+        hipMemsetAsync(B->arena + L.slots, 0, (size_t)max_slots * sizeof(SlotDesc), B->stream) != hipSuccess)
+        return bail(fail(MECH_E_DEVICE, "arena initialisation failed"));
+    rc = sync_check(B);
     if (rc) return bail(rc);
-    *out = P;
+    *out = B;
     return MECH_OK;
+}
+
+// Compacts the live slots to the front of the arena (drops retired ones), in their
+// current order.  Runs on the batch stream; results are unchanged.
+int repack(MechBatch* B)
+{
+    const Layout& L = B->L;
+    const uint32_t n_old = B->n_cells;
+    std::vector<int32_t> keep;
+    uint32_t coff = 0, voff = 0;
+    for (int32_t id : B->order) {
+        HostSlot& s = B->slots[id];
+        if (s.retired) {
+            s.d.n_cells = 0;  // dropped by k_repack
+        } else {
+            s.d.prev_cell_off = s.d.cell_off;
+            s.d.cell_off = coff;
+            s.d.voxel_off = voff;
+            coff += s.d.n_cells;
+            voff += (uint32_t)s.d.nx * s.d.ny * s.d.nz;
+            keep.push_back(id);
+        }
+        push_slot(B, id);
+    }
+    if (n_old > 0) {
+        const int cur = B->parity, nxt = cur ^ 1;
+        auto launch = [&](auto vpt_tag) {
+            using VPT = decltype(vpt_tag);
+            RepackArgs<VPT> a{};
+            for (int c = 0; c < 3; ++c) {
+                a.X[c] = B->at<double>(L.X[c]);
+                a.XS[c] = B->at<double>(L.XS[c]);
+                a.VP_cur[c] = B->at<VPT>(L.VP[cur][c]);
+                a.VP_new[c] = B->at<VPT>(L.VP[nxt][c]);
+            }
+            a.R_cur = B->at<double>(L.R[cur]);
+            a.R_new = B->at<double>(L.R[nxt]);
+            a.T_cur = B->at<int32_t>(L.T[cur]);
+            a.T_new = B->at<int32_t>(L.T[nxt]);
+            a.ID_cur = B->at<uint32_t>(L.ID[cur]);
+            a.ID_new = B->at<uint32_t>(L.ID[nxt]);
+            a.slot_of = B->at<uint32_t>(L.slot_of);
+            a.slot_new = B->at<uint32_t>(L.tmp_src);
+            a.slots = B->at<SlotDesc>(L.slots);
+            hipLaunchKernelGGL(k_repack<VPT>, dim3(blocks_for(n_old, BLOCK)), dim3(BLOCK), 0, B->stream, n_old, a);
+        };
+        if (is_fp32(B->prm))
+            launch(float{});
+        else
+            launch(double{});
+        if (coff > 0) {
+            hipLaunchKernelGGL(k_copy_positions, dim3(blocks_for(coff, BLOCK)), dim3(BLOCK), 0, B->stream, coff,
+                               B->at<double>(L.XS[0]), B->at<double>(L.XS[1]), B->at<double>(L.XS[2]),
+                               B->at<double>(L.X[0]), B->at<double>(L.X[1]), B->at<double>(L.X[2]));
+            hipLaunchKernelGGL(k_copy_u32, dim3(blocks_for(coff, BLOCK)), dim3(BLOCK), 0, B->stream, coff,
+                               B->at<uint32_t>(L.tmp_src), B->at<uint32_t>(L.slot_of));
+        }
+        B->parity ^= 1;
+    }
+    for (int32_t id : B->order) {
+        HostSlot& s = B->slots[id];
+        if (s.retired) {
+            s = HostSlot{s.d, false, false, false, 0, s.done, false};
+            s.d = SlotDesc{};
+            push_slot(B, id);
+        }
+    }
+    B->order = keep;
+    B->n_cells = coff;
+    B->n_voxels = voff;
+    push_header(B);
+    HIP_TRY(hipGetLastError());
+    return MECH_OK;
+}
+
+int admit_impl(MechBatch* B, const double lo[3], const double hi[3], int64_t n, const double* pos,
+               const double* radius, const int32_t* type, const double* vprev, int64_t n_steps,
+               int32_t* slot_out)
+{
+    int32_t dims[3];
+    uint64_t V = 0;
+    int rc = validate_domain(lo, hi, B->prm.voxel_size, dims, &V);
+    if (rc) return rc;
+    double rmax = 0.0;
+    rc = validate_cells(&B->prm, lo, hi, n, pos, radius, type, vprev, &rmax);
+    if (rc) return rc;
+    int32_t id = -1;
+    for (int32_t k = 0; k < B->cap_slots; ++k)
+        if (!B->slots[k].used) {
+            id = k;
+            break;
+        }
+    if (id < 0) return fail(MECH_E_FULL, "all %d slots are in use", B->cap_slots);
+    if ((int64_t)B->n_cells + n > B->cap_cells || (int64_t)B->n_voxels + (int64_t)V > B->cap_voxels) {
+        int64_t live_c = 0, live_v = 0;
+        for (int32_t k : B->order)
+            if (!B->slots[k].retired) {
+                live_c += B->slots[k].d.n_cells;
+                live_v += (int64_t)B->slots[k].d.nx * B->slots[k].d.ny * B->slots[k].d.nz;
+            }
+        if (live_c + n > B->cap_cells || live_v + (int64_t)V > B->cap_voxels)
+            return fail(MECH_E_BUDGET, "request of %lld cells and %llu voxels does not fit (%lld/%lld cells, "
+                        "%lld/%lld voxels in use)", (long long)n, (unsigned long long)V, (long long)live_c,
+                        (long long)B->cap_cells, (long long)live_v, (long long)B->cap_voxels);
+        rc = repack(B);
+        if (rc) return rc;
+        // the compacted range may overlap cells that queued steps still write: the
+        // copies below must come after them
+        HIP_TRY(hipStreamSynchronize(B->stream));
+    }
+    HostSlot& s = B->slots[id];
+    SlotDesc& d = s.d;
+    d = SlotDesc{};
+    for (int a = 0; a < 3; ++a) {
+        d.lo[a] = lo[a];
+        d.hi[a] = hi[a];
+    }
+    d.inv_h = 1.0 / B->prm.voxel_size;
+    d.r_max = rmax;
+    d.r_max_f = (float)rmax;
+    d.nx = dims[0];
+    d.ny = dims[1];
+    d.nz = dims[2];
+    d.voxel_off = B->n_voxels;
+    d.cell_off = B->n_cells;
+    d.prev_cell_off = d.cell_off;
+    d.n_cells = (uint32_t)n;
+    d.steps_left = n_steps < 0 ? -1 : (int32_t)std::min<int64_t>(n_steps, INT32_MAX);
+    d.euler = (B->prm.ab2_start == MECH_AB2_EULER_START && vprev == nullptr) ? 1 : 0;
+    s.used = true;
+    s.retired = false;
+    s.reported = false;
+    s.steps_total = n_steps;
+    s.done_recorded = false;
+
+    // the cells go to [cell_off, cell_off + n) of the current parity, in id order; the
+    // copies run on the copy stream, so they overlap the steps already queued, which
+    // do not touch this range
+    const Layout& L = B->L;
+    const size_t nn = (size_t)n;
+    const size_t o = d.cell_off;
+    std::vector<double> soa(3 * nn);
+    std::vector<uint32_t> ids(nn), sl(nn, (uint32_t)id);
+    std::vector<int32_t> tz;
+    for (size_t i = 0; i < nn; ++i) {
+        for (int c = 0; c < 3; ++c) soa[c * nn + i] = pos[3 * i + c];
+        ids[i] = (uint32_t)(o + i);
+    }
+    const int p = B->parity;
+    hipStream_t cs = B->copy_stream;
+    int e = 0;
+    auto H2D = [&](size_t off, const void* src, size_t bytes) {
+        if (bytes && hipMemcpyAsync(B->arena + off, src, bytes, hipMemcpyHostToDevice, cs) != hipSuccess) e = 1;
+    };
+    for (int c = 0; c < 3; ++c) H2D(L.X[c] + o * 8, soa.data() + c * nn, nn * 8);
+    H2D(L.R[p] + o * 8, radius, nn * 8);
+    if (type) {
+        H2D(L.T[p] + o * 4, type, nn * 4);
+    } else {
+        tz.assign(nn, 0);
+        H2D(L.T[p] + o * 4, tz.data(), nn * 4);
+    }
+    H2D(L.ID[p] + o * 4, ids.data(), nn * 4);
+    H2D(L.slot_of + o * 4, sl.data(), nn * 4);
+    std::vector<double> vp64;
+    std::vector<float> vp32;
+    if (is_fp32(B->prm)) {
+        vp32.assign(3 * nn, 0.f);
+        if (vprev)
+            for (size_t i = 0; i < nn; ++i)
+                for (int c = 0; c < 3; ++c) vp32[c * nn + i] = (float)vprev[3 * i + c];
+        for (int c = 0; c < 3; ++c) H2D(L.VP[p][c] + o * 4, vp32.data() + c * nn, nn * 4);
+    } else {
+        vp64.assign(3 * nn, 0.0);
+        if (vprev)
+            for (size_t i = 0; i < nn; ++i)
+                for (int c = 0; c < 3; ++c) vp64[c * nn + i] = vprev[3 * i + c];
+        for (int c = 0; c < 3; ++c) H2D(L.VP[p][c] + o * 8, vp64.data() + c * nn, nn * 8);
+    }
+    if (e) return fail(MECH_E_DEVICE, "host to device copy failed");
+    // the host buffers above go out of scope: wait for the copy stream (only these copies)
+    HIP_TRY(hipStreamSynchronize(cs));
+    B->order.push_back(id);
+    B->n_cells += (uint32_t)n;
+    B->n_voxels += (uint32_t)V;
+    push_slot(B, id);
+    push_header(B);
+    if (d.steps_left == 0) {  // nothing to run: complete at once
+        HIP_TRY(hipEventRecord(s.done, B->stream));
+        s.done_recorded = true;
+    }
+    HIP_TRY(hipGetLastError());
+    if (slot_out) *slot_out = id;
+    return MECH_OK;
+}
+
+int step_impl(MechBatch* B, int64_t n_steps)
+{
+    if (n_steps < 0) return fail(MECH_E_INVALID, "n_steps must be >= 0");
+    HIP_TRY(hipSetDevice(B->device));
+    const bool eager = (B->prm.flags & MECH_FLAG_NO_GRAPH) != 0;
+    for (int64_t k = 0; k < n_steps; ++k) {
+        if (B->n_cells > 0) {
+            if (eager) {
+                enqueue_step(B, B->parity);
+            } else {
+                if (!B->graphs_ready) {
+                    int rc = build_graphs(B);
+                    if (rc) return rc;
+                }
+                HIP_TRY(hipGraphLaunch(B->gexec[B->parity], B->stream));
+            }
+            B->parity ^= 1;
+        } else {
+            enqueue_step_end(B);  // keeps the device step counters in line with the host's
+        }
+        HIP_TRY(hipGetLastError());
+        // host mirror of the device counters; mark the step at which a slot froze
+        for (int32_t id : B->order) {
+            HostSlot& s = B->slots[id];
+            s.d.euler = 0;
+            if (s.d.steps_left > 0 && --s.d.steps_left == 0 && !s.done_recorded) {
+                HIP_TRY(hipEventRecord(s.done, B->stream));
+                s.done_recorded = true;
+            }
+        }
+        ++B->steps;
+    }
+    return MECH_OK;
+}
+
+int read_slot(MechBatch* B, int32_t id, double* pos, double* vel, int64_t n_cells)
+{
+    if (id < 0 || id >= B->cap_slots || !B->slots[id].used || B->slots[id].retired)
+        return fail(MECH_E_INVALID, "slot %d holds no simulation", id);
+    const SlotDesc& d = B->slots[id].d;
+    if (!pos) return fail(MECH_E_INVALID, "pos is NULL");
+    if (n_cells != (int64_t)d.n_cells)
+        return fail(MECH_E_INVALID, "n_cells %lld != slot size %u", (long long)n_cells, d.n_cells);
+    HIP_TRY(hipSetDevice(B->device));
+    if (d.n_cells == 0) return MECH_OK;
+    const Layout& L = B->L;
+    const int p = B->parity;
+    const uint32_t n = d.n_cells;
+    double* st = B->at<double>(L.stage);
+    if (is_fp32(B->prm))
+        hipLaunchKernelGGL(k_unpermute<float>, dim3(blocks_for(n, BLOCK)), dim3(BLOCK), 0, B->stream, d.cell_off, n,
+                           B->at<uint32_t>(L.ID[p]), B->at<double>(L.X[0]), B->at<double>(L.X[1]),
+                           B->at<double>(L.X[2]), B->at<float>(L.VP[p][0]), B->at<float>(L.VP[p][1]),
+                           B->at<float>(L.VP[p][2]), st, st + 3 * (size_t)n);
+    else
+        hipLaunchKernelGGL(k_unpermute<double>, dim3(blocks_for(n, BLOCK)), dim3(BLOCK), 0, B->stream, d.cell_off, n,
+                           B->at<uint32_t>(L.ID[p]), B->at<double>(L.X[0]), B->at<double>(L.X[1]),
+                           B->at<double>(L.X[2]), B->at<double>(L.VP[p][0]), B->at<double>(L.VP[p][1]),
+                           B->at<double>(L.VP[p][2]), st, st + 3 * (size_t)n);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(pos, st, 24 * (size_t)n, hipMemcpyDeviceToHost, B->stream));
+    if (vel) HIP_TRY(hipMemcpyAsync(vel, st + 3 * (size_t)n, 24 * (size_t)n, hipMemcpyDeviceToHost, B->stream));
+    int rc = sync_check(B);
+    if (rc) return rc;
+    for (size_t i = 0; i < 3 * (size_t)n; ++i)
+        if (!std::isfinite(pos[i]) || (vel && !std::isfinite(vel[i])))
+            return fail(MECH_E_NONFINITE, "state holds a non-finite value at cell %zu", i / 3);
+    return MECH_OK;
+}
+
+int stats_impl(MechBatch* B, int64_t* steps, int64_t* interactions, int64_t* candidates)
+{
+    HIP_TRY(hipSetDevice(B->device));
+    int rc = sync_check(B);
+    if (rc) return rc;
+    std::vector<unsigned long long> slots(2 * STAT_SLOTS);
+    HIP_TRY(hipMemcpy(slots.data(), B->arena + B->L.stats, slots.size() * 8, hipMemcpyDeviceToHost));
+    unsigned long long st[2] = {0, 0};
+    for (uint32_t k = 0; k < STAT_SLOTS; ++k) {
+        st[0] += slots[2 * k];
+        st[1] += slots[2 * k + 1];
+    }
+    if (steps) *steps = B->steps;
+    if (interactions) *interactions = (int64_t)st[0];
+    if (candidates) *candidates = (int64_t)st[1];
+    return MECH_OK;
+}
+
+int profile_impl(MechBatch* B, int64_t n_steps, double* phase_ms)
+{
+    if (!phase_ms || n_steps < 1) return fail(MECH_E_INVALID, "need phase_ms and n_steps >= 1");
+    HIP_TRY(hipSetDevice(B->device));
+    phase_ms[0] = phase_ms[1] = 0.0;
+    if (B->n_cells == 0) return step_impl(B, n_steps);
+    hipEvent_t ev[3];
+    for (int k = 0; k < 3; ++k) HIP_TRY(hipEventCreate(&ev[k]));
+    double acc[2] = {0.0, 0.0};
+    int rc = MECH_OK;
+    for (int64_t s = 0; s < n_steps && rc == MECH_OK; ++s) {
+        const int p = B->parity;
+        (void)hipEventRecord(ev[0], B->stream);
+        enqueue_binning_any(B);
+        (void)hipEventRecord(ev[1], B->stream);
+        enqueue_force_any(B, p ^ 1);
+        (void)hipEventRecord(ev[2], B->stream);
+        enqueue_step_end(B);
+        B->parity ^= 1;
+        for (int32_t id : B->order) {
+            HostSlot& h = B->slots[id];
+            h.d.euler = 0;
+            if (h.d.steps_left > 0 && --h.d.steps_left == 0 && !h.done_recorded) {
+                (void)hipEventRecord(h.done, B->stream);
+                h.done_recorded = true;
+            }
+        }
+        ++B->steps;
+        rc = sync_check(B);
+        float t0 = 0.f, t1 = 0.f;
+        if (rc == MECH_OK && (hipEventElapsedTime(&t0, ev[0], ev[1]) != hipSuccess ||
+                              hipEventElapsedTime(&t1, ev[1], ev[2]) != hipSuccess))
+            rc = fail(MECH_E_DEVICE, "hipEventElapsedTime failed");
+        acc[0] += t0;
+        acc[1] += t1;
+    }
+    for (int k = 0; k < 3; ++k) (void)hipEventDestroy(ev[k]);
+    if (rc) return rc;
+    phase_ms[0] = acc[0] / (double)n_steps;
+    phase_ms[1] = acc[1] / (double)n_steps;
+    return MECH_OK;
+}
+
+int64_t batch_bytes(const MechParams* params, int64_t max_cells, int64_t max_voxels, int32_t max_slots)
+{
+    int rc = validate_physics(params);
+    if (rc) return rc;
+    if (max_cells < 0 || max_voxels < 1 || max_slots < 1) return fail(MECH_E_INVALID, "bad capacity");
+    return (int64_t)make_layout(*params, max_cells, (uint64_t)max_voxels, max_slots).total;
 }
 
 }  // namespace
@@ -1385,113 +1891,95 @@ int32_t mech_device_count(void)
     return c;
 }
 
+// ---- single population (a batch of one slot)
+
 int64_t population_workspace_bytes(const MechParams* params, int64_t n_cells)
 {
-    int32_t dims[3];
-    int rc = validate(params, n_cells, dims);
+    int rc = validate_physics(params);
     if (rc) return rc;
-    uint64_t V = (uint64_t)dims[0] * dims[1] * dims[2];
-    return (int64_t)make_layout(*params, n_cells, V).total;
+    if (n_cells < 0 || n_cells >= (int64_t(1) << 31)) return fail(MECH_E_INVALID, "n_cells out of range");
+    int32_t dims[3];
+    uint64_t V = 0;
+    rc = validate_domain(params->domain_lo, params->domain_hi, params->voxel_size, dims, &V);
+    if (rc) return rc;
+    return batch_bytes(params, n_cells, (int64_t)V, 1);
 }
 
-int create_population(const MechParams* params, int64_t n_cells, const double* pos,
-                      const double* radius, const int32_t* type, const double* prev_velocity,
-                      void* hip_stream, MechPopulation** out)
+static int create_pop_impl(const MechParams* params, int64_t n_cells, const double* pos, const double* radius,
+                           const int32_t* type, const double* prev_velocity, void* hip_stream, void* workspace,
+                           int64_t ws_bytes, MechPopulation** out)
 {
-    return create_impl(params, n_cells, pos, radius, type, prev_velocity, hip_stream, nullptr, 0, out);
+    if (!out) return fail(MECH_E_INVALID, "out is NULL");
+    *out = nullptr;
+    int rc = validate_physics(params);
+    if (rc) return rc;
+    int32_t dims[3];
+    uint64_t V = 0;
+    rc = validate_domain(params->domain_lo, params->domain_hi, params->voxel_size, dims, &V);
+    if (rc) return rc;
+    double rmax = 0.0;
+    rc = validate_cells(params, params->domain_lo, params->domain_hi, n_cells, pos, radius, type,
+                        prev_velocity, &rmax);
+    if (rc) return rc;
+    MechBatch* B = nullptr;
+    rc = create_batch_impl(params, n_cells, (int64_t)V, 1, hip_stream, workspace, ws_bytes, &B);
+    if (rc) return rc;
+    int32_t slot = -1;
+    rc = admit_impl(B, params->domain_lo, params->domain_hi, n_cells, pos, radius, type, prev_velocity, -1, &slot);
+    if (rc) {
+        release(B);
+        return rc;
+    }
+    // initial binning, so that read_binning describes the given positions
+    if (n_cells > 0) {
+        enqueue_binning_any(B);
+        const Layout& L = B->L;
+        hipLaunchKernelGGL(k_copy_positions, dim3(blocks_for(n_cells, BLOCK)), dim3(BLOCK), 0, B->stream,
+                           (uint32_t)n_cells, B->at<double>(L.XS[0]), B->at<double>(L.XS[1]),
+                           B->at<double>(L.XS[2]), B->at<double>(L.X[0]), B->at<double>(L.X[1]),
+                           B->at<double>(L.X[2]));
+        B->parity ^= 1;
+    }
+    rc = sync_check(B);
+    if (rc) {
+        release(B);
+        return rc;
+    }
+    MechPopulation* P = new MechPopulation();
+    P->b = B;
+    P->n = n_cells;
+    *out = P;
+    return MECH_OK;
 }
 
-int create_population_in(const MechParams* params, int64_t n_cells, const double* pos,
-                         const double* radius, const int32_t* type, const double* prev_velocity,
-                         void* hip_stream, void* workspace, int64_t workspace_bytes,
-                         MechPopulation** out)
+int create_population(const MechParams* params, int64_t n_cells, const double* pos, const double* radius,
+                      const int32_t* type, const double* prev_velocity, void* hip_stream, MechPopulation** out)
+{
+    return create_pop_impl(params, n_cells, pos, radius, type, prev_velocity, hip_stream, nullptr, 0, out);
+}
+
+int create_population_in(const MechParams* params, int64_t n_cells, const double* pos, const double* radius,
+                         const int32_t* type, const double* prev_velocity, void* hip_stream, void* workspace,
+                         int64_t workspace_bytes, MechPopulation** out)
 {
     if (!workspace) {
         if (out) *out = nullptr;
         return fail(MECH_E_INVALID, "workspace is NULL");
     }
-    return create_impl(params, n_cells, pos, radius, type, prev_velocity, hip_stream, workspace,
-                       workspace_bytes, out);
+    return create_pop_impl(params, n_cells, pos, radius, type, prev_velocity, hip_stream, workspace,
+                           workspace_bytes, out);
 }
 
 int step_mechanics(MechPopulation* P, int64_t n_steps)
 {
     if (!P) return fail(MECH_E_INVALID, "population is NULL");
-    if (n_steps < 0) return fail(MECH_E_INVALID, "n_steps must be >= 0");
-    HIP_TRY(hipSetDevice(P->device));
-    const bool eager = (P->prm.flags & MECH_FLAG_NO_GRAPH) != 0;
-    for (int64_t k = 0; k < n_steps; ++k) {
-        if (P->n > 0) {
-            if (P->euler_pending || eager) {
-                enqueue_step(P, P->parity, P->euler_pending ? 1 : 0);
-            } else {
-                if (!P->graphs_ready) {
-                    int rc = build_graphs(P);
-                    if (rc) return rc;
-                }
-                HIP_TRY(hipGraphLaunch(P->gexec[P->parity], P->stream));
-            }
-            HIP_TRY(hipGetLastError());
-            P->parity ^= 1;
-        }
-        P->euler_pending = false;
-        ++P->steps;
-    }
-    return MECH_OK;
+    return step_impl(P->b, n_steps);
 }
 
 int profile_step(MechPopulation* P, int64_t n_steps, double* phase_ms)
 {
     if (!P) return fail(MECH_E_INVALID, "population is NULL");
-    if (!phase_ms || n_steps < 1) return fail(MECH_E_INVALID, "need phase_ms and n_steps >= 1");
-    HIP_TRY(hipSetDevice(P->device));
-    phase_ms[0] = phase_ms[1] = 0.0;
-    if (P->n == 0) {
-        P->steps += n_steps;
-        return MECH_OK;
-    }
-    hipEvent_t ev[3];
-    for (int k = 0; k < 3; ++k) HIP_TRY(hipEventCreate(&ev[k]));
-    double acc[2] = {0.0, 0.0};
-    int rc = MECH_OK;
-    for (int64_t s = 0; s < n_steps && rc == MECH_OK; ++s) {
-        const int euler = P->euler_pending ? 1 : 0;
-        const int p = P->parity;
-        (void)hipEventRecord(ev[0], P->stream);
-        switch (P->prm.precision) {
-        case MECH_FP64:
-            enqueue_binning<double>(P);
-            (void)hipEventRecord(ev[1], P->stream);
-            enqueue_force<0, double>(P, p ^ 1, euler);
-            break;
-        case MECH_FP32:
-            enqueue_binning<float>(P);
-            (void)hipEventRecord(ev[1], P->stream);
-            enqueue_force<1, float>(P, p ^ 1, euler);
-            break;
-        default:
-            enqueue_binning<float>(P);
-            (void)hipEventRecord(ev[1], P->stream);
-            enqueue_force<2, float>(P, p ^ 1, euler);
-            break;
-        }
-        (void)hipEventRecord(ev[2], P->stream);
-        P->parity ^= 1;
-        P->euler_pending = false;
-        ++P->steps;
-        rc = sync_check(P);
-        float t0 = 0.f, t1 = 0.f;
-        if (rc == MECH_OK && (hipEventElapsedTime(&t0, ev[0], ev[1]) != hipSuccess ||
-                              hipEventElapsedTime(&t1, ev[1], ev[2]) != hipSuccess))
-            rc = fail(MECH_E_DEVICE, "hipEventElapsedTime failed");
-        acc[0] += t0;
-        acc[1] += t1;
-    }
-    for (int k = 0; k < 3; ++k) (void)hipEventDestroy(ev[k]);
-    if (rc) return rc;
-    phase_ms[0] = acc[0] / (double)n_steps;
-    phase_ms[1] = acc[1] / (double)n_steps;
-    return MECH_OK;
+    return profile_impl(P->b, n_steps, phase_ms);
 }
 
 int read_state(MechPopulation* P, double* pos, double* vel, int64_t n_cells)
@@ -1499,59 +1987,37 @@ int read_state(MechPopulation* P, double* pos, double* vel, int64_t n_cells)
     if (!P) return fail(MECH_E_INVALID, "population is NULL");
     if (!pos) return fail(MECH_E_INVALID, "pos is NULL");
     if (n_cells != P->n) return fail(MECH_E_INVALID, "n_cells %lld != population size %lld", (long long)n_cells, (long long)P->n);
-    HIP_TRY(hipSetDevice(P->device));
-    if (P->n == 0) return MECH_OK;
-    const Layout& L = P->L;
-    const int p = P->parity;
-    const uint32_t n = (uint32_t)P->n;
-    double* st = P->at<double>(L.stage);
-    if (is_fp32(P->prm))
-        hipLaunchKernelGGL(k_unpermute<float>, dim3(blocks_for(n, BLOCK)), dim3(BLOCK), 0, P->stream, n,
-                           P->at<uint32_t>(L.ID[p]), P->at<double>(L.X[0]), P->at<double>(L.X[1]),
-                           P->at<double>(L.X[2]), P->at<float>(L.VP[p][0]), P->at<float>(L.VP[p][1]),
-                           P->at<float>(L.VP[p][2]), st, st + 3 * (size_t)n);
-    else
-        hipLaunchKernelGGL(k_unpermute<double>, dim3(blocks_for(n, BLOCK)), dim3(BLOCK), 0, P->stream, n,
-                           P->at<uint32_t>(L.ID[p]), P->at<double>(L.X[0]), P->at<double>(L.X[1]),
-                           P->at<double>(L.X[2]), P->at<double>(L.VP[p][0]), P->at<double>(L.VP[p][1]),
-                           P->at<double>(L.VP[p][2]), st, st + 3 * (size_t)n);
-    HIP_TRY(hipGetLastError());
-    HIP_TRY(hipMemcpyAsync(pos, st, 24 * (size_t)n, hipMemcpyDeviceToHost, P->stream));
-    if (vel) HIP_TRY(hipMemcpyAsync(vel, st + 3 * (size_t)n, 24 * (size_t)n, hipMemcpyDeviceToHost, P->stream));
-    int rc = sync_check(P);
-    if (rc) return rc;
-    for (size_t i = 0; i < 3 * (size_t)n; ++i)
-        if (!std::isfinite(pos[i]) || (vel && !std::isfinite(vel[i])))
-            return fail(MECH_E_NONFINITE, "state holds a non-finite value at cell %zu", i / 3);
-    return MECH_OK;
+    return read_slot(P->b, 0, pos, vel, n_cells);
 }
 
-int read_binning(MechPopulation* P, uint32_t* voxel_of_cell, uint32_t* voxel_start,
-                 uint32_t* sorted_ids, uint32_t* occ, int64_t* n_occ, int64_t* n_voxels)
+int read_binning(MechPopulation* P, uint32_t* voxel_of_cell, uint32_t* voxel_start, uint32_t* sorted_ids,
+                 uint32_t* occ, int64_t* n_occ, int64_t* n_voxels)
 {
     if (!P) return fail(MECH_E_INVALID, "population is NULL");
-    HIP_TRY(hipSetDevice(P->device));
-    int rc = sync_check(P);
+    MechBatch* B = P->b;
+    HIP_TRY(hipSetDevice(B->device));
+    int rc = sync_check(B);
     if (rc) return rc;
-    const Layout& L = P->L;
+    const Layout& L = B->L;
     const size_t n = (size_t)P->n;
-    if (n_voxels) *n_voxels = P->V;
+    const size_t V = (size_t)B->n_voxels;
+    if (n_voxels) *n_voxels = (int64_t)V;
     uint32_t m = 0;
-    if (n > 0) HIP_TRY(hipMemcpy(&m, P->arena + L.n_occ, 4, hipMemcpyDeviceToHost));
+    if (n > 0) HIP_TRY(hipMemcpy(&m, B->arena + L.hdr + 4 * H_OCC, 4, hipMemcpyDeviceToHost));
     if (n_occ) *n_occ = m;
     if (voxel_start) {
         if (n > 0)
-            HIP_TRY(hipMemcpy(voxel_start, P->arena + L.start, ((size_t)P->V + 1) * 4, hipMemcpyDeviceToHost));
+            HIP_TRY(hipMemcpy(voxel_start, B->arena + L.start, (V + 1) * 4, hipMemcpyDeviceToHost));
         else
-            std::memset(voxel_start, 0, ((size_t)P->V + 1) * 4);
+            std::memset(voxel_start, 0, (V + 1) * 4);
     }
-    if (occ && m) HIP_TRY(hipMemcpy(occ, P->arena + L.occ, (size_t)m * 4, hipMemcpyDeviceToHost));
+    if (occ && m) HIP_TRY(hipMemcpy(occ, B->arena + L.occ, (size_t)m * 4, hipMemcpyDeviceToHost));
     if (n == 0) return MECH_OK;
     std::vector<uint32_t> ids(n), vs(n);
-    HIP_TRY(hipMemcpy(ids.data(), P->arena + L.ID[P->parity], n * 4, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(ids.data(), B->arena + L.ID[B->parity], n * 4, hipMemcpyDeviceToHost));
     if (sorted_ids) std::memcpy(sorted_ids, ids.data(), n * 4);
     if (voxel_of_cell) {
-        HIP_TRY(hipMemcpy(vs.data(), P->arena + L.vid_sorted, n * 4, hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(vs.data(), B->arena + L.vid_sorted, n * 4, hipMemcpyDeviceToHost));
         for (size_t s = 0; s < n; ++s) voxel_of_cell[ids[s]] = vs[s];
     }
     return MECH_OK;
@@ -1560,39 +2026,196 @@ int read_binning(MechPopulation* P, uint32_t* voxel_of_cell, uint32_t* voxel_sta
 int read_stats(MechPopulation* P, int64_t* steps, int64_t* interactions, int64_t* candidates)
 {
     if (!P) return fail(MECH_E_INVALID, "population is NULL");
-    HIP_TRY(hipSetDevice(P->device));
-    int rc = sync_check(P);
-    if (rc) return rc;
-    std::vector<unsigned long long> slots(2 * STAT_SLOTS);
-    HIP_TRY(hipMemcpy(slots.data(), P->arena + P->L.stats, slots.size() * 8, hipMemcpyDeviceToHost));
-    unsigned long long st[2] = {0, 0};
-    for (uint32_t k = 0; k < STAT_SLOTS; ++k) {
-        st[0] += slots[2 * k];
-        st[1] += slots[2 * k + 1];
-    }
-    if (steps) *steps = P->steps;
-    if (interactions) *interactions = (int64_t)st[0];
-    if (candidates) *candidates = (int64_t)st[1];
-    return MECH_OK;
+    return stats_impl(P->b, steps, interactions, candidates);
 }
 
 int population_info(MechPopulation* P, int64_t* n_cells, int32_t dims[3])
 {
     if (!P) return fail(MECH_E_INVALID, "population is NULL");
     if (n_cells) *n_cells = P->n;
-    if (dims)
-        for (int a = 0; a < 3; ++a) dims[a] = P->dims[a];
+    if (dims) {
+        const SlotDesc& d = P->b->slots[0].d;
+        dims[0] = d.nx;
+        dims[1] = d.ny;
+        dims[2] = d.nz;
+    }
     return MECH_OK;
 }
 
-void* population_stream(MechPopulation* P) { return P ? (void*)P->stream : nullptr; }
+void* population_stream(MechPopulation* P) { return P ? (void*)P->b->stream : nullptr; }
 
 int destroy_population(MechPopulation* P)
 {
     if (!P) return MECH_OK;
-    (void)hipSetDevice(P->device);
-    hipError_t e = P->stream ? hipStreamSynchronize(P->stream) : hipSuccess;
-    release(P);
+    MechBatch* B = P->b;
+    (void)hipSetDevice(B->device);
+    hipError_t e = B->stream ? hipStreamSynchronize(B->stream) : hipSuccess;
+    release(B);
+    delete P;
+    if (e != hipSuccess) return fail(MECH_E_DEVICE, "stream error at destroy: %s", hipGetErrorString(e));
+    return MECH_OK;
+}
+
+// ---- batches of independent simulations
+
+int64_t batch_workspace_bytes(const MechParams* params, int64_t max_cells, int64_t max_voxels, int32_t max_slots)
+{
+    return batch_bytes(params, max_cells, max_voxels, max_slots);
+}
+
+int64_t batch_request_voxels(const MechParams* params, const double domain_lo[3], const double domain_hi[3])
+{
+    int rc = validate_physics(params);
+    if (rc) return rc;
+    int32_t dims[3];
+    uint64_t V = 0;
+    rc = validate_domain(domain_lo, domain_hi, params->voxel_size, dims, &V);
+    if (rc) return rc;
+    return (int64_t)V;
+}
+
+int create_batch(const MechParams* params, int64_t max_cells, int64_t max_voxels, int32_t max_slots,
+                 void* hip_stream, MechBatch** out)
+{
+    return create_batch_impl(params, max_cells, max_voxels, max_slots, hip_stream, nullptr, 0, out);
+}
+
+int create_batch_in(const MechParams* params, int64_t max_cells, int64_t max_voxels, int32_t max_slots,
+                    void* hip_stream, void* workspace, int64_t workspace_bytes, MechBatch** out)
+{
+    if (!workspace) {
+        if (out) *out = nullptr;
+        return fail(MECH_E_INVALID, "workspace is NULL");
+    }
+    return create_batch_impl(params, max_cells, max_voxels, max_slots, hip_stream, workspace, workspace_bytes, out);
+}
+
+int batch_admit(MechBatch* B, const double domain_lo[3], const double domain_hi[3], int64_t n_cells,
+                const double* pos, const double* radius, const int32_t* type, const double* prev_velocity,
+                int64_t n_steps, int32_t* slot_out)
+{
+    if (!B) return fail(MECH_E_INVALID, "batch is NULL");
+    if (!domain_lo || !domain_hi) return fail(MECH_E_INVALID, "domain is NULL");
+    HIP_TRY(hipSetDevice(B->device));
+    return admit_impl(B, domain_lo, domain_hi, n_cells, pos, radius, type, prev_velocity, n_steps, slot_out);
+}
+
+int batch_step(MechBatch* B, int64_t n_steps)
+{
+    if (!B) return fail(MECH_E_INVALID, "batch is NULL");
+    return step_impl(B, n_steps);
+}
+
+int batch_poll(MechBatch* B, int32_t* done_slots, int32_t capacity, int32_t* n_done)
+{
+    if (!B || !n_done) return fail(MECH_E_INVALID, "batch or n_done is NULL");
+    int32_t k = 0;
+    for (int32_t id : B->order) {
+        HostSlot& s = B->slots[id];
+        if (s.retired || s.reported || !s.done_recorded) continue;
+        hipError_t q = hipEventQuery(s.done);
+        if (q == hipErrorNotReady) continue;
+        if (q != hipSuccess) return fail(MECH_E_DEVICE, "hipEventQuery failed: %s", hipGetErrorString(q));
+        if (k < capacity && done_slots) done_slots[k] = id;
+        ++k;
+        s.reported = true;
+    }
+    *n_done = k;
+    return MECH_OK;
+}
+
+int batch_read(MechBatch* B, int32_t slot, double* pos, double* vel, int64_t n_cells)
+{
+    if (!B) return fail(MECH_E_INVALID, "batch is NULL");
+    return read_slot(B, slot, pos, vel, n_cells);
+}
+
+int batch_retire(MechBatch* B, int32_t slot)
+{
+    if (!B) return fail(MECH_E_INVALID, "batch is NULL");
+    if (slot < 0 || slot >= B->cap_slots || !B->slots[slot].used || B->slots[slot].retired)
+        return fail(MECH_E_INVALID, "slot %d holds no simulation", slot);
+    HIP_TRY(hipSetDevice(B->device));
+    HostSlot& s = B->slots[slot];
+    s.retired = true;
+    s.d.steps_left = 0;  // frozen until the next repack drops it
+    push_slot(B, slot);
+    HIP_TRY(hipGetLastError());
+    return MECH_OK;
+}
+
+int batch_slot_info(MechBatch* B, int32_t slot, int64_t* n_cells, int64_t* steps_left)
+{
+    if (!B) return fail(MECH_E_INVALID, "batch is NULL");
+    if (slot < 0 || slot >= B->cap_slots || !B->slots[slot].used || B->slots[slot].retired)
+        return fail(MECH_E_INVALID, "slot %d holds no simulation", slot);
+    if (n_cells) *n_cells = B->slots[slot].d.n_cells;
+    if (steps_left) *steps_left = B->slots[slot].d.steps_left;
+    return MECH_OK;
+}
+
+int batch_info(MechBatch* B, int64_t* n_cells, int64_t* n_voxels, int32_t* n_live, int64_t* free_cells,
+               int64_t* free_voxels)
+{
+    if (!B) return fail(MECH_E_INVALID, "batch is NULL");
+    int64_t lc = 0, lv = 0;
+    int32_t nl = 0;
+    for (int32_t id : B->order)
+        if (!B->slots[id].retired) {
+            const SlotDesc& d = B->slots[id].d;
+            lc += d.n_cells;
+            lv += (int64_t)d.nx * d.ny * d.nz;
+            ++nl;
+        }
+    if (n_cells) *n_cells = B->n_cells;
+    if (n_voxels) *n_voxels = B->n_voxels;
+    if (n_live) *n_live = nl;
+    if (free_cells) *free_cells = B->cap_cells - lc;
+    if (free_voxels) *free_voxels = B->cap_voxels - lv;
+    return MECH_OK;
+}
+
+int batch_stats(MechBatch* B, int64_t* steps, int64_t* interactions, int64_t* candidates)
+{
+    if (!B) return fail(MECH_E_INVALID, "batch is NULL");
+    return stats_impl(B, steps, interactions, candidates);
+}
+
+int batch_profile(MechBatch* B, int64_t n_steps, double* phase_ms)
+{
+    if (!B) return fail(MECH_E_INVALID, "batch is NULL");
+    return profile_impl(B, n_steps, phase_ms);
+}
+
+int batch_set_flags(MechBatch* B, int32_t flags)
+{
+    if (!B) return fail(MECH_E_INVALID, "batch is NULL");
+    MechParams p = B->prm;
+    p.flags = flags;
+    int rc = validate_physics(&p);
+    if (rc) return rc;
+    HIP_TRY(hipSetDevice(B->device));
+    HIP_TRY(hipStreamSynchronize(B->stream));
+    drop_graphs(B);
+    B->prm.flags = flags;
+    return MECH_OK;
+}
+
+int batch_sync(MechBatch* B)
+{
+    if (!B) return fail(MECH_E_INVALID, "batch is NULL");
+    HIP_TRY(hipSetDevice(B->device));
+    return sync_check(B);
+}
+
+void* batch_stream(MechBatch* B) { return B ? (void*)B->stream : nullptr; }
+
+int destroy_batch(MechBatch* B)
+{
+    if (!B) return MECH_OK;
+    (void)hipSetDevice(B->device);
+    hipError_t e = B->stream ? hipStreamSynchronize(B->stream) : hipSuccess;
+    release(B);
     if (e != hipSuccess) return fail(MECH_E_DEVICE, "stream error at destroy: %s", hipGetErrorString(e));
     return MECH_OK;
 }

@@ -1,0 +1,202 @@
+"""Continuous-batching server for simulation requests on one GPU.
+
+Requests (a population and a step count each) arrive over time.  The server keeps one
+batch (see include/mech.h) whose arena is sized from an HBM budget: a request is
+admitted as soon as it has arrived and its cells and voxels fit in the space the
+running simulations leave free (first come, first served); it then runs inside the same
+step launches as every other admitted request, its state stays on the device, and it
+is read back and retired when its last step completes.  Requests that do not fit wait
+in the queue until earlier ones finish.  Each request's result is bitwise the one it
+would get alone.
+
+The loop enqueues a chunk of steps, admits arrivals and reads finished requests while
+that chunk runs (admission copies go on a second stream), then waits for the chunk.
+Latency is completion minus arrival, with completion taken when the step that finished
+the request is seen complete.
+
+  python -m paper_2306_11544_amd.serve --requests 400 --rate 50 --budget-gb 200
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import json
+import sys
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import binding as B
+
+
+@dataclass
+class Done:
+    rid: int
+    n: int
+    steps: int
+    arrival_s: float
+    admit_s: float
+    done_s: float
+    pos: np.ndarray | None = None
+    vel: np.ndarray | None = None
+
+    @property
+    def latency_s(self) -> float:
+        return self.done_s - self.arrival_s
+
+
+def capacity_for_budget(params: B.MechParams, budget_bytes: int, voxels_per_cell: float,
+                        max_slots: int):
+    """Largest (cells, voxels) arena, voxels = voxels_per_cell * cells, within the budget."""
+    base = B.batch_workspace_bytes(params, 0, 1, max_slots)
+    per = (B.batch_workspace_bytes(params, 1 << 20, int((1 << 20) * voxels_per_cell) + 1,
+                                   max_slots) - base) / float(1 << 20)
+    cells = int(max(0, budget_bytes - base - (1 << 20)) / per)
+    cells = min(cells, (1 << 31) - 1)
+    voxels = min(int(cells * voxels_per_cell) + 1, (1 << 31) - 2)
+    while cells > 0 and B.batch_workspace_bytes(params, cells, voxels, max_slots) > budget_bytes:
+        cells = int(cells * 0.99)
+        voxels = int(cells * voxels_per_cell) + 1
+    return cells, voxels
+
+
+@dataclass
+class Server:
+    params: B.MechParams
+    budget_bytes: int
+    max_slots: int = 1024
+    voxels_per_cell: float = 1.6
+    steps_per_chunk: int = 10
+    stats: dict = field(default_factory=dict)
+
+    def __post_init__(self):
+        self.cap_cells, self.cap_voxels = capacity_for_budget(
+            self.params, self.budget_bytes, self.voxels_per_cell, self.max_slots)
+        if self.cap_cells < 1:
+            raise ValueError("HBM budget too small for any request")
+        self.batch = B.Batch(self.params, self.cap_cells, self.cap_voxels, self.max_slots)
+        self.arena_bytes = B.batch_workspace_bytes(self.params, self.cap_cells, self.cap_voxels,
+                                                   self.max_slots)
+
+    def close(self):
+        self.batch.close()
+
+    def run(self, requests, make_population, keep_results=False, log=None):
+        """Serve `requests` (objects with rid, arrival_s, n, steps) in real time.
+
+        make_population(request) builds its workloads.Population.  Returns the list of
+        Done records in completion order."""
+        bt = self.batch
+        pending = collections.deque(sorted(requests, key=lambda r: r.arrival_s))
+        queue = collections.deque()
+        running = {}   # slot -> (request, population size, admit time)
+        done = []
+        cell_steps = 0
+        max_live = 0
+        max_queue = 0
+        busy_chunks = 0
+        t0 = time.perf_counter()
+
+        def now():
+            return time.perf_counter() - t0
+
+        while pending or queue or running:
+            t = now()
+            while pending and pending[0].arrival_s <= t:
+                r = pending.popleft()
+                queue.append((r, make_population(r)))
+            max_queue = max(max_queue, len(queue))
+            # enqueue a chunk of steps for the admitted requests
+            if running:
+                k = min(self.steps_per_chunk,
+                        min(bt.slot_info(s)[1] for s in running))
+                bt.step(max(k, 1))
+                busy_chunks += 1
+            # admit while the chunk runs: first come, first served
+            while queue:
+                r, pop = queue[0]
+                try:
+                    slot = bt.admit_pop(pop, n_steps=r.steps)
+                except B.MechError as e:
+                    if e.code in (B.MECH_E_BUDGET, B.MECH_E_FULL):
+                        break
+                    raise
+                queue.popleft()
+                running[slot] = (r, pop.n, now())
+            max_live = max(max_live, len(running))
+            B.batch_sync(bt)
+            for slot in bt.poll():
+                r, n, t_admit = running.pop(slot)
+                t_done = now()
+                pos = vel = None
+                if keep_results:
+                    pos, vel = bt.read(slot)
+                bt.retire(slot)
+                cell_steps += n * r.steps
+                done.append(Done(r.rid, n, r.steps, r.arrival_s, t_admit, t_done, pos, vel))
+                if log:
+                    log(f"done rid={r.rid} n={n} steps={r.steps} latency={t_done - r.arrival_s:.3f}s")
+            if not running and not queue and pending:
+                time.sleep(max(0.0, min(0.01, pending[0].arrival_s - now())))
+        makespan = now()
+        lat = np.array([d.latency_s for d in done]) if done else np.zeros(1)
+        self.stats = {
+            "requests": len(done),
+            "makespan_s": makespan,
+            "cell_steps": cell_steps,
+            "cell_steps_per_s": cell_steps / makespan if makespan > 0 else 0.0,
+            "latency_p50_s": float(np.percentile(lat, 50)),
+            "latency_p99_s": float(np.percentile(lat, 99)),
+            "latency_mean_s": float(lat.mean()),
+            "max_live_slots": max_live,
+            "max_queue": max_queue,
+            "chunks": busy_chunks,
+            "arena_bytes": self.arena_bytes,
+            "cap_cells": self.cap_cells,
+            "cap_voxels": self.cap_voxels,
+        }
+        return done
+
+
+def main(argv=None):
+    import os
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import workloads
+
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--requests", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=20, help="requests excluded from the statistics")
+    ap.add_argument("--rate", type=float, default=50.0)
+    ap.add_argument("--budget-gb", type=float, default=200.0)
+    ap.add_argument("--precision", default="fp32")
+    ap.add_argument("--chunk", type=int, default=10)
+    ap.add_argument("--max-slots", type=int, default=1024)
+    args = ap.parse_args(argv)
+    reqs = workloads.request_stream(args.requests, args.rate)
+    params = B.make_params((0, 0, 0), (1, 1, 1), c_adh=workloads.C_ADH_2,
+                           precision=B.PRECISIONS[args.precision])
+    srv = Server(params, int(args.budget_gb * (1 << 30)), args.max_slots,
+                 steps_per_chunk=args.chunk)
+    # populations are drawn before the clock starts
+    pops = {r.rid: workloads.request_population(r) for r in reqs}
+    done = srv.run(reqs, lambda r: pops[r.rid])
+    srv.close()
+    measured = [d for d in done if d.rid >= args.warmup]
+    lat = np.array([d.latency_s for d in measured])
+    offered = sum(r.n * r.steps for r in reqs) / max(r.arrival_s for r in reqs)
+    out = dict(srv.stats)
+    out.update({
+        "measured_requests": len(measured),
+        "latency_p50_s": float(np.percentile(lat, 50)),
+        "latency_p99_s": float(np.percentile(lat, 99)),
+        "offered_cell_steps_per_s": offered,
+        "rate_req_per_s": args.rate,
+        "budget_gb": args.budget_gb,
+        "precision": args.precision,
+    })
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

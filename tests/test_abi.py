@@ -127,3 +127,23 @@ def test_null_handles_are_rejected():
     assert lib.read_stats(None, None, None, None) == B.MECH_E_INVALID
     assert lib.destroy_population(None) == B.MECH_OK
     assert lib.population_stream(None) is None
+
+
+def test_batch_capacity_validation():
+    p = B.make_params((0, 0, 0), (1, 1, 1))
+    assert B.batch_workspace_bytes(p, 1000, 500, 4) > B.batch_workspace_bytes(p, 100, 500, 4)
+    for args in ((-1, 10, 1), (10, 0, 1), (10, 10, 0)):
+        with pytest.raises(B.MechError):
+            B.batch_workspace_bytes(p, *args)
+    # voxels a request needs: ceil per axis, at least one
+    assert B.batch_request_voxels(p, (-100, -100, -100), (100, 100, 100)) == 7 ** 3
+    assert B.batch_request_voxels(p, (0, 0, 0), (90, 90, 0)) == 9
+    with pytest.raises(B.MechError):
+        B.batch_request_voxels(p, (0, 0, 0), (-1, 1, 1))
+
+
+def test_population_workspace_is_a_one_slot_batch():
+    pop = workloads.plain(1000)
+    p = B.params_of(pop)
+    v = B.batch_request_voxels(p, pop.lo, pop.hi)
+    assert B.population_workspace_bytes(p, pop.n) == B.batch_workspace_bytes(p, pop.n, v, 1)
