@@ -49,6 +49,31 @@ FORCE_BYTES_PER_CELL = {"fp64": 24 + 32 + 4 + 48 + 24, "fp32": 24 + 32 + 4 + 24 
                         "fp32k": 24 + 32 + 4 + 24 + 24}
 
 
+def measured_traffic(kernel: str, workload: str, precision: str):
+    """HBM bytes per launch of `kernel` from its committed counter summary, or None when
+    there is none or the kernel source has changed since the counters were taken."""
+    from paper_2306_11544_amd import rocprof_summary as RS
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}_{precision}.txt")
+    if not os.path.exists(path):
+        return None
+    b, sha, _ = RS.read_traffic(path)
+    return b if sha == RS.source_sha256() else None
+
+
+def copy_calibration(mb: int, stream):
+    """A streaming kernel of known traffic (y = -x over mb MiB of float32: reads and
+    writes mb MiB) for scaling the HBM counters of a profiled run."""
+    import torch
+    n = (mb << 20) // 4
+    with torch.cuda.stream(stream):
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    log(f"copy calibration: 3 x neg over {n * 4} bytes")
+
+
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
@@ -151,6 +176,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sims", type=int, default=256, help="batch workload: simulations")
     ap.add_argument("--force", default="cells", help="force kernel: cells | rows | voxel")
+    ap.add_argument("--calibrate-copy-mb", type=int, default=0,
+                    help="after the run, a streaming copy of this size for counter scaling")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -227,6 +254,10 @@ def main():
     log(f"phases: binning+reorder {bin_ms:.4f} ms, force+update {force_ms:.4f} ms; "
         f"{achieved_tflops:.2f} TFLOP/s, {force_gbs:.1f} GB/s algorithmic")
     P.close()
+    if args.calibrate_copy_mb:
+        copy_calibration(args.calibrate_copy_mb, stream)
+    kname = f"k_force_{args.force}"
+    traffic = measured_traffic(kname, pop.name, precision)
 
     out = {
         "metric": METRIC,
@@ -249,9 +280,11 @@ def main():
         "step_latency_ms": {"p50": float(np.percentile(lat, 50)),
                             "p99": float(np.percentile(lat, 99))},
         "phase_ms": {"binning_reorder": bin_ms, "force_update": force_ms},
-        "roofline": {"bound": "alu", "kernel": f"k_force_{args.force}", "achieved": achieved_tflops,
+        "roofline": {"bound": "alu", "kernel": kname, "achieved": achieved_tflops,
                      "peak": peak, "unit": "TFLOP/s", "frac": achieved_tflops / peak,
-                     "traffic": None,
+                     "traffic": traffic,
+                     "traffic_GBs": None if traffic is None else traffic / (force_ms * 1e-3) / 1e9,
+                     "force_ms_per_launch": force_ms,
                      "hbm_algorithmic_GBs": force_gbs,
                      "hbm_frac": force_gbs / PEAK_HBM_GBS},
     }

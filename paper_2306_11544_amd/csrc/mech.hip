@@ -1622,30 +1622,37 @@ int admit_impl(MechBatch* B, const double lo[3], const double hi[3], int64_t n, 
     double rmax = 0.0;
     rc = validate_cells(&B->prm, lo, hi, n, pos, radius, type, vprev, &rmax);
     if (rc) return rc;
-    int32_t id = -1;
-    for (int32_t k = 0; k < B->cap_slots; ++k)
-        if (!B->slots[k].used) {
-            id = k;
-            break;
+    auto free_id = [&]() {
+        for (int32_t k = 0; k < B->cap_slots; ++k)
+            if (!B->slots[k].used) return k;
+        return -1;
+    };
+    int64_t live_c = 0, live_v = 0;
+    bool any_retired = false;
+    for (int32_t k : B->order) {
+        if (B->slots[k].retired) {
+            any_retired = true;
+        } else {
+            live_c += B->slots[k].d.n_cells;
+            live_v += (int64_t)B->slots[k].d.nx * B->slots[k].d.ny * B->slots[k].d.nz;
         }
-    if (id < 0) return fail(MECH_E_FULL, "all %d slots are in use", B->cap_slots);
-    if ((int64_t)B->n_cells + n > B->cap_cells || (int64_t)B->n_voxels + (int64_t)V > B->cap_voxels) {
-        int64_t live_c = 0, live_v = 0;
-        for (int32_t k : B->order)
-            if (!B->slots[k].retired) {
-                live_c += B->slots[k].d.n_cells;
-                live_v += (int64_t)B->slots[k].d.nx * B->slots[k].d.ny * B->slots[k].d.nz;
-            }
-        if (live_c + n > B->cap_cells || live_v + (int64_t)V > B->cap_voxels)
-            return fail(MECH_E_BUDGET, "request of %lld cells and %llu voxels does not fit (%lld/%lld cells, "
-                        "%lld/%lld voxels in use)", (long long)n, (unsigned long long)V, (long long)live_c,
-                        (long long)B->cap_cells, (long long)live_v, (long long)B->cap_voxels);
+    }
+    if (free_id() < 0 && !any_retired) return fail(MECH_E_FULL, "all %d slots are in use", B->cap_slots);
+    if (live_c + n > B->cap_cells || live_v + (int64_t)V > B->cap_voxels)
+        return fail(MECH_E_BUDGET, "request of %lld cells and %llu voxels does not fit (%lld/%lld cells, "
+                    "%lld/%lld voxels in use)", (long long)n, (unsigned long long)V, (long long)live_c,
+                    (long long)B->cap_cells, (long long)live_v, (long long)B->cap_voxels);
+    // retired slots hold their id and space until a compaction drops them
+    if (free_id() < 0 || (int64_t)B->n_cells + n > B->cap_cells ||
+        (int64_t)B->n_voxels + (int64_t)V > B->cap_voxels) {
         rc = repack(B);
         if (rc) return rc;
         // the compacted range may overlap cells that queued steps still write: the
         // copies below must come after them
         HIP_TRY(hipStreamSynchronize(B->stream));
     }
+    const int32_t id = free_id();
+    if (id < 0) return fail(MECH_E_FULL, "all %d slots are in use", B->cap_slots);
     HostSlot& s = B->slots[id];
     SlotDesc& d = s.d;
     d = SlotDesc{};

@@ -1,0 +1,141 @@
+"""Short text summaries of rocprofv3 CSV output (kernel statistics, HBM counters).
+
+  python -m paper_2306_11544_amd.rocprof_summary stats <..._kernel_stats.csv> --command "<cmd>"
+  python -m paper_2306_11544_amd.rocprof_summary traffic --fetch <fetch counter_collection.csv>
+      --write <write counter_collection.csv> --kernel k_force_cells --copy-kernel neg_kernel
+      --copy-bytes <bytes read = bytes written by the copy> --command-fetch "<cmd>" --command-write "<cmd>"
+
+`traffic` scales the per-dispatch FETCH_SIZE and WRITE_SIZE (KiB) of a kernel by what the
+same counters read for a streaming copy of known size, and records the SHA-256 of the
+kernel source so a reader can tell whether the figure still describes the current code.
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import hashlib
+import os
+import sys
+
+SOURCE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "mech.hip")
+
+
+def source_sha256() -> str:
+    with open(SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def _short(name: str) -> str:
+    """Kernel name without return type and template arguments' noise."""
+    s = name
+    if s.startswith("void "):
+        s = s[5:]
+    return s if len(s) <= 110 else s[:107] + "..."
+
+
+def stats(path: str, command: str, top: int = 25) -> str:
+    rows = list(csv.DictReader(open(path)))
+    total = sum(float(r["TotalDurationNs"]) for r in rows)
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    out = [f"command: {command}", f"source_sha256(csrc/mech.hip): {source_sha256()}",
+           f"kernels: {len(rows)}  total kernel time: {total / 1e6:.3f} ms", "",
+           f"{'calls':>7} {'avg_us':>10} {'min_us':>10} {'max_us':>10} {'pct':>6}  name"]
+    for r in rows[:top]:
+        out.append(f"{int(r['Calls']):7d} {float(r['AverageNs']) / 1e3:10.3f} "
+                   f"{float(r['MinNs']) / 1e3:10.3f} {float(r['MaxNs']) / 1e3:10.3f} "
+                   f"{100.0 * float(r['TotalDurationNs']) / total:6.2f}  {_short(r['Name'])}")
+    return "\n".join(out) + "\n"
+
+
+def _per_dispatch(path: str, counter: str):
+    """{kernel name: [counter value per dispatch, ...]} (values summed over the counter's
+    instances within a dispatch)."""
+    acc = collections.defaultdict(float)
+    names = {}
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] != counter:
+            continue
+        key = r["Dispatch_Id"]
+        acc[key] += float(r["Counter_Value"])
+        names[key] = r["Kernel_Name"]
+    by = collections.defaultdict(list)
+    for key, v in acc.items():
+        by[names[key]].append(v)
+    return by
+
+
+def _pick(by, sub: str):
+    hits = {k: v for k, v in by.items() if sub in k}
+    if not hits:
+        raise SystemExit(f"no dispatch of a kernel matching {sub!r}")
+    vals = [x for v in hits.values() for x in v]
+    return sorted(hits), vals
+
+
+def traffic(a) -> str:
+    f_by = _per_dispatch(a.fetch, "FETCH_SIZE")
+    w_by = _per_dispatch(a.write, "WRITE_SIZE")
+    kn, kf = _pick(f_by, a.kernel)
+    _, kw = _pick(w_by, a.kernel)
+    cn, cf = _pick(f_by, a.copy_kernel)
+    _, cw = _pick(w_by, a.copy_kernel)
+    # the copy's largest dispatches are the calibration copies (other matches are small)
+    cf_kib = max(cf)
+    cw_kib = max(cw)
+    sf = a.copy_bytes / (cf_kib * 1024.0)
+    sw = a.copy_bytes / (cw_kib * 1024.0)
+    kf_kib = sum(kf) / len(kf)
+    kw_kib = sum(kw) / len(kw)
+    fetch_b = kf_kib * 1024.0 * sf
+    write_b = kw_kib * 1024.0 * sw
+    lines = [
+        f"command (FETCH_SIZE): {a.command_fetch}",
+        f"command (WRITE_SIZE): {a.command_write}",
+        f"source_sha256(csrc/mech.hip): {source_sha256()}",
+        f"kernel: {a.kernel}  ({len(kf)} dispatches; {'; '.join(_short(k) for k in kn)})",
+        f"workload: {a.workload}",
+        f"copy kernel: {'; '.join(_short(k) for k in cn)}  bytes read = bytes written = {a.copy_bytes}",
+        f"copy FETCH_SIZE KiB/dispatch: {cf_kib:.1f}  scale: {sf:.4f}",
+        f"copy WRITE_SIZE KiB/dispatch: {cw_kib:.1f}  scale: {sw:.4f}",
+        f"kernel FETCH_SIZE KiB/dispatch (mean): {kf_kib:.1f}  min {min(kf):.1f} max {max(kf):.1f}",
+        f"kernel WRITE_SIZE KiB/dispatch (mean): {kw_kib:.1f}  min {min(kw):.1f} max {max(kw):.1f}",
+        f"fetch_bytes_per_launch: {fetch_b:.0f}",
+        f"write_bytes_per_launch: {write_b:.0f}",
+        f"traffic_bytes_per_launch: {fetch_b + write_b:.0f}",
+    ]
+    return "\n".join(lines) + "\n"
+
+
+def read_traffic(path: str):
+    """(traffic bytes per launch, source sha256, workload) from a `traffic` summary."""
+    vals = {}
+    for line in open(path):
+        k, _, v = line.partition(":")
+        vals[k.strip()] = v.strip()
+    return (float(vals["traffic_bytes_per_launch"]), vals["source_sha256(csrc/mech.hip)"],
+            vals.get("workload", ""))
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("csv")
+    s.add_argument("--command", required=True)
+    s.add_argument("--top", type=int, default=25)
+    t = sub.add_parser("traffic")
+    t.add_argument("--fetch", required=True)
+    t.add_argument("--write", required=True)
+    t.add_argument("--kernel", required=True)
+    t.add_argument("--copy-kernel", required=True)
+    t.add_argument("--copy-bytes", type=float, required=True)
+    t.add_argument("--workload", required=True)
+    t.add_argument("--command-fetch", required=True)
+    t.add_argument("--command-write", required=True)
+    a = ap.parse_args(argv)
+    sys.stdout.write(stats(a.csv, a.command, a.top) if a.cmd == "stats" else traffic(a))
+
+
+if __name__ == "__main__":
+    main()

@@ -168,7 +168,7 @@ def main(argv=None):
     ap.add_argument("--requests", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=20, help="requests excluded from the statistics")
     ap.add_argument("--rate", type=float, default=50.0)
-    ap.add_argument("--budget-gb", type=float, default=200.0)
+    ap.add_argument("--budget-gb", type=float, default=200.0, help="HBM budget in GiB")
     ap.add_argument("--precision", default="fp32")
     ap.add_argument("--chunk", type=int, default=10)
     ap.add_argument("--max-slots", type=int, default=1024)
@@ -192,7 +192,7 @@ def main(argv=None):
         "latency_p99_s": float(np.percentile(lat, 99)),
         "offered_cell_steps_per_s": offered,
         "rate_req_per_s": args.rate,
-        "budget_gb": args.budget_gb,
+        "budget_gib": args.budget_gb,
         "precision": args.precision,
     })
     print(json.dumps(out), flush=True)
