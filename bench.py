@@ -49,15 +49,20 @@ FORCE_BYTES_PER_CELL = {"fp64": 24 + 32 + 4 + 48 + 24, "fp32": 24 + 32 + 4 + 24 
                         "fp32k": 24 + 32 + 4 + 24 + 24}
 
 
-def measured_traffic(kernel: str, workload: str, precision: str):
+def tuning_str(t: dict) -> str:
+    return ",".join(str(t[k]) for k in ("force_kernel", "block_waves", "unroll", "blocks_per_cu"))
+
+
+def measured_traffic(kernel: str, workload: str, precision: str, tuning: dict):
     """HBM bytes per launch of `kernel` from its committed counter summary, or None when
-    there is none or the kernel source has changed since the counters were taken."""
+    there is none, it was taken with another launch configuration, or the kernel source
+    has changed since the counters were taken."""
     from paper_2306_11544_amd import rocprof_summary as RS
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}_{precision}.txt")
     if not os.path.exists(path):
         return None
-    b, sha, _ = RS.read_traffic(path)
-    return b if sha == RS.source_sha256() else None
+    b, sha, _, tun = RS.read_traffic(path)
+    return b if sha == RS.source_sha256() and tun == tuning_str(tuning) else None
 
 
 def copy_calibration(mb: int, stream):
@@ -117,7 +122,20 @@ def bench_batch(args):
     vox = sum(B.batch_request_voxels(p, x.lo, x.hi) for x in pops)
     log(f"batch: {n_sims} simulations, {cells} cells, {vox} voxels, {prec}")
     torch.cuda.init()
+    tune_info = None
+    best = None
+    if args.tune:
+        from paper_2306_11544_amd import autotune as A
+        t0 = time.perf_counter()
+        best, rows = A.tune(p, pops, log=log)
+        default_ms = next(r["force_ms"] for r in rows if r == dict(r, **A.DEFAULT.as_dict()))
+        tune_info = {"chosen": best.as_dict(), "candidates": len(rows),
+                     "force_ms_chosen": min(r["force_ms"] for r in rows),
+                     "force_ms_default": default_ms, "seconds": time.perf_counter() - t0}
+        log(f"autotuner: {tune_info}")
     with B.Batch(p, cells, vox, n_sims) as bt:
+        if best is not None:
+            bt.set_tuning(best)
         slots = [bt.admit_pop(x, n_steps=-1) for x in pops]
         bt.step(args.warmup)
         B.batch_sync(bt)
@@ -154,7 +172,9 @@ def bench_batch(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"batch{n_sims}", "simulations": n_sims, "cells": cells,
-                   "voxels": vox, "precision": prec, "force_kernel": args.force},
+                   "voxels": vox, "precision": prec,
+                   "tuning": best.as_dict() if best is not None else {"force_kernel": args.force}},
+        "autotuner": tune_info,
         "interactions_per_s": (i1 - i0) / wall,
         "step_latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "phase_ms": {"binning_reorder": bin_ms, "force_update": force_ms},
@@ -175,7 +195,13 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sims", type=int, default=256, help="batch workload: simulations")
-    ap.add_argument("--force", default="cells", help="force kernel: cells | rows | voxel")
+    ap.add_argument("--force", default="cells",
+                    help="force kernel when not tuned: cells | rows | voxel")
+    ap.add_argument("--no-tune", dest="tune", action="store_false",
+                    help="skip the autotuner (default configuration or --force)")
+    ap.add_argument("--tuning", default="",
+                    help="fixed force-kernel configuration K,W,U,G (kernel flag, waves per "
+                         "workgroup, candidates per trip, workgroups per CU); skips the tuner")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="after the run, a streaming copy of this size for counter scaling")
     args = ap.parse_args()
@@ -205,6 +231,22 @@ def main():
     stream = torch.cuda.Stream(device=dev)
     ws = torch.empty(B.population_workspace_bytes(prm, pop.n), dtype=torch.uint8, device=dev)
     P = B.Population(prm, pop.pos, pop.radius, pop.type, stream=stream.cuda_stream, workspace=ws)
+    tune_info = None
+    if args.tuning:
+        P.set_tuning(B.tuning(*[int(x) for x in args.tuning.split(",")]))
+    elif args.tune:
+        from paper_2306_11544_amd import autotune as A
+        t0 = time.perf_counter()
+        best, rows = A.tune(prm, [pop], log=log)
+        default_ms = next(r["force_ms"] for r in rows if r == dict(r, **A.DEFAULT.as_dict()))
+        P.set_tuning(best)
+        tune_info = {"chosen": best.as_dict(), "candidates": len(rows),
+                     "force_ms_chosen": min(r["force_ms"] for r in rows),
+                     "force_ms_default": default_ms, "seconds": time.perf_counter() - t0}
+        log(f"autotuner: {tune_info}")
+    tuning = P.get_tuning().as_dict()
+    kname = {0: "k_force_cells", B.MECH_FLAG_SIMPLE_FORCE: "k_force_rows",
+             B.MECH_FLAG_VOXEL_FORCE: "k_force_lds"}[tuning["force_kernel"]]
 
     P.step(args.warmup)
     torch.cuda.synchronize()
@@ -256,8 +298,7 @@ def main():
     P.close()
     if args.calibrate_copy_mb:
         copy_calibration(args.calibrate_copy_mb, stream)
-    kname = f"k_force_{args.force}"
-    traffic = measured_traffic(kname, pop.name, precision)
+    traffic = measured_traffic(kname, pop.name, precision, tuning)
 
     out = {
         "metric": METRIC,
@@ -274,7 +315,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": pop.name, "cells": pop.n, "precision": precision,
                    "voxel_um": pop.voxel, "dt_min": pop.dt,
-                   "integration": "f64 two-step Adams-Bashforth"},
+                   "integration": "f64 two-step Adams-Bashforth", "tuning": tuning},
+        "autotuner": tune_info,
         "cell_steps_per_s": cell_steps,
         "candidates_per_s": cand / elapsed_s,
         "step_latency_ms": {"p50": float(np.percentile(lat, 50)),

@@ -88,6 +88,22 @@ typedef struct MechParams {
                                    symmetric (Newton's third law), um/min               */
 } MechParams;
 
+/* Launch configuration of the neighbour-force kernel (a6 + a7).  Every configuration
+ * computes the same results up to the summation order of the force sums (bitwise the
+ * same for one configuration); it only sets how the work is dealt to the GPU. */
+typedef struct MechTuning {
+    int32_t force_kernel;       /* 0 (list kernel), MECH_FLAG_SIMPLE_FORCE or
+                                   MECH_FLAG_VOXEL_FORCE (the force bits of flags)      */
+    int32_t block_waves;        /* wave64s per workgroup of the per-cell kernels:
+                                   1, 2, 4 (default) or 8                               */
+    int32_t unroll;             /* candidates the list kernel tests per loop trip:
+                                   2, 4 (default) or 8                                  */
+    int32_t blocks_per_cu;      /* force-kernel workgroups per compute unit, 1..64, or 0
+                                   (default): one per block_waves*64 cells of capacity
+                                   (at most 32768 wave64s) for the per-cell kernels and
+                                   4 per compute unit for the voxel kernel              */
+} MechTuning;
+
 typedef struct MechPopulation MechPopulation;
 
 /* Text of the last error on this thread ("" if none).  Valid until the next call. */
@@ -157,6 +173,12 @@ int read_stats(MechPopulation* pop, int64_t* steps, int64_t* interactions,
  *   phase_ms[1]  mean ms per step of the neighbour-force and update kernel (a6-a7)
  * Synchronises.  For tuning and roofline measurement. */
 int profile_step(MechPopulation* pop, int64_t n_steps, double* phase_ms);
+
+/* Current force-kernel launch configuration of a population, and a replacement for
+ * it (validated: MECH_E_INVALID for a value outside the ranges of MechTuning).  Setting
+ * waits for the stream; the step graph is captured again on the next step. */
+int population_get_tuning(MechPopulation* pop, MechTuning* out);
+int population_set_tuning(MechPopulation* pop, const MechTuning* tuning);
 
 /* Size and grid of a population: n_cells, and voxels per axis. */
 int population_info(MechPopulation* pop, int64_t* n_cells, int32_t dims[3]);
@@ -237,6 +259,11 @@ int batch_profile(MechBatch* batch, int64_t n_steps, double* phase_ms);
 /* Replace the batch's MechParams.flags (force-kernel variant, graph use): the tuner's
  * hook.  Waits for the stream; the step graph is captured again on the next step. */
 int batch_set_flags(MechBatch* batch, int32_t flags);
+
+/* As population_get_tuning / population_set_tuning, for a batch (what the autotuner
+ * sets once it has timed the candidates on a copy of the batch). */
+int batch_get_tuning(MechBatch* batch, MechTuning* out);
+int batch_set_tuning(MechBatch* batch, const MechTuning* tuning);
 
 /* Wait until every step enqueued so far has completed on the device. */
 int batch_sync(MechBatch* batch);

@@ -1,0 +1,119 @@
+"""Autotuner for the neighbour-force kernel of a batch (or a population).
+
+The force kernel has three variants (per-cell list kernel, per-cell inline kernel,
+wave-per-voxel LDS kernel) and, for the per-cell ones, a workgroup size (wave64s per
+workgroup), a tile (candidates tested per loop trip) and a grid size (workgroups per
+compute unit).  Which is fastest depends on the density and size mix of the
+simulations, so the tuner times each candidate configuration on a scratch copy of the
+workload (the real batch's trajectories are not advanced) and keeps the fastest.
+Every configuration gives the same results up to the summation order of the force sums.
+
+Choices are cached in a JSON file keyed by a shape class of the workload (precision,
+number of types, total cells and cells per voxel, both on a log2 scale), so a server
+tunes once per class.
+
+  best, table = tune(params, populations)          # time the space on a scratch batch
+  best = tuned(params, populations)                # cached, else tune()
+  batch.set_tuning(best)
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import time
+
+from . import binding as B
+
+DEFAULT = B.tuning()
+
+
+def search_space():
+    """Candidate configurations: the list kernel over workgroup size x tile x grid, the
+    inline kernel over workgroup size, the LDS kernel over grid size."""
+    space = []
+    for w in (1, 2, 4, 8):
+        for u in (2, 4, 8):
+            for g in (0, 16):
+                space.append(B.tuning("cells", w, u, g))
+    for w in (2, 4, 8):
+        space.append(B.tuning("rows", w, 4, 0))
+    for g in (2, 4, 8):
+        space.append(B.tuning("voxel", 4, 4, g))
+    return space
+
+
+def _cache_path():
+    return os.environ.get("MECH_TUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "paper_2306_11544_amd",
+                                       "tuning.json"))
+
+
+def shape_class(params: B.MechParams, pops) -> str:
+    cells = sum(p.n for p in pops)
+    vox = sum(B.batch_request_voxels(params, p.lo, p.hi) for p in pops)
+    return (f"prec{int(params.precision)}-types{int(params.n_types)}"
+            f"-cells2^{round(math.log2(max(cells, 1)))}"
+            f"-density2^{round(math.log2(max(cells, 1) / max(vox, 1)))}")
+
+
+def _scratch_batch(params: B.MechParams, pops):
+    cells = sum(p.n for p in pops)
+    vox = sum(B.batch_request_voxels(params, p.lo, p.hi) for p in pops)
+    bt = B.Batch(params, cells, vox, len(pops))
+    for p in pops:
+        bt.admit_pop(p, n_steps=-1)
+    return bt
+
+
+def tune(params: B.MechParams, pops, steps: int = 3, repeats: int = 2, space=None, log=None):
+    """Time every configuration of `space` on a scratch batch holding `pops`.
+
+    Returns (best MechTuning, table of {config..., force_ms}) with the mean force-kernel
+    time per step over `steps` steps, the best of `repeats` passes over the space."""
+    space = list(space or search_space())
+    table = {i: math.inf for i in range(len(space))}
+    bt = _scratch_batch(params, pops)
+    try:
+        bt.step(2)
+        B.batch_sync(bt)
+        for _ in range(repeats):
+            for i, t in enumerate(space):
+                bt.set_tuning(t)
+                bt.profile(1)  # first launch of this configuration
+                _, force_ms = bt.profile(steps)
+                table[i] = min(table[i], force_ms)
+                if log:
+                    log(f"tune {t.as_dict()} force {force_ms:.4f} ms")
+    finally:
+        bt.close()
+    best = min(table, key=table.get)
+    rows = [dict(space[i].as_dict(), force_ms=table[i]) for i in range(len(space))]
+    return space[best], rows
+
+
+def tuned(params: B.MechParams, pops, cache: bool = True, log=None, **kw):
+    """The cached choice for this workload's shape class, else tune() and cache it."""
+    key = shape_class(params, pops)
+    path = _cache_path()
+    data = {}
+    if cache and os.path.exists(path):
+        try:
+            with open(path) as f:
+                data = json.load(f)
+        except (OSError, ValueError):
+            data = {}
+    if key in data:
+        return B.tuning(**data[key]["tuning"])
+    t0 = time.perf_counter()
+    best, rows = tune(params, pops, log=log, **kw)
+    if cache:
+        data[key] = {"tuning": best.as_dict(),
+                     "force_ms": min(r["force_ms"] for r in rows),
+                     "seconds": time.perf_counter() - t0}
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        tmp = path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(data, f, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    return best

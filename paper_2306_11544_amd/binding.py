@@ -22,6 +22,7 @@ MECH_AB2_ZERO_HISTORY, MECH_AB2_EULER_START = 0, 1
 MECH_FLAG_NO_GRAPH = 1
 MECH_FLAG_SIMPLE_FORCE = 2
 MECH_FLAG_VOXEL_FORCE = 4
+MECH_FORCE_KERNEL_MASK = 6
 FORCE_KERNELS = {"cells": 0, "rows": MECH_FLAG_SIMPLE_FORCE, "voxel": MECH_FLAG_VOXEL_FORCE}
 MECH_ABI_VERSION = 1
 
@@ -31,11 +32,12 @@ PRECISIONS = {"fp64": MECH_FP64, "fp32": MECH_FP32, "fp32k": MECH_FP32_KAHAN}
 EXPORTS = ("mech_last_error", "mech_abi_version", "mech_device_count",
            "population_workspace_bytes", "create_population", "create_population_in",
            "step_mechanics", "read_state", "read_binning", "read_stats", "profile_step",
+           "population_get_tuning", "population_set_tuning",
            "population_info", "population_stream", "destroy_population",
            "batch_workspace_bytes", "batch_request_voxels", "create_batch", "create_batch_in",
            "batch_admit", "batch_step", "batch_poll", "batch_read", "batch_retire",
            "batch_slot_info", "batch_info", "batch_stats", "batch_profile", "batch_set_flags",
-           "batch_sync", "batch_stream", "destroy_batch")
+           "batch_get_tuning", "batch_set_tuning", "batch_sync", "batch_stream", "destroy_batch")
 
 
 class MechError(RuntimeError):
@@ -50,6 +52,20 @@ class MechParams(C.Structure):
                 ("voxel_size", C.c_double), ("dt", C.c_double), ("c_rep", C.c_double),
                 ("rel_adh_distance", C.c_double), ("n_types", C.c_int32), ("reserved", C.c_int32),
                 ("c_adh", C.c_double * 64)]
+
+
+class MechTuning(C.Structure):
+    _fields_ = [("force_kernel", C.c_int32), ("block_waves", C.c_int32), ("unroll", C.c_int32),
+                ("blocks_per_cu", C.c_int32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+def tuning(force_kernel=0, block_waves=4, unroll=4, blocks_per_cu=0) -> MechTuning:
+    if isinstance(force_kernel, str):
+        force_kernel = FORCE_KERNELS[force_kernel]
+    return MechTuning(int(force_kernel), int(block_waves), int(unroll), int(blocks_per_cu))
 
 
 _lib = None
@@ -84,6 +100,8 @@ def lib():
             "read_binning": (C.c_int, [vp, up, up, up, up, lp, lp]),
             "read_stats": (C.c_int, [vp, lp, lp, lp]),
             "profile_step": (C.c_int, [vp, C.c_int64, dp]),
+            "population_get_tuning": (C.c_int, [vp, P(MechTuning)]),
+            "population_set_tuning": (C.c_int, [vp, P(MechTuning)]),
             "population_info": (C.c_int, [vp, lp, ip]),
             "population_stream": (C.c_void_p, [vp]),
             "destroy_population": (C.c_int, [vp]),
@@ -102,6 +120,8 @@ def lib():
             "batch_stats": (C.c_int, [vp, lp, lp, lp]),
             "batch_profile": (C.c_int, [vp, C.c_int64, dp]),
             "batch_set_flags": (C.c_int, [vp, C.c_int32]),
+            "batch_get_tuning": (C.c_int, [vp, P(MechTuning)]),
+            "batch_set_tuning": (C.c_int, [vp, P(MechTuning)]),
             "batch_sync": (C.c_int, [vp]),
             "batch_stream": (C.c_void_p, [vp]),
             "destroy_batch": (C.c_int, [vp]),
@@ -284,6 +304,14 @@ class Population:
     def profile(self, n_steps=1):
         return profile_step(self.h, n_steps)
 
+    def get_tuning(self) -> MechTuning:
+        t = MechTuning()
+        _ck(lib().population_get_tuning(self.h, C.byref(t)))
+        return t
+
+    def set_tuning(self, t: MechTuning):
+        _ck(lib().population_set_tuning(self.h, C.byref(t)))
+
     @property
     def stream(self) -> int:
         return population_stream(self.h)
@@ -413,6 +441,15 @@ class Batch:
     def set_flags(self, flags: int):
         _ck(lib().batch_set_flags(self.h, int(flags)))
         self.params.flags = int(flags)
+
+    def get_tuning(self) -> MechTuning:
+        t = MechTuning()
+        _ck(lib().batch_get_tuning(self.h, C.byref(t)))
+        return t
+
+    def set_tuning(self, t: MechTuning):
+        _ck(lib().batch_set_tuning(self.h, C.byref(t)))
+        self.params.flags = (int(self.params.flags) & ~MECH_FORCE_KERNEL_MASK) | int(t.force_kernel)
 
     @property
     def stream(self) -> int:

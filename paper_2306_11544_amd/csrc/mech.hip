@@ -184,6 +184,11 @@ __device__ __forceinline__ void wave_sync()
 
 // ------------------------------------------------------------------------ a1 + a2
 
+// After the previous step's reorder the cells of one voxel are adjacent, so the lanes
+// of a wave fall into a few runs of equal voxel ids and a per-lane atomic would hit the
+// same counter many times over.  One lane per run adds the run's length; the run's
+// lanes take consecutive offsets from the value it gets back.  Which cell of a voxel
+// gets which offset does not matter: a4 orders each voxel's cells by id.
 __global__ __launch_bounds__(BLOCK) void k_bin(const double* __restrict__ px,
                                                const double* __restrict__ py,
                                                const double* __restrict__ pz,
@@ -195,11 +200,31 @@ __global__ __launch_bounds__(BLOCK) void k_bin(const double* __restrict__ px,
                                                uint32_t* __restrict__ off)
 {
     const uint32_t n = hdr[H_CELLS];
-    for (uint32_t s = blockIdx.x * BLOCK + threadIdx.x; s < n; s += gridDim.x * BLOCK) {
-        const SlotDesc& d = slots[slot_of[s]];
-        const uint32_t v = d.voxel_off + voxel_key(px[s], py[s], pz[s], d);
-        off[s] = atomicAdd(&count[v], 1u);
-        vid[s] = v;
+    const uint32_t lane = threadIdx.x & (WAVE - 1);
+    const uint64_t le = lane == WAVE - 1 ? ~0ull : (2ull << lane) - 1ull;  // lanes <= this one
+    // the trip count is uniform per wave, so every lane takes part in the shuffles
+    for (uint32_t s0 = blockIdx.x * BLOCK + (threadIdx.x & ~(WAVE - 1)); s0 < n; s0 += gridDim.x * BLOCK) {
+        const uint32_t s = s0 + lane;
+        const bool live = s < n;
+        uint32_t v = 0xffffffffu;
+        if (live) {
+            const SlotDesc& d = slots[slot_of[s]];
+            v = d.voxel_off + voxel_key(px[s], py[s], pz[s], d);
+        }
+        const uint32_t left = __shfl_up(v, 1, WAVE);
+        const bool head = live && (lane == 0 || left != v);
+        const uint64_t heads = __ballot(head);
+        const uint64_t n_live = __popcll(__ballot(live));  // live lanes are a prefix
+        const uint32_t first = 63u - (uint32_t)__clzll(heads & le);
+        const uint64_t above = heads & ~le;
+        const uint32_t end = above ? (uint32_t)__ffsll((long long)above) - 1u : (uint32_t)n_live;
+        uint32_t base = 0;
+        if (head) base = atomicAdd(&count[v], end - lane);
+        base = __shfl(base, (int)first, WAVE);
+        if (live) {
+            off[s] = base + (lane - first);
+            vid[s] = v;
+        }
     }
 }
 
@@ -631,18 +656,19 @@ __device__ __forceinline__ void force_rows_cell(const PhysArgs& P, const ForceAr
     }
 }
 
-// The cells of the batch in blocks of BLOCK, taken in rounds of gridDim.x blocks; in
-// each round the active blocks are renumbered so that each XCD gets a contiguous run.
-template <int PREC, bool MULTI, typename VPT>
-__global__ __launch_bounds__(BLOCK) void k_force_rows(PhysArgs P, ForceArgs<VPT> a)
+// The cells of the batch in blocks of WPB wave64s, taken in rounds of gridDim.x blocks;
+// in each round the active blocks are renumbered so that each XCD gets a contiguous run.
+template <int PREC, bool MULTI, typename VPT, int WPB>
+__global__ __launch_bounds__(WPB * WAVE) void k_force_rows(PhysArgs P, ForceArgs<VPT> a)
 {
+    constexpr uint32_t TB = WPB * WAVE;
     const uint32_t n = a.hdr[H_CELLS];
-    const uint32_t nb = (n + BLOCK - 1) / BLOCK;
+    const uint32_t nb = (n + TB - 1) / TB;
     uint32_t inter = 0, cand = 0;
     for (uint32_t lb0 = 0; lb0 < nb; lb0 += gridDim.x) {
         const uint32_t active = min(gridDim.x, nb - lb0);
         if (blockIdx.x >= active) break;
-        const uint32_t i = (lb0 + xcd_block(blockIdx.x, active)) * BLOCK + threadIdx.x;
+        const uint32_t i = (lb0 + xcd_block(blockIdx.x, active)) * TB + threadIdx.x;
         if (i < n) force_rows_cell<PREC, MULTI, VPT>(P, a, i, inter, cand);
     }
     add_stats(a.stats, inter, cand);
@@ -651,7 +677,7 @@ __global__ __launch_bounds__(BLOCK) void k_force_rows(PhysArgs P, ForceArgs<VPT>
 // ------------------------------------------------------------------------ a6 + a7, list kernel
 
 constexpr int FC_LIST = 16;    // listed candidates a lane holds before a flush
-constexpr int FC_UNROLL = 4;   // candidates tested per loop trip (independent loads in flight)
+// UNROLL: candidates tested per loop trip (independent loads in flight), at most FC_LIST / 2
 
 // One thread per cell in voxel order.  Each lane walks its 9 neighbour rows and only
 // prefilters the candidates, four loads in flight per trip: a candidate is listed in
@@ -663,7 +689,7 @@ constexpr int FC_UNROLL = 4;   // candidates tested per loop trip (independent l
 // pair term of pair64 / pair32, in candidate order, so each sum is still taken in the
 // fixed neighbour order and the rare interacting pairs do not make the wave diverge.
 // Lanes of one voxel read the same candidate at the same time (one cache line).
-template <int PREC, bool MULTI, typename VPT>
+template <int PREC, bool MULTI, typename VPT, int FC_UNROLL>
 __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceArgs<VPT>& a, uint32_t i,
                                                  uint32_t n, uint32_t* const list0, uint32_t& inter,
                                                  uint32_t& cand)
@@ -798,20 +824,22 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
     }
 }
 
-template <int PREC, bool MULTI, typename VPT>
-__global__ __launch_bounds__(BLOCK) void k_force_cells(PhysArgs P, ForceArgs<VPT> a)
+template <int PREC, bool MULTI, typename VPT, int WPB, int UNROLL>
+__global__ __launch_bounds__(WPB * WAVE) void k_force_cells(PhysArgs P, ForceArgs<VPT> a)
 {
-    __shared__ uint32_t s_list[BLOCK / WAVE][FC_LIST][WAVE];
+    static_assert(2 * UNROLL <= FC_LIST, "a trip must fit the list above the flush mark");
+    constexpr uint32_t TB = WPB * WAVE;
+    __shared__ uint32_t s_list[WPB][FC_LIST][WAVE];
     const uint32_t n = a.hdr[H_CELLS];
-    const uint32_t nb = (n + BLOCK - 1) / BLOCK;
+    const uint32_t nb = (n + TB - 1) / TB;
     uint32_t* const list0 = &s_list[threadIdx.x / WAVE][0][threadIdx.x & (WAVE - 1)];
     uint32_t inter = 0, cand = 0;
     // rounds of gridDim.x blocks, renumbered per round as in k_force_rows
     for (uint32_t lb0 = 0; lb0 < nb; lb0 += gridDim.x) {
         const uint32_t active = min(gridDim.x, nb - lb0);
         if (blockIdx.x >= active) break;
-        const uint32_t i = (lb0 + xcd_block(blockIdx.x, active)) * BLOCK + threadIdx.x;
-        force_cells_cell<PREC, MULTI, VPT>(P, a, i, n, list0, inter, cand);
+        const uint32_t i = (lb0 + xcd_block(blockIdx.x, active)) * TB + threadIdx.x;
+        force_cells_cell<PREC, MULTI, VPT, UNROLL>(P, a, i, n, list0, inter, cand);
     }
     add_stats(a.stats, inter, cand);
 }
@@ -1242,7 +1270,8 @@ struct MechBatch {
     std::vector<int32_t> order;           // used slots in arena order
     int parity = 0;
     int64_t steps = 0;
-    uint32_t force_grid = 1024;
+    int32_t cus = 256;                    // compute units of the device
+    MechTuning tune{0, 4, 4, 0};          // force-kernel launch configuration
     bool graphs_ready = false;
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
 
@@ -1312,6 +1341,57 @@ void enqueue_binning(MechBatch* B)
     hipLaunchKernelGGL(k_rank_gather<VPT>, dim3(nbc), dim3(BLOCK), 0, B->stream, hdr, g);
 }
 
+// Workgroups of a per-cell force kernel: one per WPB*64 cells of the arena's capacity,
+// at most 32768 wave64s in total, or tune.blocks_per_cu per compute unit.  The kernels
+// loop over the live cells, so any count is correct; it only sets how work is dealt.
+uint32_t force_cell_grid(const MechBatch* B, int wpb)
+{
+    const uint32_t tiles = std::max<uint32_t>(1, blocks_for((uint64_t)B->cap_cells, (uint32_t)wpb * WAVE));
+    const uint32_t cap = B->tune.blocks_per_cu ? (uint32_t)B->cus * (uint32_t)B->tune.blocks_per_cu
+                                               : 32768u / (uint32_t)wpb;
+    return std::min(tiles, cap);
+}
+
+template <int PREC, bool MULTI, typename VPT, int WPB>
+void launch_cells_w(MechBatch* B, const ForceArgs<VPT>& a)
+{
+    const dim3 grid(force_cell_grid(B, WPB)), block(WPB * WAVE);
+    switch (B->tune.unroll) {
+    case 2: hipLaunchKernelGGL((k_force_cells<PREC, MULTI, VPT, WPB, 2>), grid, block, 0, B->stream, B->phys, a); break;
+    case 8: hipLaunchKernelGGL((k_force_cells<PREC, MULTI, VPT, WPB, 8>), grid, block, 0, B->stream, B->phys, a); break;
+    default: hipLaunchKernelGGL((k_force_cells<PREC, MULTI, VPT, WPB, 4>), grid, block, 0, B->stream, B->phys, a); break;
+    }
+}
+
+template <int PREC, bool MULTI, typename VPT>
+void launch_cells(MechBatch* B, const ForceArgs<VPT>& a)
+{
+    switch (B->tune.block_waves) {
+    case 1: launch_cells_w<PREC, MULTI, VPT, 1>(B, a); break;
+    case 2: launch_cells_w<PREC, MULTI, VPT, 2>(B, a); break;
+    case 8: launch_cells_w<PREC, MULTI, VPT, 8>(B, a); break;
+    default: launch_cells_w<PREC, MULTI, VPT, 4>(B, a); break;
+    }
+}
+
+template <int PREC, bool MULTI, typename VPT, int WPB>
+void launch_rows_w(MechBatch* B, const ForceArgs<VPT>& a)
+{
+    hipLaunchKernelGGL((k_force_rows<PREC, MULTI, VPT, WPB>), dim3(force_cell_grid(B, WPB)), dim3(WPB * WAVE), 0,
+                       B->stream, B->phys, a);
+}
+
+template <int PREC, bool MULTI, typename VPT>
+void launch_rows(MechBatch* B, const ForceArgs<VPT>& a)
+{
+    switch (B->tune.block_waves) {
+    case 1: launch_rows_w<PREC, MULTI, VPT, 1>(B, a); break;
+    case 2: launch_rows_w<PREC, MULTI, VPT, 2>(B, a); break;
+    case 8: launch_rows_w<PREC, MULTI, VPT, 8>(B, a); break;
+    default: launch_rows_w<PREC, MULTI, VPT, 4>(B, a); break;
+    }
+}
+
 template <int PREC, typename VPT>
 void enqueue_force(MechBatch* B, int parity_after_sort)
 {
@@ -1335,25 +1415,25 @@ void enqueue_force(MechBatch* B, int parity_after_sort)
     a.cadh_f = B->at<float>(L.cadh_f);
     a.stats = B->at<unsigned long long>(L.stats);
     const bool multi = B->prm.n_types > 1;
-    const uint32_t nbc = cell_grid(B);
     if (B->prm.flags & MECH_FLAG_SIMPLE_FORCE) {
         if (multi)
-            hipLaunchKernelGGL((k_force_rows<PREC, true, VPT>), dim3(nbc), dim3(BLOCK), 0, B->stream, B->phys, a);
+            launch_rows<PREC, true, VPT>(B, a);
         else
-            hipLaunchKernelGGL((k_force_rows<PREC, false, VPT>), dim3(nbc), dim3(BLOCK), 0, B->stream, B->phys, a);
+            launch_rows<PREC, false, VPT>(B, a);
     } else if (B->prm.flags & MECH_FLAG_VOXEL_FORCE) {
         const uint32_t* occ = B->at<uint32_t>(L.occ);
+        const uint32_t grid = (uint32_t)B->cus * (uint32_t)(B->tune.blocks_per_cu ? B->tune.blocks_per_cu : 4);
         if (multi)
-            hipLaunchKernelGGL((k_force_lds<PREC, true, VPT>), dim3(B->force_grid), dim3(FL_WAVES * WAVE), 0,
+            hipLaunchKernelGGL((k_force_lds<PREC, true, VPT>), dim3(grid), dim3(FL_WAVES * WAVE), 0,
                                B->stream, B->phys, a, occ);
         else
-            hipLaunchKernelGGL((k_force_lds<PREC, false, VPT>), dim3(B->force_grid), dim3(FL_WAVES * WAVE), 0,
+            hipLaunchKernelGGL((k_force_lds<PREC, false, VPT>), dim3(grid), dim3(FL_WAVES * WAVE), 0,
                                B->stream, B->phys, a, occ);
     } else {
         if (multi)
-            hipLaunchKernelGGL((k_force_cells<PREC, true, VPT>), dim3(nbc), dim3(BLOCK), 0, B->stream, B->phys, a);
+            launch_cells<PREC, true, VPT>(B, a);
         else
-            hipLaunchKernelGGL((k_force_cells<PREC, false, VPT>), dim3(nbc), dim3(BLOCK), 0, B->stream, B->phys, a);
+            launch_cells<PREC, false, VPT>(B, a);
     }
 }
 
@@ -1488,7 +1568,7 @@ int create_batch_impl(const MechParams* params, int64_t max_cells, int64_t max_v
         int cus = 0;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, B->device) != hipSuccess || cus < 1)
             cus = 256;
-        B->force_grid = (uint32_t)cus * 4u;
+        B->cus = cus;
     }
     if (stream) {
         B->stream = (hipStream_t)stream;
@@ -2036,6 +2116,18 @@ int read_stats(MechPopulation* P, int64_t* steps, int64_t* interactions, int64_t
     return stats_impl(P->b, steps, interactions, candidates);
 }
 
+int population_get_tuning(MechPopulation* P, MechTuning* out)
+{
+    if (!P) return fail(MECH_E_INVALID, "population is NULL");
+    return batch_get_tuning(P->b, out);
+}
+
+int population_set_tuning(MechPopulation* P, const MechTuning* t)
+{
+    if (!P) return fail(MECH_E_INVALID, "population is NULL");
+    return batch_set_tuning(P->b, t);
+}
+
 int population_info(MechPopulation* P, int64_t* n_cells, int32_t dims[3])
 {
     if (!P) return fail(MECH_E_INVALID, "population is NULL");
@@ -2205,6 +2297,33 @@ int batch_set_flags(MechBatch* B, int32_t flags)
     HIP_TRY(hipStreamSynchronize(B->stream));
     drop_graphs(B);
     B->prm.flags = flags;
+    return MECH_OK;
+}
+
+int batch_get_tuning(MechBatch* B, MechTuning* out)
+{
+    if (!B || !out) return fail(MECH_E_INVALID, "batch or out is NULL");
+    *out = B->tune;
+    out->force_kernel = B->prm.flags & MECH_FORCE_KERNEL_MASK;
+    return MECH_OK;
+}
+
+int batch_set_tuning(MechBatch* B, const MechTuning* t)
+{
+    if (!B || !t) return fail(MECH_E_INVALID, "batch or tuning is NULL");
+    if (t->force_kernel != 0 && t->force_kernel != MECH_FLAG_SIMPLE_FORCE && t->force_kernel != MECH_FLAG_VOXEL_FORCE)
+        return fail(MECH_E_INVALID, "force_kernel %d unknown", t->force_kernel);
+    if (t->block_waves != 1 && t->block_waves != 2 && t->block_waves != 4 && t->block_waves != 8)
+        return fail(MECH_E_INVALID, "block_waves %d not in {1, 2, 4, 8}", t->block_waves);
+    if (t->unroll != 2 && t->unroll != 4 && t->unroll != 8)
+        return fail(MECH_E_INVALID, "unroll %d not in {2, 4, 8}", t->unroll);
+    if (t->blocks_per_cu < 0 || t->blocks_per_cu > 64)
+        return fail(MECH_E_INVALID, "blocks_per_cu %d not in [0, 64]", t->blocks_per_cu);
+    HIP_TRY(hipSetDevice(B->device));
+    HIP_TRY(hipStreamSynchronize(B->stream));
+    drop_graphs(B);
+    B->tune = *t;
+    B->prm.flags = (B->prm.flags & ~MECH_FORCE_KERNEL_MASK) | t->force_kernel;
     return MECH_OK;
 }
 

@@ -95,6 +95,7 @@ def traffic(a) -> str:
         f"source_sha256(csrc/mech.hip): {source_sha256()}",
         f"kernel: {a.kernel}  ({len(kf)} dispatches; {'; '.join(_short(k) for k in kn)})",
         f"workload: {a.workload}",
+        f"tuning: {a.tuning}",
         f"copy kernel: {'; '.join(_short(k) for k in cn)}  bytes read = bytes written = {a.copy_bytes}",
         f"copy FETCH_SIZE KiB/dispatch: {cf_kib:.1f}  scale: {sf:.4f}",
         f"copy WRITE_SIZE KiB/dispatch: {cw_kib:.1f}  scale: {sw:.4f}",
@@ -108,13 +109,14 @@ def traffic(a) -> str:
 
 
 def read_traffic(path: str):
-    """(traffic bytes per launch, source sha256, workload) from a `traffic` summary."""
+    """(traffic bytes per launch, source sha256, workload, tuning) from a `traffic`
+    summary."""
     vals = {}
     for line in open(path):
         k, _, v = line.partition(":")
         vals[k.strip()] = v.strip()
     return (float(vals["traffic_bytes_per_launch"]), vals["source_sha256(csrc/mech.hip)"],
-            vals.get("workload", ""))
+            vals.get("workload", ""), vals.get("tuning", ""))
 
 
 def main(argv=None):
@@ -131,6 +133,7 @@ def main(argv=None):
     t.add_argument("--copy-kernel", required=True)
     t.add_argument("--copy-bytes", type=float, required=True)
     t.add_argument("--workload", required=True)
+    t.add_argument("--tuning", default="", help="launch configuration the run used, as K,W,U,G")
     t.add_argument("--command-fetch", required=True)
     t.add_argument("--command-write", required=True)
     a = ap.parse_args(argv)

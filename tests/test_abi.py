@@ -42,6 +42,29 @@ def test_params_struct_matches_header_layout():
     assert B.MechParams.c_adh.offset == 16 + 48 + 32 + 8
 
 
+def test_tuning_struct_matches_header_layout():
+    assert C.sizeof(B.MechTuning) == 16
+    t = B.tuning("voxel", 8, 2, 16)
+    assert t.as_dict() == {"force_kernel": B.MECH_FLAG_VOXEL_FORCE, "block_waves": 8, "unroll": 2,
+                           "blocks_per_cu": 16}
+
+
+def test_tuning_search_space_is_valid():
+    from paper_2306_11544_amd import autotune as A
+    space = A.search_space()
+    assert len({tuple(t.as_dict().values()) for t in space}) == len(space)
+    for t in space:
+        assert t.force_kernel in (0, B.MECH_FLAG_SIMPLE_FORCE, B.MECH_FLAG_VOXEL_FORCE)
+        assert t.block_waves in (1, 2, 4, 8) and t.unroll in (2, 4, 8)
+        assert 0 <= t.blocks_per_cu <= 64
+
+
+def test_tuning_calls_reject_null_handles():
+    t = B.tuning()
+    assert B.lib().batch_set_tuning(None, C.byref(t)) == B.MECH_E_INVALID
+    assert B.lib().population_get_tuning(None, C.byref(t)) == B.MECH_E_INVALID
+
+
 def test_abi_version():
     assert B.mech_abi_version() == B.MECH_ABI_VERSION
 
