@@ -9,7 +9,8 @@
  *   a2  voxel histogram
  *   a3  exclusive scan of the counts and the list of occupied voxels (the paper's
  *       non-empty voxel list, Section 5.4)
- *   a4  rank of each cell inside its voxel by ascending cell id (bit-exact order)
+ *   a4  order of the cells inside each voxel: by x slab (each voxel cut into 4 slabs
+ *       along x), then by ascending cell id (bit-exact order)
  *   a5  gather of the cell state into that voxel order, so that cells close in space
  *       are close in memory (the layout the paper recommends, Sections 5.4 and 6)
  *   a6  velocity of each cell: sum over the cells of the 27 surrounding voxels of
@@ -31,7 +32,7 @@
  *     up as MECH_E_DEVICE at the next synchronising call (read_*, destroy).
  *   - A population is used from one host thread at a time.  Different populations may
  *     run on different streams concurrently.
- *   - Units: um, min, um/min.  n_cells < 2^31 and n_voxels < 2^31.
+ *   - Units: um, min, um/min.  n_cells < 2^31 and n_voxels < 2^30.
  *   - Cell ids are the row indices of the arrays given at creation; every read_* call
  *     returns arrays in id order unless it says otherwise.
  */
@@ -155,7 +156,8 @@ int read_state(MechPopulation* pop, double* pos, double* vel, int64_t n_cells);
 /* Wait and copy the binning of the last step (or of creation, before any step):
  *   voxel_of_cell  n_cells uint32, id order (may be NULL)
  *   voxel_start    n_voxels + 1 uint32: exclusive prefix of voxel counts (may be NULL)
- *   sorted_ids     n_cells uint32: ids in (voxel, id) order (may be NULL)
+ *   sorted_ids     n_cells uint32: ids in storage order (voxel, x slab, id), the x slab
+ *                  being floor((x - lo) * (1/h) * 4) - 4 * (voxel's x index) (may be NULL)
  *   occ            n_voxels uint32: occupied voxels, ascending; *n_occ of them are valid
  *                  (may be NULL)
  *   n_occ, n_voxels  outputs (may be NULL) */
@@ -163,7 +165,9 @@ int read_binning(MechPopulation* pop, uint32_t* voxel_of_cell, uint32_t* voxel_s
                  uint32_t* sorted_ids, uint32_t* occ, int64_t* n_occ, int64_t* n_voxels);
 
 /* Wait and return the running totals: steps taken, interacting ordered pairs
- * (0 < d^2 < R_A^2), and candidate pairs visited in the 27-voxel neighbourhoods. */
+ * (0 < d^2 < R_A^2), and candidate pairs the force kernel tested: the cells of the 27
+ * voxels around each cell, narrowed by the default kernel to the x slabs within reach of
+ * the cell (the other kernels test all of them). */
 int read_stats(MechPopulation* pop, int64_t* steps, int64_t* interactions,
                int64_t* candidates);
 

@@ -84,6 +84,12 @@ constexpr int SCAN_PER_THREAD = 8;
 constexpr int SCAN_TILE = BLOCK * SCAN_PER_THREAD;
 constexpr uint32_t N_XCD = 8;              // MI355X: 8 accelerator complex dies
 constexpr uint32_t STAT_SLOTS = 1024;      // spread of the running counters
+// Storage bins: each voxel is cut into XSUB slabs along x, and cells are stored bin by
+// bin (voxel, then slab, then id).  A voxel is still one contiguous run (its XSUB bins),
+// and the cells of a neighbour row that lie within reach of a cell along x are a
+// contiguous run of whole slabs.
+constexpr uint32_t XSUB = 4;
+static_assert(SCAN_PER_THREAD % XSUB == 0 && SCAN_TILE % XSUB == 0, "scan tiles hold whole voxels");
 
 // device header words
 constexpr int H_CELLS = 0, H_VOXELS = 1, H_OCC = 2;
@@ -123,18 +129,20 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb)
     return xcd < r ? xcd * (q + 1) + k : r * (q + 1) + (xcd - r) * q + k;
 }
 
-// a1: voxel of a position in its slot's grid.  (x - lo) * (1/h) is a subtraction then a
-// product, so no fused form exists and the result is the IEEE value of the expression.
-__device__ __forceinline__ uint32_t voxel_key(double x, double y, double z, const SlotDesc& d)
+// a1: storage bin of a position in its slot's grid, XSUB * (voxel id) + x slab.
+// (x - lo) * (1/h) is a subtraction then a product, so no fused form exists and the
+// result is the IEEE value of the expression; multiplying it by XSUB (a power of two) is
+// exact, so slab / XSUB is the voxel's x index floor((x - lo) * (1/h)), clamped alike.
+__device__ __forceinline__ uint32_t bin_key(double x, double y, double z, const SlotDesc& d)
 {
-    double f0 = floor((x - d.lo[0]) * d.inv_h);
+    double f0 = floor((x - d.lo[0]) * d.inv_h * (double)XSUB);
     double f1 = floor((y - d.lo[1]) * d.inv_h);
     double f2 = floor((z - d.lo[2]) * d.inv_h);
-    f0 = fmin(fmax(f0, 0.0), (double)(d.nx - 1));
+    f0 = fmin(fmax(f0, 0.0), (double)XSUB * (double)d.nx - 1.0);
     f1 = fmin(fmax(f1, 0.0), (double)(d.ny - 1));
     f2 = fmin(fmax(f2, 0.0), (double)(d.nz - 1));
     uint32_t k0 = (uint32_t)f0, k1 = (uint32_t)f1, k2 = (uint32_t)f2;
-    return k0 + (uint32_t)d.nx * (k1 + (uint32_t)d.ny * k2);
+    return k0 + XSUB * (uint32_t)d.nx * (k1 + (uint32_t)d.ny * k2);
 }
 
 // ------------------------------------------------------------------------ wave / block helpers
@@ -184,11 +192,12 @@ __device__ __forceinline__ void wave_sync()
 
 // ------------------------------------------------------------------------ a1 + a2
 
-// After the previous step's reorder the cells of one voxel are adjacent, so the lanes
-// of a wave fall into a few runs of equal voxel ids and a per-lane atomic would hit the
-// same counter many times over.  One lane per run adds the run's length; the run's
-// lanes take consecutive offsets from the value it gets back.  Which cell of a voxel
-// gets which offset does not matter: a4 orders each voxel's cells by id.
+// After the previous step's reorder the cells of one bin are adjacent, so the lanes of
+// a wave fall into a few runs of equal bins and a per-lane atomic would hit the same
+// counter many times over.  One lane per run adds the run's length; the run's lanes
+// take consecutive offsets from the value it gets back.  Which cell of a bin gets which
+// offset does not matter: a4 orders each bin's cells by id.  vid receives the global
+// bin (XSUB * voxel_off + bin_key).
 __global__ __launch_bounds__(BLOCK) void k_bin(const double* __restrict__ px,
                                                const double* __restrict__ py,
                                                const double* __restrict__ pz,
@@ -209,7 +218,7 @@ __global__ __launch_bounds__(BLOCK) void k_bin(const double* __restrict__ px,
         uint32_t v = 0xffffffffu;
         if (live) {
             const SlotDesc& d = slots[slot_of[s]];
-            v = d.voxel_off + voxel_key(px[s], py[s], pz[s], d);
+            v = XSUB * d.voxel_off + bin_key(px[s], py[s], pz[s], d);
         }
         const uint32_t left = __shfl_up(v, 1, WAVE);
         const bool head = live && (lane == 0 || left != v);
@@ -230,26 +239,29 @@ __global__ __launch_bounds__(BLOCK) void k_bin(const double* __restrict__ px,
 
 // ------------------------------------------------------------------------ a3
 
-// Low 32 bits: cells; high 32 bits: occupied voxels.  Both sums stay below 2^32.
-__device__ __forceinline__ uint64_t pack_count(uint32_t c)
-{
-    return (uint64_t)c | ((uint64_t)(c != 0u) << 32);
-}
+// Scan words: low 32 bits count cells, high 32 bits count occupied voxels; both sums
+// stay below 2^32.
 
+// The scans run over the XSUB * V bins; the high word counts occupied voxels (a voxel
+// is occupied when any of its bins is), flagged at the voxel's first bin.
 __global__ __launch_bounds__(BLOCK) void k_scan_reduce(const uint32_t* __restrict__ count,
                                                        const uint32_t* __restrict__ hdr,
                                                        uint64_t* __restrict__ tsum)
 {
     __shared__ uint64_t sh[BLOCK / WAVE];
-    const uint32_t V = hdr[H_VOXELS];
-    const uint32_t nt = (V + SCAN_TILE - 1) / SCAN_TILE;
+    const uint32_t S = XSUB * hdr[H_VOXELS];
+    const uint32_t nt = (S + SCAN_TILE - 1) / SCAN_TILE;
     for (uint32_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
         const uint32_t base = tile * SCAN_TILE;
         uint64_t acc = 0;
 #pragma unroll
         for (int k = 0; k < SCAN_PER_THREAD; ++k) {
-            uint32_t v = base + k * BLOCK + threadIdx.x;
-            if (v < V) acc += pack_count(count[v]);
+            const uint32_t v = base + k * BLOCK + threadIdx.x;
+            const uint32_t c = v < S ? count[v] : 0u;
+            // the XSUB bins of a voxel are read by XSUB adjacent lanes
+            uint32_t any = c;
+            for (uint32_t o = 1; o < XSUB; o <<= 1) any |= __shfl_xor(any, (int)o, WAVE);
+            acc += (uint64_t)c | ((uint64_t)((threadIdx.x % XSUB) == 0 && any != 0u) << 32);
         }
         acc = wave_sum(acc);
         if ((threadIdx.x & (WAVE - 1)) == 0) sh[threadIdx.x / WAVE] = acc;
@@ -268,8 +280,8 @@ __global__ __launch_bounds__(BLOCK) void k_scan_top(uint64_t* __restrict__ tsum,
                                                     uint32_t* __restrict__ hdr)
 {
     __shared__ uint64_t sh[BLOCK / WAVE];
-    const uint32_t V = hdr[H_VOXELS];
-    const uint32_t nt = (V + SCAN_TILE - 1) / SCAN_TILE;
+    const uint32_t S = XSUB * hdr[H_VOXELS];
+    const uint32_t nt = (S + SCAN_TILE - 1) / SCAN_TILE;
     uint64_t carry = 0;
     for (uint32_t base = 0; base < nt; base += BLOCK) {
         uint32_t i = base + threadIdx.x;
@@ -280,7 +292,7 @@ __global__ __launch_bounds__(BLOCK) void k_scan_top(uint64_t* __restrict__ tsum,
         carry += tot;
     }
     if (threadIdx.x == 0) {
-        voxel_start[V] = (uint32_t)carry;
+        voxel_start[S] = (uint32_t)carry;
         hdr[H_OCC] = (uint32_t)(carry >> 32);
     }
 }
@@ -293,39 +305,50 @@ __global__ __launch_bounds__(BLOCK) void k_scan_down(uint32_t* __restrict__ coun
 {
     __shared__ uint32_t tile[SCAN_TILE];
     __shared__ uint64_t sh[BLOCK / WAVE];
-    const uint32_t V = hdr[H_VOXELS];
-    const uint32_t nt = (V + SCAN_TILE - 1) / SCAN_TILE;
+    const uint32_t S = XSUB * hdr[H_VOXELS];
+    const uint32_t nt = (S + SCAN_TILE - 1) / SCAN_TILE;
     for (uint32_t ti = blockIdx.x; ti < nt; ti += gridDim.x) {
         const uint32_t base = ti * SCAN_TILE;
 #pragma unroll
         for (int k = 0; k < SCAN_PER_THREAD; ++k) {
             uint32_t v = base + k * BLOCK + threadIdx.x;
-            tile[k * BLOCK + threadIdx.x] = v < V ? count[v] : 0u;
+            tile[k * BLOCK + threadIdx.x] = v < S ? count[v] : 0u;
         }
         __syncthreads();
+        // each thread holds whole voxels: bins t*SCAN_PER_THREAD + k
+        const uint32_t* mine = tile + threadIdx.x * SCAN_PER_THREAD;
         uint64_t loc[SCAN_PER_THREAD];
+        bool first_occ[SCAN_PER_THREAD];
         uint64_t sum = 0;
 #pragma unroll
         for (int k = 0; k < SCAN_PER_THREAD; ++k) {
+            bool f = false;
+            if (k % XSUB == 0) {
+                uint32_t any = 0;
+#pragma unroll
+                for (uint32_t m = 0; m < XSUB; ++m) any |= mine[k + m];
+                f = any != 0u;
+            }
+            first_occ[k] = f;
             loc[k] = sum;
-            sum += pack_count(tile[threadIdx.x * SCAN_PER_THREAD + k]);
+            sum += (uint64_t)mine[k] | ((uint64_t)f << 32);
         }
         uint64_t tot;
         uint64_t off = toff[ti] + block_excl_scan(sum, sh, &tot);
 #pragma unroll
         for (int k = 0; k < SCAN_PER_THREAD; ++k) {
             uint32_t v = base + threadIdx.x * SCAN_PER_THREAD + k;
-            if (v < V) {
+            if (v < S) {
                 uint64_t e = off + loc[k];
                 voxel_start[v] = (uint32_t)e;
-                if (tile[threadIdx.x * SCAN_PER_THREAD + k]) occ[(uint32_t)(e >> 32)] = v;
+                if (first_occ[k]) occ[(uint32_t)(e >> 32)] = v / XSUB;
             }
         }
         // the histogram of the next step starts from zero
 #pragma unroll
         for (int k = 0; k < SCAN_PER_THREAD; ++k) {
             uint32_t v = base + k * BLOCK + threadIdx.x;
-            if (v < V) count[v] = 0u;
+            if (v < S) count[v] = 0u;
         }
         __syncthreads();
     }
@@ -368,8 +391,8 @@ struct GatherArgs {
     uint32_t* vid_sorted;
 };
 
-// Segments are short (tens of cells), so each cell counts the smaller ids of its own
-// segment directly; the cost is below that of the force loop over the same cells.
+// Bins are short (a few to tens of cells), so each cell counts the smaller ids of its own
+// bin directly; the cost is below that of the force loop over the same cells.
 template <typename VPT>
 __global__ __launch_bounds__(BLOCK) void k_rank_gather(const uint32_t* __restrict__ hdr, GatherArgs<VPT> a)
 {
@@ -612,7 +635,7 @@ __device__ __forceinline__ void force_rows_cell(const PhysArgs& P, const ForceAr
         if (d.steps_left == 0) {
             hold(a, i);
         } else {
-            const Cellgeo g = cell_geo(a.vid_sorted[i], d);
+            const Cellgeo g = cell_geo(a.vid_sorted[i] / XSUB, d);
             const int ti = MULTI ? a.T[i] : 0;
             double v[3];
             if (PREC == 0) {
@@ -622,7 +645,8 @@ __device__ __forceinline__ void force_rows_cell(const PhysArgs& P, const ForceAr
                 for (int q = 0; q < 9; ++q) {
                     const int64_t r0 = row_first(g, d, q);
                     if (r0 < 0) continue;
-                    const uint32_t b = a.voxel_start[r0], e = a.voxel_start[r0 + (g.x1 - g.x0) + 1];
+                    const uint32_t b = a.voxel_start[XSUB * r0];
+                    const uint32_t e = a.voxel_start[XSUB * (r0 + (g.x1 - g.x0) + 1)];
                     cand += e - b;
                     for (uint32_t j = b; j < e; ++j) {
                         const double c = MULTI ? a.cadh[ti * P.n_types + a.T[j]] : P.c_adh0;
@@ -639,7 +663,8 @@ __device__ __forceinline__ void force_rows_cell(const PhysArgs& P, const ForceAr
                 for (int q = 0; q < 9; ++q) {
                     const int64_t r0 = row_first(g, d, q);
                     if (r0 < 0) continue;
-                    const uint32_t b = a.voxel_start[r0], e = a.voxel_start[r0 + (g.x1 - g.x0) + 1];
+                    const uint32_t b = a.voxel_start[XSUB * r0];
+                    const uint32_t e = a.voxel_start[XSUB * (r0 + (g.x1 - g.x0) + 1)];
                     cand += e - b;
                     for (uint32_t j = b; j < e; ++j) {
                         const float c = MULTI ? a.cadh_f[ti * P.n_types + a.T[j]] : P.c_adh0_f;
@@ -699,7 +724,23 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
     const uint32_t ii = in_pop ? i : n - 1;  // idle lanes mirror the last cell
     const SlotDesc& d = a.slots[a.slot_of[ii]];
     const bool valid = in_pop && d.steps_left != 0;
-    const Cellgeo g = cell_geo(a.vid_sorted[ii], d);
+    const Cellgeo g = cell_geo(a.vid_sorted[ii] / XSUB, d);
+    // The x slabs of each neighbour row that can hold a partner: every interacting j has
+    // |x_j - x_i| < alpha (r_i + r_max).  The window is taken in FP64 from the exact
+    // position and widened by a margin that covers the float rounding of the FP32
+    // decision (a few ulp of |x|) and of R_A, so it never drops a pair either
+    // precision counts.  s0, s1: slot-local slab indices, inside the row's voxels.
+    uint32_t w0, w1;
+    {
+        const double xg = a.XS[0][ii];
+        const double reach = P.alpha * (a.R[ii] + d.r_max);
+        const double m = reach * (1.0 + 1e-6) + 1e-3 + 5e-7 * (fabs(xg) + reach);
+        const double xs = (double)XSUB * d.inv_h;
+        const double lo_s = floor((xg - d.lo[0] - m) * xs), hi_s = floor((xg - d.lo[0] + m) * xs);
+        const double s_min = (double)(XSUB * (uint32_t)g.x0), s_max = (double)(XSUB * (uint32_t)g.x1 + XSUB - 1);
+        w0 = (uint32_t)(fmax(lo_s, s_min) - s_min);            // first slab, from the row's start
+        w1 = (uint32_t)(fmin(hi_s, s_max) - s_min) + 1u;       // one past the last slab
+    }
     Real xi, yi, zi, ri;
     if constexpr (PREC == 0) {
         xi = a.XS[0][ii];
@@ -758,8 +799,8 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
     for (int q = 0; q < 9; ++q) {
         const int64_t r0 = valid ? row_first(g, d, q) : -1;
         if (r0 < 0) continue;
-        uint32_t j = a.voxel_start[r0];
-        const uint32_t e = a.voxel_start[r0 + (g.x1 - g.x0) + 1];
+        uint32_t j = a.voxel_start[XSUB * r0 + w0];
+        const uint32_t e = a.voxel_start[XSUB * r0 + w1];
         cand += e - j;
         if constexpr (PREC == 0) {
             const double* px = a.XS[0] + j;
@@ -886,7 +927,7 @@ __global__ __launch_bounds__(FL_WAVES * WAVE) void k_force_lds(PhysArgs P, Force
     const uint32_t q0 = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * FL_WAVES + w);
     for (uint32_t o = q0; o < M; o += nwaves) {
         const uint32_t vox = __builtin_amdgcn_readfirstlane(occ[o]);
-        const uint32_t vb = a.voxel_start[vox], k = a.voxel_start[vox + 1] - vb;
+        const uint32_t vb = a.voxel_start[XSUB * vox], k = a.voxel_start[XSUB * vox + XSUB] - vb;
         const SlotDesc& d = a.slots[__builtin_amdgcn_readfirstlane(a.slot_of[vb])];
         if (d.steps_left == 0) {
             for (uint32_t t = lane; t < k; t += WAVE) hold(a, vb + t);
@@ -901,8 +942,8 @@ __global__ __launch_bounds__(FL_WAVES * WAVE) void k_force_lds(PhysArgs P, Force
             const int64_t r0 = row_first(g, d, q);
             uint32_t b = 0, e = 0;
             if (r0 >= 0) {
-                b = a.voxel_start[r0];
-                e = a.voxel_start[r0 + (g.x1 - g.x0) + 1];
+                b = a.voxel_start[XSUB * r0];
+                e = a.voxel_start[XSUB * (r0 + (g.x1 - g.x0) + 1)];
             }
             rb[q] = b;
             pre[q + 1] = pre[q] + (e - b);
@@ -1147,11 +1188,11 @@ Layout make_layout(const MechParams& p, int64_t ncap, uint64_t vcap, int32_t sca
     L.tmp_key = take(nn * 4);
     L.tmp_src = take(nn * 4);
     L.vid_sorted = take(nn * 4);
-    L.count = take(vv * 4);
-    L.start = take((vv + 1) * 4);
-    L.occ = take(vv * 4);
+    L.count = take(XSUB * vv * 4);          // per bin
+    L.start = take((XSUB * vv + 1) * 4);    // per bin, plus the total
+    L.occ = take(vv * 4);                   // per voxel
     L.hdr = take(16);
-    L.tsum = take((size_t)blocks_for(vv, SCAN_TILE) * 8);
+    L.tsum = take((size_t)blocks_for(XSUB * vv, SCAN_TILE) * 8);
     L.stats = take(STAT_SLOTS * 16);
     L.cadh = take(64 * 8);
     L.cadh_f = take(64 * 4);
@@ -1205,7 +1246,7 @@ int validate_domain(const double lo[3], const double hi[3], double h, int32_t di
         dims[a] = std::max(1, (int)cells);
         v *= (uint64_t)dims[a];
     }
-    if (v >= (uint64_t(1) << 31)) return fail(MECH_E_INVALID, "grid of %llu voxels is too large", (unsigned long long)v);
+    if (v >= (uint64_t(1) << 30)) return fail(MECH_E_INVALID, "grid of %llu voxels is too large", (unsigned long long)v);
     *V = v;
     return MECH_OK;
 }
@@ -1305,7 +1346,7 @@ void enqueue_binning(MechBatch* B)
     const Layout& L = B->L;
     const int cur = B->parity, nxt = cur ^ 1;
     const uint32_t nbc = cell_grid(B);
-    const uint32_t nbt = std::min<uint32_t>(blocks_for((uint64_t)B->cap_voxels, SCAN_TILE), TILE_GRID_MAX);
+    const uint32_t nbt = std::min<uint32_t>(blocks_for((uint64_t)B->cap_voxels * XSUB, SCAN_TILE), TILE_GRID_MAX);
     const uint32_t* hdr = B->at<uint32_t>(L.hdr);
     hipLaunchKernelGGL(k_bin, dim3(nbc), dim3(BLOCK), 0, B->stream, B->at<double>(L.X[0]),
                        B->at<double>(L.X[1]), B->at<double>(L.X[2]), B->at<uint32_t>(L.slot_of),
@@ -1541,7 +1582,7 @@ int create_batch_impl(const MechParams* params, int64_t max_cells, int64_t max_v
     int rc = validate_physics(params);
     if (rc) return rc;
     if (max_cells < 0 || max_cells >= (int64_t(1) << 31)) return fail(MECH_E_INVALID, "max_cells out of range");
-    if (max_voxels < 1 || max_voxels >= (int64_t(1) << 31)) return fail(MECH_E_INVALID, "max_voxels out of range");
+    if (max_voxels < 1 || max_voxels >= (int64_t(1) << 30)) return fail(MECH_E_INVALID, "max_voxels out of range");
     if (max_slots < 1 || max_slots > 65536) return fail(MECH_E_INVALID, "max_slots out of range");
 
     MechBatch* B = new MechBatch();
@@ -1606,9 +1647,9 @@ int create_batch_impl(const MechParams* params, int64_t max_cells, int64_t max_v
     }
     if (hipMemcpy(B->arena + L.cadh, cd, sizeof cd, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(B->arena + L.cadh_f, cf, sizeof cf, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemsetAsync(B->arena + L.count, 0, (size_t)max_voxels * 4, B->stream) != hipSuccess ||
+        hipMemsetAsync(B->arena + L.count, 0, (size_t)max_voxels * XSUB * 4, B->stream) != hipSuccess ||
         hipMemsetAsync(B->arena + L.stats, 0, STAT_SLOTS * 16, B->stream) != hipSuccess ||
-        hipMemsetAsync(B->arena + L.start, 0, ((size_t)max_voxels + 1) * 4, B->stream) != hipSuccess ||
+        hipMemsetAsync(B->arena + L.start, 0, ((size_t)max_voxels * XSUB + 1) * 4, B->stream) != hipSuccess ||
         hipMemsetAsync(B->arena + L.hdr, 0, 16, B->stream) != hipSuccess ||
         hipMemsetAsync(B->arena + L.slots, 0, (size_t)max_slots * sizeof(SlotDesc), B->stream) != hipSuccess)
         return bail(fail(MECH_E_DEVICE, "arena initialisation failed"));
@@ -1954,7 +1995,9 @@ int64_t batch_bytes(const MechParams* params, int64_t max_cells, int64_t max_vox
 {
     int rc = validate_physics(params);
     if (rc) return rc;
-    if (max_cells < 0 || max_voxels < 1 || max_slots < 1) return fail(MECH_E_INVALID, "bad capacity");
+    if (max_cells < 0 || max_cells >= (int64_t(1) << 31) || max_voxels < 1 || max_voxels >= (int64_t(1) << 30) ||
+        max_slots < 1)
+        return fail(MECH_E_INVALID, "bad capacity");
     return (int64_t)make_layout(*params, max_cells, (uint64_t)max_voxels, max_slots).total;
 }
 
@@ -2093,8 +2136,9 @@ int read_binning(MechPopulation* P, uint32_t* voxel_of_cell, uint32_t* voxel_sta
     if (n > 0) HIP_TRY(hipMemcpy(&m, B->arena + L.hdr + 4 * H_OCC, 4, hipMemcpyDeviceToHost));
     if (n_occ) *n_occ = m;
     if (voxel_start) {
+        // voxel v starts at its first bin, XSUB * v
         if (n > 0)
-            HIP_TRY(hipMemcpy(voxel_start, B->arena + L.start, (V + 1) * 4, hipMemcpyDeviceToHost));
+            HIP_TRY(hipMemcpy2D(voxel_start, 4, B->arena + L.start, 4 * XSUB, 4, V + 1, hipMemcpyDeviceToHost));
         else
             std::memset(voxel_start, 0, (V + 1) * 4);
     }
@@ -2105,7 +2149,7 @@ int read_binning(MechPopulation* P, uint32_t* voxel_of_cell, uint32_t* voxel_sta
     if (sorted_ids) std::memcpy(sorted_ids, ids.data(), n * 4);
     if (voxel_of_cell) {
         HIP_TRY(hipMemcpy(vs.data(), B->arena + L.vid_sorted, n * 4, hipMemcpyDeviceToHost));
-        for (size_t s = 0; s < n; ++s) voxel_of_cell[ids[s]] = vs[s];
+        for (size_t s = 0; s < n; ++s) voxel_of_cell[ids[s]] = vs[s] / XSUB;
     }
     return MECH_OK;
 }

@@ -1,9 +1,10 @@
 """Pins the oracle's binning against numpy floor + lexsort (a library routine).
 
 Binning is integer work and must be bit-exact: voxel of each cell, the exclusive
-prefix of voxel counts, cells ordered by (voxel, id) and the list of occupied voxels.
-Adversarial positions sit exactly on voxel faces, on lo and hi, one ulp either side
-of a face, and at -0.0.
+prefix of voxel counts, cells ordered by (voxel, x slab, id) -- the slab being the
+quarter of the voxel along x that holds the cell -- and the list of occupied voxels.
+Adversarial positions sit exactly on voxel and slab faces, on lo and hi, one ulp
+either side of a face, and at -0.0.
 """
 import numpy as np
 import pytest
@@ -17,8 +18,10 @@ def numpy_bin(lo, hi, h, pos):
     k = np.floor((pos - lo) * (1.0 / h))
     k = np.clip(k, 0, dims - 1).astype(np.int64)
     vid = k[:, 0] + dims[0] * (k[:, 1] + dims[1] * k[:, 2])
+    s4 = np.floor((pos[:, 0] - lo[0]) * (1.0 / h) * 4.0)
+    slab = np.clip(s4, 0, 4 * dims[0] - 1).astype(np.int64) - 4 * k[:, 0]
     V = int(np.prod(dims))
-    order = np.lexsort((np.arange(len(pos)), vid))
+    order = np.lexsort((np.arange(len(pos)), slab, vid))
     start = np.concatenate([[0], np.cumsum(np.bincount(vid, minlength=V))])
     occ = np.unique(vid)
     return vid.astype(np.uint32), start.astype(np.uint32), order.astype(np.uint32), occ.astype(np.uint32)
@@ -27,7 +30,7 @@ def numpy_bin(lo, hi, h, pos):
 def adversarial(n=4000, seed=3):
     lo, hi, h = (-100.0,) * 3, (100.0,) * 3, 30.0
     rng = np.random.default_rng(seed)
-    faces = -100.0 + h * np.arange(0, 8)
+    faces = -100.0 + (h / 4) * np.arange(0, 29)   # voxel and slab faces
     faces = faces[faces <= 100.0]
     vals = np.concatenate([faces, np.nextafter(faces, np.inf), np.nextafter(faces, -np.inf),
                            [-100.0, 100.0, -0.0, 0.0, np.nextafter(100.0, -np.inf)]])
@@ -68,3 +71,14 @@ def test_voxel_numbering_is_x_fastest(orc):
     pos = np.array([[31.0, 1.0, 1.0], [1.0, 31.0, 1.0], [1.0, 1.0, 31.0], [89.0, 89.0, 89.0]])
     vid, _, _, _ = orc.bin(p, pos)
     assert list(vid) == [1, 3, 9, 26]
+
+
+def test_slab_order_inside_a_voxel(orc):
+    """Cells of one voxel are listed by x quarter of the voxel, then by id."""
+    p = orc.params((0.0,) * 3, (90.0,) * 3, h=30.0)
+    x = np.array([29.0, 1.0, 16.0, 7.5, 7.4999, 22.5, 0.0, 15.0])
+    pos = np.stack([x, np.full_like(x, 3.0), np.full_like(x, 3.0)], axis=1)
+    _, start, order, _ = orc.bin(p, pos)
+    # slabs: 29->3, 1->0, 16->2, 7.5->1, 7.4999->0, 22.5->3, 0->0, 15->2
+    assert list(order) == [1, 4, 6, 3, 2, 7, 0, 5]
+    assert start[0] == 0 and start[1] == 8
