@@ -1,6 +1,8 @@
 """Short text summaries of rocprofv3 CSV output (kernel statistics, HBM counters).
 
   python -m paper_2306_11544_amd.rocprof_summary stats <..._kernel_stats.csv> --command "<cmd>"
+  python -m paper_2306_11544_amd.rocprof_summary pmc <counter_collection.csv>... --kernel k_force_cells
+      --command "<cmd of the first csv>" --command ...
   python -m paper_2306_11544_amd.rocprof_summary traffic --fetch <fetch counter_collection.csv>
       --write <write counter_collection.csv> --kernel k_force_cells --copy-kernel neg_kernel
       --copy-bytes <bytes read = bytes written by the copy> --command-fetch "<cmd>" --command-write "<cmd>"
@@ -108,6 +110,26 @@ def traffic(a) -> str:
     return "\n".join(lines) + "\n"
 
 
+def pmc(paths, kernel: str, commands) -> str:
+    """Mean per dispatch of every counter in the counter-collection CSVs, for the
+    dispatches of kernels whose name contains `kernel`."""
+    lines = [f"command: {c}" for c in commands]
+    lines.append(f"source_sha256(csrc/mech.hip): {source_sha256()}")
+    lines.append(f"kernel: {kernel}")
+    for path in paths:
+        acc = collections.defaultdict(lambda: collections.defaultdict(float))
+        name = {}
+        for r in csv.DictReader(open(path)):
+            if kernel not in r["Kernel_Name"]:
+                continue
+            acc[r["Counter_Name"]][r["Dispatch_Id"]] += float(r["Counter_Value"])
+            name[r["Dispatch_Id"]] = r["Kernel_Name"]
+        for counter in sorted(acc):
+            vals = list(acc[counter].values())
+            lines.append(f"{counter}: {sum(vals) / len(vals):.6g}  ({len(vals)} dispatches)")
+    return "\n".join(lines) + "\n"
+
+
 def read_traffic(path: str):
     """(traffic bytes per launch, source sha256, workload, tuning) from a `traffic`
     summary."""
@@ -136,8 +158,17 @@ def main(argv=None):
     t.add_argument("--tuning", default="", help="launch configuration the run used, as K,W,U,G")
     t.add_argument("--command-fetch", required=True)
     t.add_argument("--command-write", required=True)
+    m = sub.add_parser("pmc")
+    m.add_argument("csvs", nargs="+")
+    m.add_argument("--kernel", required=True)
+    m.add_argument("--command", action="append", default=[])
     a = ap.parse_args(argv)
-    sys.stdout.write(stats(a.csv, a.command, a.top) if a.cmd == "stats" else traffic(a))
+    if a.cmd == "stats":
+        sys.stdout.write(stats(a.csv, a.command, a.top))
+    elif a.cmd == "traffic":
+        sys.stdout.write(traffic(a))
+    else:
+        sys.stdout.write(pmc(a.csvs, a.kernel, a.command))
 
 
 if __name__ == "__main__":
