@@ -185,6 +185,46 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_locality(args):
+    """The paper's locality finding on the GPU: force-kernel time when the cells are
+    reordered into voxel order every step (the default), every 10 or 100 steps, or never
+    (left in the order they were given in, which is spatially random).  Binning runs
+    every step in all modes and the trajectories are bitwise the same; only the memory
+    access pattern of the force kernel differs."""
+    import torch
+
+    import workloads
+    from paper_2306_11544_amd import binding as B
+
+    precision = args.precision or {"tumour1m": "fp32k", "sph100k": "fp64",
+                                   "plain1k": "fp64"}[args.workload]
+    pop = workloads.config(args.workload)
+    prm = B.params_of(pop, B.PRECISIONS[precision])
+    torch.cuda.init()
+    modes = {}
+    for every in (1, 10, 100, 0):
+        steps = max(args.steps, 100) if every in (1, 0) else max(args.steps, every)
+        with B.Population(prm, pop.pos, pop.radius, pop.type) as P:
+            P.step(args.warmup)
+            P.set_reorder(every)
+            bin_ms, force_ms = P.profile(steps)
+            _, inter, cand = P.stats()
+        name = "never" if every == 0 else str(every)
+        modes[name] = {"steps": steps, "binning_ms": bin_ms, "force_ms": force_ms,
+                       "step_ms": bin_ms + force_ms}
+        log(f"reorder every {name}: {modes[name]}")
+    out = {
+        "metric": "force-kernel ms per step by reorder interval (locality ablation)",
+        "value": modes["never"]["force_ms"] / modes["1"]["force_ms"],
+        "unit": "slowdown of the force kernel without reordering",
+        "n_gpus": 1, "higher_is_better": False, "data": "synthetic",
+        "config": {"workload": pop.name, "cells": pop.n, "precision": precision,
+                   "warmup": args.warmup},
+        "modes": modes,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -199,6 +239,10 @@ def main():
                     help="force kernel when not tuned: cells | rows | voxel")
     ap.add_argument("--no-tune", dest="tune", action="store_false",
                     help="skip the autotuner (default configuration or --force)")
+    ap.add_argument("--reorder-every", type=int, default=1,
+                    help="reorder the cells every K steps (0: never; the locality study)")
+    ap.add_argument("--locality", action="store_true",
+                    help="run the locality ablation (reorder every 1, 10, 100 steps, never)")
     ap.add_argument("--tuning", default="",
                     help="fixed force-kernel configuration K,W,U,G (kernel flag, waves per "
                          "workgroup, candidates per trip, workgroups per CU); skips the tuner")
@@ -212,6 +256,9 @@ def main():
         sys.exit(2)
     if args.workload == "batch":
         bench_batch(args)
+        return
+    if args.locality:
+        bench_locality(args)
         return
 
     import torch
@@ -244,6 +291,8 @@ def main():
                      "force_ms_chosen": min(r["force_ms"] for r in rows),
                      "force_ms_default": default_ms, "seconds": time.perf_counter() - t0}
         log(f"autotuner: {tune_info}")
+    if args.reorder_every != 1:
+        P.set_reorder(args.reorder_every)
     tuning = P.get_tuning().as_dict()
     kname = {0: "k_force_cells", B.MECH_FLAG_SIMPLE_FORCE: "k_force_rows",
              B.MECH_FLAG_VOXEL_FORCE: "k_force_lds"}[tuning["force_kernel"]]
@@ -315,7 +364,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": pop.name, "cells": pop.n, "precision": precision,
                    "voxel_um": pop.voxel, "dt_min": pop.dt,
-                   "integration": "f64 two-step Adams-Bashforth", "tuning": tuning},
+                   "integration": "f64 two-step Adams-Bashforth", "tuning": tuning,
+                   "reorder_every": args.reorder_every},
         "autotuner": tune_info,
         "cell_steps_per_s": cell_steps,
         "candidates_per_s": cand / elapsed_s,

@@ -178,6 +178,17 @@ int read_stats(MechPopulation* pop, int64_t* steps, int64_t* interactions,
  * Synchronises.  For tuning and roofline measurement. */
 int profile_step(MechPopulation* pop, int64_t n_steps, double* phase_ms);
 
+/* Locality study (the paper's finding that cells stored far from their neighbours slow
+ * the velocity update, Section 5.4): every >= 1 reorders the cells into voxel order
+ * every `every` steps (1, the default, reorders every step); between reorders the cells
+ * stay where they are and the force kernel reads the candidates through the sorted
+ * index.  every = 0 first puts the cells back in the order they were given in (their
+ * ids) and never reorders them.  Binning still runs every step, and the results are
+ * bitwise those of reordering every step (same candidates, order and arithmetic); only
+ * the memory access pattern changes.  Waits for the stream; MECH_E_INVALID if
+ * every < 0. */
+int population_set_reorder(MechPopulation* pop, int32_t every);
+
 /* Current force-kernel launch configuration of a population, and a replacement for
  * it (validated: MECH_E_INVALID for a value outside the ranges of MechTuning).  Setting
  * waits for the stream; the step graph is captured again on the next step. */

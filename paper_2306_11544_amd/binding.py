@@ -32,7 +32,7 @@ PRECISIONS = {"fp64": MECH_FP64, "fp32": MECH_FP32, "fp32k": MECH_FP32_KAHAN}
 EXPORTS = ("mech_last_error", "mech_abi_version", "mech_device_count",
            "population_workspace_bytes", "create_population", "create_population_in",
            "step_mechanics", "read_state", "read_binning", "read_stats", "profile_step",
-           "population_get_tuning", "population_set_tuning",
+           "population_set_reorder", "population_get_tuning", "population_set_tuning",
            "population_info", "population_stream", "destroy_population",
            "batch_workspace_bytes", "batch_request_voxels", "create_batch", "create_batch_in",
            "batch_admit", "batch_step", "batch_poll", "batch_read", "batch_retire",
@@ -100,6 +100,7 @@ def lib():
             "read_binning": (C.c_int, [vp, up, up, up, up, lp, lp]),
             "read_stats": (C.c_int, [vp, lp, lp, lp]),
             "profile_step": (C.c_int, [vp, C.c_int64, dp]),
+            "population_set_reorder": (C.c_int, [vp, C.c_int32]),
             "population_get_tuning": (C.c_int, [vp, P(MechTuning)]),
             "population_set_tuning": (C.c_int, [vp, P(MechTuning)]),
             "population_info": (C.c_int, [vp, lp, ip]),
@@ -303,6 +304,11 @@ class Population:
 
     def profile(self, n_steps=1):
         return profile_step(self.h, n_steps)
+
+    def set_reorder(self, every: int):
+        """Reorder the cells every `every` steps (1: every step); 0: never, cells in id
+        order (the locality study)."""
+        _ck(lib().population_set_reorder(self.h, int(every)))
 
     def get_tuning(self) -> MechTuning:
         t = MechTuning()

@@ -420,6 +420,84 @@ __global__ __launch_bounds__(BLOCK) void k_rank_gather(const uint32_t* __restric
     }
 }
 
+// Cells left in place (the locality study): a4 only.  perm[slot] = storage index of the
+// cell that the sorted order puts in that slot (the same (bin, id) order as a4 + a5).
+__global__ __launch_bounds__(BLOCK) void k_rank_perm(const uint32_t* __restrict__ hdr,
+                                                     const uint32_t* __restrict__ vid_cur,
+                                                     const uint32_t* __restrict__ tmp_key,
+                                                     const uint32_t* __restrict__ tmp_src,
+                                                     const uint32_t* __restrict__ voxel_start,
+                                                     uint32_t* __restrict__ perm)
+{
+    const uint32_t n = hdr[H_CELLS];
+    for (uint32_t p = blockIdx.x * BLOCK + threadIdx.x; p < n; p += gridDim.x * BLOCK) {
+        const uint32_t s = tmp_src[p];
+        const uint32_t key = tmp_key[p];
+        const uint32_t v = vid_cur[s];
+        const uint32_t b = voxel_start[v], e = voxel_start[v + 1];
+        uint32_t rank = 0;
+        for (uint32_t q = b; q < e; ++q) rank += tmp_key[q] < key;
+        perm[b + rank] = s;
+    }
+}
+
+// Cells left in place: the new positions, written beside the old ones, become current.
+__global__ __launch_bounds__(BLOCK) void k_commit(const uint32_t* __restrict__ hdr, const double* __restrict__ a0,
+                                                  const double* __restrict__ a1, const double* __restrict__ a2,
+                                                  double* __restrict__ b0, double* __restrict__ b1,
+                                                  double* __restrict__ b2)
+{
+    const uint32_t n = hdr[H_CELLS];
+    for (uint32_t s = blockIdx.x * BLOCK + threadIdx.x; s < n; s += gridDim.x * BLOCK) {
+        b0[s] = a0[s];
+        b1[s] = a1[s];
+        b2[s] = a2[s];
+    }
+}
+
+// Cells left in place: the float shadow of the positions, in storage order.
+__global__ __launch_bounds__(BLOCK) void k_shadow(const uint32_t* __restrict__ hdr, const double* __restrict__ x0,
+                                                  const double* __restrict__ x1, const double* __restrict__ x2,
+                                                  const double* __restrict__ r, float4* __restrict__ sh)
+{
+    const uint32_t n = hdr[H_CELLS];
+    for (uint32_t s = blockIdx.x * BLOCK + threadIdx.x; s < n; s += gridDim.x * BLOCK)
+        sh[s] = make_float4((float)x0[s], (float)x1[s], (float)x2[s], (float)r[s]);
+}
+
+// Before the cells are left in place: put them in id order (the order they were given
+// in), with the state in the other buffer of each pair and the positions in XS.
+template <typename VPT>
+struct OrderArgs {
+    const double* X[3];
+    double* XS[3];
+    const double* R_cur;
+    double* R_new;
+    const int32_t* T_cur;
+    int32_t* T_new;
+    const uint32_t* ID_cur;
+    uint32_t* ID_new;
+    const VPT* VP_cur[3];
+    VPT* VP_new[3];
+};
+
+template <typename VPT>
+__global__ __launch_bounds__(BLOCK) void k_order_by_id(const uint32_t* __restrict__ hdr, OrderArgs<VPT> a)
+{
+    const uint32_t n = hdr[H_CELLS];
+    for (uint32_t p = blockIdx.x * BLOCK + threadIdx.x; p < n; p += gridDim.x * BLOCK) {
+        const uint32_t d = a.ID_cur[p];  // global id: cell_off + index given at admission
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            a.XS[c][d] = a.X[c][p];
+            a.VP_new[c][d] = a.VP_cur[c][p];
+        }
+        a.R_new[d] = a.R_cur[p];
+        a.T_new[d] = a.T_cur[p];
+        a.ID_new[d] = d;
+    }
+}
+
 __global__ __launch_bounds__(BLOCK) void k_copy_positions(uint32_t n, const double* __restrict__ a0,
                                                           const double* __restrict__ a1,
                                                           const double* __restrict__ a2,
@@ -458,6 +536,7 @@ struct ForceArgs {
     const float* cadh_f;       // n_types^2 (FP32)
     VPT* VP[3];                // read v_prev, write v (in place, own element)
     double* X[3];              // new positions
+    const uint32_t* perm;      // cells left in place: storage index of each sorted slot
     unsigned long long* stats; // STAT_SLOTS pairs (interactions, candidates)
 };
 
@@ -714,7 +793,10 @@ constexpr int FC_LIST = 16;    // listed candidates a lane holds before a flush
 // pair term of pair64 / pair32, in candidate order, so each sum is still taken in the
 // fixed neighbour order and the rare interacting pairs do not make the wave diverge.
 // Lanes of one voxel read the same candidate at the same time (one cache line).
-template <int PREC, bool MULTI, typename VPT, int FC_UNROLL>
+// IND: the cells are left in storage order; candidate slot j of the sorted order is read
+// through perm[j] (the locality study).  The candidates, their order and the arithmetic
+// are those of the reordered path, so the results are bitwise the same.
+template <int PREC, bool MULTI, typename VPT, int FC_UNROLL, bool IND = false>
 __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceArgs<VPT>& a, uint32_t i,
                                                  uint32_t n, uint32_t* const list0, uint32_t& inter,
                                                  uint32_t& cand)
@@ -802,6 +884,25 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
         uint32_t j = a.voxel_start[XSUB * r0 + w0];
         const uint32_t e = a.voxel_start[XSUB * r0 + w1];
         cand += e - j;
+        if constexpr (IND) {
+            // gathers through the sorted order: no locality between consecutive lanes
+            for (; j < e; ++j) {
+                const uint32_t jj = a.perm[j];
+                bool in;
+                if constexpr (PREC == 0) {
+                    in = near(a.XS[0][jj], a.XS[1][jj], a.XS[2][jj]);
+                } else {
+                    const float4 c = a.SH[jj];
+                    in = near(c.x, c.y, c.z);
+                }
+                if (in) {
+                    *lp = jj;
+                    lp += WAVE;
+                }
+                if (__any(lp > list_hi)) flush();
+            }
+            continue;
+        }
         if constexpr (PREC == 0) {
             const double* px = a.XS[0] + j;
             const double* py = a.XS[1] + j;
@@ -865,7 +966,7 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
     }
 }
 
-template <int PREC, bool MULTI, typename VPT, int WPB, int UNROLL>
+template <int PREC, bool MULTI, typename VPT, int WPB, int UNROLL, bool IND = false>
 __global__ __launch_bounds__(WPB * WAVE) void k_force_cells(PhysArgs P, ForceArgs<VPT> a)
 {
     static_assert(2 * UNROLL <= FC_LIST, "a trip must fit the list above the flush mark");
@@ -880,7 +981,7 @@ __global__ __launch_bounds__(WPB * WAVE) void k_force_cells(PhysArgs P, ForceArg
         const uint32_t active = min(gridDim.x, nb - lb0);
         if (blockIdx.x >= active) break;
         const uint32_t i = (lb0 + xcd_block(blockIdx.x, active)) * TB + threadIdx.x;
-        force_cells_cell<PREC, MULTI, VPT, UNROLL>(P, a, i, n, list0, inter, cand);
+        force_cells_cell<PREC, MULTI, VPT, UNROLL, IND>(P, a, i, n, list0, inter, cand);
     }
     add_stats(a.stats, inter, cand);
 }
@@ -1313,8 +1414,13 @@ struct MechBatch {
     int64_t steps = 0;
     int32_t cus = 256;                    // compute units of the device
     MechTuning tune{0, 4, 4, 0};          // force-kernel launch configuration
+    // locality study: reorder (gather) every reorder_every steps, 0 = never
+    int32_t reorder_every = 1;
+    int64_t reorder_phase = 0;            // steps since the mode was set
+    bool last_gather = true;              // the last binning reordered the cells
     bool graphs_ready = false;
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    hipGraphExec_t gexec_inplace[2] = {nullptr, nullptr};
 
     template <typename T>
     T* at(size_t off) const { return reinterpret_cast<T*>(arena + off); }
@@ -1340,11 +1446,11 @@ uint32_t cell_grid(const MechBatch* B)
     return std::max<uint32_t>(1, std::min<uint32_t>(blocks_for((uint64_t)B->cap_cells, BLOCK), CELL_GRID_MAX));
 }
 
-template <typename VPT>
-void enqueue_binning(MechBatch* B)
+// a1..a3 and the scatter of a4 (sorted slots of the cells, before the rank by id)
+void enqueue_keys(MechBatch* B)
 {
     const Layout& L = B->L;
-    const int cur = B->parity, nxt = cur ^ 1;
+    const int cur = B->parity;
     const uint32_t nbc = cell_grid(B);
     const uint32_t nbt = std::min<uint32_t>(blocks_for((uint64_t)B->cap_voxels * XSUB, SCAN_TILE), TILE_GRID_MAX);
     const uint32_t* hdr = B->at<uint32_t>(L.hdr);
@@ -1361,6 +1467,16 @@ void enqueue_binning(MechBatch* B)
     hipLaunchKernelGGL(k_scatter, dim3(nbc), dim3(BLOCK), 0, B->stream, hdr, B->at<uint32_t>(L.vid_cur),
                        B->at<uint32_t>(L.off), B->at<uint32_t>(L.start), B->at<uint32_t>(L.ID[cur]),
                        B->at<uint32_t>(L.tmp_key), B->at<uint32_t>(L.tmp_src));
+}
+
+template <typename VPT>
+void enqueue_binning(MechBatch* B)
+{
+    const Layout& L = B->L;
+    const int cur = B->parity, nxt = cur ^ 1;
+    const uint32_t nbc = cell_grid(B);
+    const uint32_t* hdr = B->at<uint32_t>(L.hdr);
+    enqueue_keys(B);
     GatherArgs<VPT> g{};
     for (int c = 0; c < 3; ++c) {
         g.X[c] = B->at<double>(L.X[c]);
@@ -1495,21 +1611,99 @@ void enqueue_force_any(MechBatch* B, int parity_after_sort)
     }
 }
 
+// ------------------------------------------------------------------------ cells left in place
+
+// The locality study: binning as usual, but the cells stay in their storage order; the
+// force kernel takes the cells in that order and reads the candidates of the sorted
+// order through perm (which aliases `off`, free once a4's scatter has used it).
+template <int PREC, typename VPT>
+void enqueue_force_inplace(MechBatch* B)
+{
+    const Layout& L = B->L;
+    const int cur = B->parity;
+    ForceArgs<VPT> a{};
+    for (int c = 0; c < 3; ++c) {
+        a.XS[c] = B->at<double>(L.X[c]);   // positions, storage order
+        a.X[c] = B->at<double>(L.XS[c]);   // new positions, storage order
+        a.VP[c] = B->at<VPT>(L.VP[cur][c]);
+    }
+    a.R = B->at<double>(L.R[cur]);
+    a.T = B->at<int32_t>(L.T[cur]);
+    a.SH = is_fp32(B->prm) ? B->at<float4>(L.SH) : nullptr;
+    a.vid_sorted = B->at<uint32_t>(L.vid_cur);
+    a.voxel_start = B->at<uint32_t>(L.start);
+    a.slot_of = B->at<uint32_t>(L.slot_of);
+    a.slots = B->at<SlotDesc>(L.slots);
+    a.hdr = B->at<uint32_t>(L.hdr);
+    a.cadh = B->at<double>(L.cadh);
+    a.cadh_f = B->at<float>(L.cadh_f);
+    a.stats = B->at<unsigned long long>(L.stats);
+    a.perm = B->at<uint32_t>(L.off);
+    const dim3 grid(force_cell_grid(B, 4)), block(4 * WAVE);
+    if (B->prm.n_types > 1)
+        hipLaunchKernelGGL((k_force_cells<PREC, true, VPT, 4, 4, true>), grid, block, 0, B->stream, B->phys, a);
+    else
+        hipLaunchKernelGGL((k_force_cells<PREC, false, VPT, 4, 4, true>), grid, block, 0, B->stream, B->phys, a);
+}
+
+// a1..a4 without the reorder: keys, scan, scatter, perm (and the float shadow first).
+void enqueue_binning_inplace(MechBatch* B)
+{
+    const Layout& L = B->L;
+    const int cur = B->parity;
+    const uint32_t nbc = cell_grid(B);
+    const uint32_t* hdr = B->at<uint32_t>(L.hdr);
+    if (is_fp32(B->prm))
+        hipLaunchKernelGGL(k_shadow, dim3(nbc), dim3(BLOCK), 0, B->stream, hdr, B->at<double>(L.X[0]),
+                           B->at<double>(L.X[1]), B->at<double>(L.X[2]), B->at<double>(L.R[cur]),
+                           B->at<float4>(L.SH));
+    enqueue_keys(B);
+    hipLaunchKernelGGL(k_rank_perm, dim3(nbc), dim3(BLOCK), 0, B->stream, hdr, B->at<uint32_t>(L.vid_cur),
+                       B->at<uint32_t>(L.tmp_key), B->at<uint32_t>(L.tmp_src), B->at<uint32_t>(L.start),
+                       B->at<uint32_t>(L.off));
+}
+
+void enqueue_force_inplace_any(MechBatch* B)
+{
+    const Layout& L = B->L;
+    switch (B->prm.precision) {
+    case MECH_FP64: enqueue_force_inplace<0, double>(B); break;
+    case MECH_FP32: enqueue_force_inplace<1, float>(B); break;
+    default: enqueue_force_inplace<2, float>(B); break;
+    }
+    hipLaunchKernelGGL(k_commit, dim3(cell_grid(B)), dim3(BLOCK), 0, B->stream, B->at<uint32_t>(L.hdr),
+                       B->at<double>(L.XS[0]), B->at<double>(L.XS[1]), B->at<double>(L.XS[2]),
+                       B->at<double>(L.X[0]), B->at<double>(L.X[1]), B->at<double>(L.X[2]));
+}
+
 void enqueue_step_end(MechBatch* B)
 {
     hipLaunchKernelGGL(k_step_end, dim3(blocks_for((uint64_t)B->cap_slots, BLOCK)), dim3(BLOCK), 0, B->stream,
                        B->at<SlotDesc>(B->L.slots), (uint32_t)B->cap_slots);
 }
 
-// One full step a1..a7 from `parity`; flips nothing on the host.
-void enqueue_step(MechBatch* B, int parity)
+// One full step a1..a7 from `parity`; flips nothing on the host.  gather: reorder the
+// cells (the default); otherwise leave them in place (the step keeps the parity).
+void enqueue_step(MechBatch* B, int parity, bool gather = true)
 {
     const int saved = B->parity;
     B->parity = parity;
-    enqueue_binning_any(B);
-    enqueue_force_any(B, parity ^ 1);
+    if (gather) {
+        enqueue_binning_any(B);
+        enqueue_force_any(B, parity ^ 1);
+    } else {
+        enqueue_binning_inplace(B);
+        enqueue_force_inplace_any(B);
+    }
     enqueue_step_end(B);
     B->parity = saved;
+}
+
+bool gather_now(const MechBatch* B)
+{
+    if (B->reorder_every == 1) return true;
+    if (B->reorder_every == 0) return false;
+    return B->reorder_phase % B->reorder_every == 0;
 }
 
 int sync_check(MechBatch* B)
@@ -1521,26 +1715,36 @@ int sync_check(MechBatch* B)
 
 int drop_graphs(MechBatch* B)
 {
-    for (int p = 0; p < 2; ++p)
+    for (int p = 0; p < 2; ++p) {
         if (B->gexec[p]) {
             (void)hipGraphExecDestroy(B->gexec[p]);
             B->gexec[p] = nullptr;
         }
+        if (B->gexec_inplace[p]) {
+            (void)hipGraphExecDestroy(B->gexec_inplace[p]);
+            B->gexec_inplace[p] = nullptr;
+        }
+    }
     B->graphs_ready = false;
     return MECH_OK;
 }
 
+// One graph per parity for reordering steps and, when cells may be left in place, one
+// per parity for those steps.
 int build_graphs(MechBatch* B)
 {
-    for (int p = 0; p < 2; ++p) {
-        hipGraph_t g = nullptr;
-        HIP_TRY(hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal));
-        enqueue_step(B, p);
-        hipError_t e = hipStreamEndCapture(B->stream, &g);
-        if (e != hipSuccess) return fail(MECH_E_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
-        e = hipGraphInstantiate(&B->gexec[p], g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        if (e != hipSuccess) return fail(MECH_E_DEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
+    for (int kind = 0; kind < 2; ++kind) {
+        if (kind == 1 && B->reorder_every == 1) break;
+        for (int p = 0; p < 2; ++p) {
+            hipGraph_t g = nullptr;
+            HIP_TRY(hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal));
+            enqueue_step(B, p, kind == 0);
+            hipError_t e = hipStreamEndCapture(B->stream, &g);
+            if (e != hipSuccess) return fail(MECH_E_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
+            e = hipGraphInstantiate(kind == 0 ? &B->gexec[p] : &B->gexec_inplace[p], g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) return fail(MECH_E_DEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
+        }
     }
     B->graphs_ready = true;
     return MECH_OK;
@@ -1860,37 +2064,50 @@ int admit_impl(MechBatch* B, const double lo[3], const double hi[3], int64_t n, 
     return MECH_OK;
 }
 
+// Host side of a step: parity, the host mirror of the device counters, and the event
+// that marks the step at which a slot froze.
+int after_step(MechBatch* B, bool gather)
+{
+    if (B->n_cells > 0) {
+        if (gather) B->parity ^= 1;
+        B->last_gather = gather;
+    }
+    ++B->reorder_phase;
+    for (int32_t id : B->order) {
+        HostSlot& s = B->slots[id];
+        s.d.euler = 0;
+        if (s.d.steps_left > 0 && --s.d.steps_left == 0 && !s.done_recorded) {
+            HIP_TRY(hipEventRecord(s.done, B->stream));
+            s.done_recorded = true;
+        }
+    }
+    ++B->steps;
+    return MECH_OK;
+}
+
 int step_impl(MechBatch* B, int64_t n_steps)
 {
     if (n_steps < 0) return fail(MECH_E_INVALID, "n_steps must be >= 0");
     HIP_TRY(hipSetDevice(B->device));
     const bool eager = (B->prm.flags & MECH_FLAG_NO_GRAPH) != 0;
     for (int64_t k = 0; k < n_steps; ++k) {
+        const bool gather = gather_now(B);
         if (B->n_cells > 0) {
             if (eager) {
-                enqueue_step(B, B->parity);
+                enqueue_step(B, B->parity, gather);
             } else {
                 if (!B->graphs_ready) {
                     int rc = build_graphs(B);
                     if (rc) return rc;
                 }
-                HIP_TRY(hipGraphLaunch(B->gexec[B->parity], B->stream));
+                HIP_TRY(hipGraphLaunch(gather ? B->gexec[B->parity] : B->gexec_inplace[B->parity], B->stream));
             }
-            B->parity ^= 1;
         } else {
             enqueue_step_end(B);  // keeps the device step counters in line with the host's
         }
         HIP_TRY(hipGetLastError());
-        // host mirror of the device counters; mark the step at which a slot froze
-        for (int32_t id : B->order) {
-            HostSlot& s = B->slots[id];
-            s.d.euler = 0;
-            if (s.d.steps_left > 0 && --s.d.steps_left == 0 && !s.done_recorded) {
-                HIP_TRY(hipEventRecord(s.done, B->stream));
-                s.done_recorded = true;
-            }
-        }
-        ++B->steps;
+        int rc = after_step(B, gather);
+        if (rc) return rc;
     }
     return MECH_OK;
 }
@@ -1960,23 +2177,21 @@ int profile_impl(MechBatch* B, int64_t n_steps, double* phase_ms)
     int rc = MECH_OK;
     for (int64_t s = 0; s < n_steps && rc == MECH_OK; ++s) {
         const int p = B->parity;
+        const bool gather = gather_now(B);
         (void)hipEventRecord(ev[0], B->stream);
-        enqueue_binning_any(B);
+        if (gather)
+            enqueue_binning_any(B);
+        else
+            enqueue_binning_inplace(B);
         (void)hipEventRecord(ev[1], B->stream);
-        enqueue_force_any(B, p ^ 1);
+        if (gather)
+            enqueue_force_any(B, p ^ 1);
+        else
+            enqueue_force_inplace_any(B);
         (void)hipEventRecord(ev[2], B->stream);
         enqueue_step_end(B);
-        B->parity ^= 1;
-        for (int32_t id : B->order) {
-            HostSlot& h = B->slots[id];
-            h.d.euler = 0;
-            if (h.d.steps_left > 0 && --h.d.steps_left == 0 && !h.done_recorded) {
-                (void)hipEventRecord(h.done, B->stream);
-                h.done_recorded = true;
-            }
-        }
-        ++B->steps;
-        rc = sync_check(B);
+        rc = after_step(B, gather);
+        if (rc == MECH_OK) rc = sync_check(B);
         float t0 = 0.f, t1 = 0.f;
         if (rc == MECH_OK && (hipEventElapsedTime(&t0, ev[0], ev[1]) != hipSuccess ||
                               hipEventElapsedTime(&t1, ev[1], ev[2]) != hipSuccess))
@@ -2144,6 +2359,19 @@ int read_binning(MechPopulation* P, uint32_t* voxel_of_cell, uint32_t* voxel_sta
     }
     if (occ && m) HIP_TRY(hipMemcpy(occ, B->arena + L.occ, (size_t)m * 4, hipMemcpyDeviceToHost));
     if (n == 0) return MECH_OK;
+    if (!B->last_gather) {
+        // cells left in place: storage order is not the sorted order; perm maps one to
+        // the other
+        std::vector<uint32_t> perm(n), ids(n), vc(n);
+        HIP_TRY(hipMemcpy(perm.data(), B->arena + L.off, n * 4, hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(ids.data(), B->arena + L.ID[B->parity], n * 4, hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(vc.data(), B->arena + L.vid_cur, n * 4, hipMemcpyDeviceToHost));
+        if (sorted_ids)
+            for (size_t q = 0; q < n; ++q) sorted_ids[q] = ids[perm[q]];
+        if (voxel_of_cell)
+            for (size_t q = 0; q < n; ++q) voxel_of_cell[ids[q]] = vc[q] / XSUB;
+        return MECH_OK;
+    }
     std::vector<uint32_t> ids(n), vs(n);
     HIP_TRY(hipMemcpy(ids.data(), B->arena + L.ID[B->parity], n * 4, hipMemcpyDeviceToHost));
     if (sorted_ids) std::memcpy(sorted_ids, ids.data(), n * 4);
@@ -2158,6 +2386,55 @@ int read_stats(MechPopulation* P, int64_t* steps, int64_t* interactions, int64_t
 {
     if (!P) return fail(MECH_E_INVALID, "population is NULL");
     return stats_impl(P->b, steps, interactions, candidates);
+}
+
+int population_set_reorder(MechPopulation* P, int32_t every)
+{
+    if (!P) return fail(MECH_E_INVALID, "population is NULL");
+    if (every < 0) return fail(MECH_E_INVALID, "every must be >= 0");
+    MechBatch* B = P->b;
+    HIP_TRY(hipSetDevice(B->device));
+    HIP_TRY(hipStreamSynchronize(B->stream));
+    drop_graphs(B);
+    if (every == 0 && B->n_cells > 0) {
+        // back to the order the cells were given in, then binned where they are
+        const Layout& L = B->L;
+        const int cur = B->parity, nxt = cur ^ 1;
+        const uint32_t nbc = cell_grid(B);
+        const uint32_t* hdr = B->at<uint32_t>(L.hdr);
+        auto order = [&](auto tag) {
+            using VPT = decltype(tag);
+            OrderArgs<VPT> o{};
+            for (int c = 0; c < 3; ++c) {
+                o.X[c] = B->at<double>(L.X[c]);
+                o.XS[c] = B->at<double>(L.XS[c]);
+                o.VP_cur[c] = B->at<VPT>(L.VP[cur][c]);
+                o.VP_new[c] = B->at<VPT>(L.VP[nxt][c]);
+            }
+            o.R_cur = B->at<double>(L.R[cur]);
+            o.R_new = B->at<double>(L.R[nxt]);
+            o.T_cur = B->at<int32_t>(L.T[cur]);
+            o.T_new = B->at<int32_t>(L.T[nxt]);
+            o.ID_cur = B->at<uint32_t>(L.ID[cur]);
+            o.ID_new = B->at<uint32_t>(L.ID[nxt]);
+            hipLaunchKernelGGL(k_order_by_id<VPT>, dim3(nbc), dim3(BLOCK), 0, B->stream, hdr, o);
+        };
+        if (is_fp32(B->prm))
+            order(float{});
+        else
+            order(double{});
+        hipLaunchKernelGGL(k_commit, dim3(nbc), dim3(BLOCK), 0, B->stream, hdr, B->at<double>(L.XS[0]),
+                           B->at<double>(L.XS[1]), B->at<double>(L.XS[2]), B->at<double>(L.X[0]),
+                           B->at<double>(L.X[1]), B->at<double>(L.X[2]));
+        B->parity = nxt;
+        enqueue_binning_inplace(B);
+        B->last_gather = false;
+        int rc = sync_check(B);
+        if (rc) return rc;
+    }
+    B->reorder_every = every;
+    B->reorder_phase = 0;
+    return MECH_OK;
 }
 
 int population_get_tuning(MechPopulation* P, MechTuning* out)

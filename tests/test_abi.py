@@ -60,6 +60,7 @@ def test_tuning_search_space_is_valid():
 
 
 def test_tuning_calls_reject_null_handles():
+    assert B.lib().population_set_reorder(None, 1) == B.MECH_E_INVALID
     t = B.tuning()
     assert B.lib().batch_set_tuning(None, C.byref(t)) == B.MECH_E_INVALID
     assert B.lib().population_get_tuning(None, C.byref(t)) == B.MECH_E_INVALID
