@@ -27,7 +27,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mech_oracle.c")
-_LIB = os.path.join(_HERE, "libmech_oracle.so")
+# Another build of the oracle can be loaded instead by naming it in MECH_ORACLE_LIB: the
+# test that plants mistakes in copies of mech_oracle.c runs the pins against them.
+_LIB = os.environ.get("MECH_ORACLE_LIB") or os.path.join(_HERE, "libmech_oracle.so")
 
 FP64, FP32, FP32_KAHAN = 0, 1, 2
 
@@ -40,13 +42,19 @@ class OracleParams(C.Structure):
 
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (OpenMP over cells; no fast-math, no contraction)."""
+    if os.environ.get("MECH_ORACLE_LIB"):
+        return _LIB
     if force or not os.path.exists(_LIB):
-        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
-               "-fno-fast-math", "-Wall", "-Wextra", "-Wno-unused-parameter", _SRC, "-o",
-               _LIB + ".tmp", "-lm"]
-        subprocess.run(cmd, check=True)
-        os.replace(_LIB + ".tmp", _LIB)
+        compile_to(_SRC, _LIB)
     return _LIB
+
+
+def compile_to(src: str, out: str) -> None:
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+           "-fno-fast-math", "-Wall", "-Wextra", "-Wno-unused-parameter", src, "-o",
+           out + ".tmp", "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(out + ".tmp", out)
 
 
 _lib = None

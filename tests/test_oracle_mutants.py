@@ -1,0 +1,109 @@
+"""The oracle's pins catch plausible mistakes.
+
+Each mutant is a copy of oracle/mech_oracle.c with one mistake planted: a dropped term,
+a wrong sign, a wrong index, an off-by-one, a wrong tie-break.  The copy is compiled on
+the CPU and the oracle's pin tests are run against it in a child process (through
+MECH_ORACLE_LIB); at least one pin must fail.  The mutants never leave the CPU.
+"""
+import os
+import subprocess
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "mech_oracle.c")
+PINS = ["tests/test_oracle_closed_form.py", "tests/test_oracle_invariants.py",
+        "tests/test_oracle_bruteforce.py", "tests/test_oracle_binning.py", "tests/test_kahan.py"]
+
+# (name, text in mech_oracle.c, replacement); each text occurs exactly once
+MUTANTS = [
+    ("repulsion sign",
+     "        w += p->c_rep * u * u;", "        w -= p->c_rep * u * u;"),
+    ("adhesion dropped",
+     "    w -= p->c_adh[ti * p->n_types + tj] * a * a;\n    double s", "    double s"),
+    ("adhesion matrix index",
+     "    w -= p->c_adh[ti * p->n_types + tj] * a * a;\n    double s",
+     "    w -= p->c_adh[ti * p->n_types + ti] * a * a;\n    double s"),
+    ("adhesion distance without alpha",
+     "    double RA = p->alpha * R;", "    double RA = R;"),
+    ("repulsion cutoff at R_A",
+     "    double w = 0.0;\n    if (d < R) {", "    double w = 0.0;\n    if (d < RA) {"),
+    ("force direction on one axis",
+     "    acc[0] += s * dx;", "    acc[0] -= s * dx;"),
+    ("coincident cells not skipped",
+     "    if (!(d2 > 0.0 && d2 < RA * RA)) return 0;", "    if (!(d2 < RA * RA)) return 0;"),
+    ("Adams-Bashforth weight sign",
+     "(1.5 * v - 0.5 * vp)", "(1.5 * v + 0.5 * vp)"),
+    ("Euler start ignored",
+     "double vp = euler_start ? v : vprev[3 * i + c];", "double vp = vprev[3 * i + c];"),
+    ("upper wall clamps instead of mirroring",
+     "    if (x > hi) x = 2.0 * hi - x;", "    if (x > hi) x = hi;"),
+    ("neighbour voxels on one side only",
+     "        memset(&accf, 0, sizeof accf);\n        for (int dz = -1; dz <= 1; ++dz)\n"
+     "            for (int dy = -1; dy <= 1; ++dy)\n                for (int dx = -1; dx <= 1; ++dx) {",
+     "        memset(&accf, 0, sizeof accf);\n        for (int dz = -1; dz <= 1; ++dz)\n"
+     "            for (int dy = -1; dy <= 1; ++dy)\n                for (int dx = -1; dx <= 0; ++dx) {"),
+    ("voxel numbering y fastest",
+     "    return k[0] + (int64_t)dims[0] * (k[1] + (int64_t)dims[1] * k[2]);",
+     "    return k[1] + (int64_t)dims[1] * (k[0] + (int64_t)dims[0] * k[2]);"),
+    ("x slab ignored",
+     "    *slab = (int)(s4 - 4 * k[0]);", "    *slab = 0;"),
+    ("ties broken by descending id",
+     "    for (int64_t i = 0; i < n; ++i) sorted_ids[cursor[key[i]]++] = (uint32_t)i;",
+     "    for (int64_t i = n - 1; i >= 0; --i) sorted_ids[cursor[key[i]]++] = (uint32_t)i;"),
+    ("voxel counts off by one",
+     "    for (int64_t i = 0; i < n; ++i) voxel_start[vid[i] + 1] += 1;",
+     "    for (int64_t i = 0; i < n; ++i) voxel_start[vid[i]] += 1;"),
+    ("scan drops the last voxel",
+     "    for (int64_t v = 0; v < V; ++v) voxel_start[v + 1] += voxel_start[v];",
+     "    for (int64_t v = 0; v + 1 < V; ++v) voxel_start[v + 1] += voxel_start[v];"),
+    ("empty voxels listed as occupied",
+     "        if (voxel_start[v + 1] > voxel_start[v]) occ[m++] = (uint32_t)v;",
+     "        if (voxel_start[v + 1] >= voxel_start[v]) occ[m++] = (uint32_t)v;"),
+    ("Kahan compensation sign",
+     "        *c = (t - *sum) - y;", "        *c = (t - *sum) + y;"),
+    ("float repulsion dropped",
+     "        w += (float)p->c_rep * u * u;", "        w += 0.0f;"),
+]
+
+
+def _run_pins(name, text, repl, workdir):
+    src = open(SRC).read()
+    assert src.count(text) == 1, f"mutant '{name}': its text is not unique in mech_oracle.c"
+    tag = "".join(ch if ch.isalnum() else "_" for ch in name)
+    c_path = os.path.join(workdir, f"mutant_{tag}.c")
+    so_path = os.path.join(workdir, f"mutant_{tag}.so")
+    with open(c_path, "w") as f:
+        f.write(src.replace(text, repl))
+    oracle.compile_to(c_path, so_path)
+    env = dict(os.environ, MECH_ORACLE_LIB=so_path, OMP_NUM_THREADS="2")
+    res = subprocess.run([sys.executable, "-m", "pytest", *PINS, "-x", "-q", "-m", "not gpu",
+                          "-p", "no:cacheprovider"], cwd=ROOT, env=env, capture_output=True,
+                         text=True, timeout=600)
+    return res.returncode, res.stdout[-600:]
+
+
+def test_every_mutant_fails_a_pin(tmp_path):
+    with ThreadPoolExecutor(max_workers=4) as ex:
+        futs = {name: ex.submit(_run_pins, name, text, repl, str(tmp_path))
+                for name, text, repl in MUTANTS}
+        results = {name: f.result() for name, f in futs.items()}
+    survivors = [name for name, (rc, _) in results.items() if rc == 0]
+    assert not survivors, f"mutants no pin caught: {survivors}"
+    # rc 1 = tests failed; anything else would be a crash of the run itself
+    crashed = {name: out for name, (rc, out) in results.items() if rc not in (0, 1)}
+    assert not crashed, crashed
+
+
+def test_unmutated_copy_passes_the_pins(tmp_path):
+    rc, out = _run_pins("identity", "#include <math.h>", "#include <math.h>", str(tmp_path))
+    assert rc == 0, out
+
+
+@pytest.mark.parametrize("name,text,repl", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_mutant_text_is_present(name, text, repl):
+    assert open(SRC).read().count(text) == 1
