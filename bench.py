@@ -225,6 +225,54 @@ def bench_locality(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_grow(args):
+    """The paper's experiment proper: a tumour that grows by division, daughters appended
+    at the end of the cell arrays.  Left in that order, the cells lose their spatial
+    locality as the population grows; reordered into voxel order every step, they keep
+    it.  Force-kernel time per step is sampled as the population doubles, both ways (the
+    trajectories are bitwise the same)."""
+    import torch
+
+    import workloads
+    from paper_2306_11544_amd import binding as B
+
+    precision = args.precision or "fp32k"
+    n0, steps, every = 500_000, max(args.steps, 200), 25
+    # a dense core that grows into its surroundings; p_div doubles it in about 200 steps
+    pop = workloads.tumour(n0, seed=31, steps=steps, core_radius=600 * 0.5 ** (1 / 3),
+                           half=1000.0)
+    p_div = 2.0 ** (1.0 / 200) - 1.0
+    prm = B.params_of(pop, B.PRECISIONS[precision])
+    torch.cuda.init()
+    series = {}
+    # reorder every step, or once at the first step and never again (the cells start in
+    # voxel order and daughters pile up at the end)
+    for mode in (1, 10 ** 9):
+        rows = []
+        with B.Population(prm, pop.pos, pop.radius, pop.type, max_cells=2 * n0 + 1000) as P:
+            P.set_division(p_div, 1234)
+            P.set_reorder(mode)
+            for k in range(0, steps + 1, every):
+                bin_ms, force_ms = P.profile(3)
+                rows.append({"step": k, "cells": P.size(), "binning_ms": bin_ms,
+                             "force_ms": force_ms})
+                log(f"reorder {mode}: {rows[-1]}")
+                if k < steps:
+                    P.step(every - 3)
+        series["every_step" if mode == 1 else "never"] = rows  # never: after the first step
+    last = {m: series[m][-1]["force_ms"] for m in series}
+    out = {
+        "metric": "force-kernel ms per step as a dividing tumour doubles (locality)",
+        "value": last["never"] / last["every_step"],
+        "unit": "slowdown without reordering, at the end of the run",
+        "n_gpus": 1, "higher_is_better": False, "data": "synthetic",
+        "config": {"workload": f"growing tumour {n0}", "precision": precision,
+                   "p_div": p_div, "steps": steps},
+        "series": series,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -241,6 +289,8 @@ def main():
                     help="skip the autotuner (default configuration or --force)")
     ap.add_argument("--reorder-every", type=int, default=1,
                     help="reorder the cells every K steps (0: never; the locality study)")
+    ap.add_argument("--grow", action="store_true",
+                    help="run the growing-tumour locality experiment (division, no reorder)")
     ap.add_argument("--locality", action="store_true",
                     help="run the locality ablation (reorder every 1, 10, 100 steps, never)")
     ap.add_argument("--tuning", default="",
@@ -259,6 +309,9 @@ def main():
         return
     if args.locality:
         bench_locality(args)
+        return
+    if args.grow:
+        bench_grow(args)
         return
 
     import torch

@@ -134,6 +134,12 @@ int create_population(const MechParams* params, int64_t n_cells, const double* p
                       const double* radius, const int32_t* type,
                       const double* prev_velocity, void* hip_stream, MechPopulation** out);
 
+/* Same, with room for the population to grow to max_cells (>= n_cells) by division
+ * (population_set_division).  MECH_E_INVALID if max_cells is out of range. */
+int create_population_cap(const MechParams* params, int64_t n_cells, int64_t max_cells,
+                          const double* pos, const double* radius, const int32_t* type,
+                          const double* prev_velocity, void* hip_stream, MechPopulation** out);
+
 /* Same, but all device arrays are carved from the caller's device buffer `workspace`
  * of `workspace_bytes` (>= population_workspace_bytes, 256-byte aligned); the library
  * makes no device allocation.  MECH_E_NOMEM if the buffer is too small. */
@@ -177,6 +183,24 @@ int read_stats(MechPopulation* pop, int64_t* steps, int64_t* interactions,
  *   phase_ms[1]  mean ms per step of the neighbour-force and update kernel (a6-a7)
  * Synchronises.  For tuning and roofline measurement. */
 int profile_step(MechPopulation* pop, int64_t n_steps, double* phase_ms);
+
+/* Growing population: cells divide, and daughters are appended at the end of the cell
+ * arrays -- how the paper's cells lose their spatial locality (Section 5.4).  The paper
+ * gives no division rule; this one is the library's.  After the walls of step t (t
+ * counts steps from creation), cell `id` divides when u0 < p_div, where u_k =
+ * (m >> 11) * 2^-53 and m is the SplitMix64 output function of the state
+ * seed + 0x9E3779B97F4A7C15 * (4 (2^32 t + id) + k + 1) (mod 2^64).  Dividing cells are
+ * ranked by id; while the population has room (max_cells at creation), the daughter of
+ * rank k gets id n + k.  With e = v/|v|, v = (2u1 - 1, 2u2 - 1, 2u3 - 1) (or (0, 0, 1)
+ * when |v|^2 < 1e-12), the parent moves to x - (r/2) e and the daughter sits at
+ * x + (r/2) e, both through the walls; the daughter copies radius, type and v_prev.
+ * p_div = 0 stops division.  Waits for the stream.  MECH_E_INVALID if p_div is outside
+ * [0, 1]. */
+int population_set_division(MechPopulation* pop, double p_div, uint64_t seed);
+
+/* Current number of cells (waits for the stream; a growing population's size is known
+ * on the device only).  read_state and read_binning take this many cells. */
+int population_size(MechPopulation* pop, int64_t* n_cells);
 
 /* Locality study (the paper's finding that cells stored far from their neighbours slow
  * the velocity update, Section 5.4): every >= 1 reorders the cells into voxel order

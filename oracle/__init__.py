@@ -80,6 +80,13 @@ def lib():
         L.oracle_velocity_sampled.argtypes = [P(OracleParams), C.c_int64, dp, dp, ip,
                                               C.c_int32, C.c_int64, lp, dp, lp]
         L.oracle_set_threads.argtypes = [C.c_int32]
+        L.oracle_splitmix64.argtypes = [C.c_uint64]
+        L.oracle_splitmix64.restype = C.c_uint64
+        L.oracle_uniform.argtypes = [C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint64]
+        L.oracle_uniform.restype = C.c_double
+        L.oracle_divide.argtypes = [P(OracleParams), C.c_int64, C.c_int64, dp, dp, ip, dp,
+                                    C.c_uint64, C.c_int64, C.c_double, lp]
+        L.oracle_divide.restype = C.c_int32
         L.oracle_sum_f32.argtypes = [P(C.c_float), C.c_int64, C.c_int32]
         L.oracle_sum_f32.restype = C.c_float
         for f in ("oracle_grid_dims", "oracle_bin", "oracle_velocity_allpairs",
@@ -243,3 +250,46 @@ def run(p, pos, radius, types=None, vprev=None, steps=1, precision=FP64, euler_f
 def run_pop(pop, steps=None, precision=FP64, euler_first=False, per_step=False):
     return run(params_of(pop), pop.pos, pop.radius, pop.type, None,
                pop.steps if steps is None else steps, precision, euler_first, False, per_step)
+
+
+def splitmix64(state: int) -> int:
+    """The SplitMix64 output function applied to one state."""
+    return int(lib().oracle_splitmix64(C.c_uint64(state & ((1 << 64) - 1))))
+
+
+def uniform(seed: int, cell_id: int, t: int, k: int) -> float:
+    """The counter-based uniform draw of division (see oracle_divide in mech_oracle.c)."""
+    return float(lib().oracle_uniform(seed, cell_id, t, k))
+
+
+def run_growing(p: OracleParams, pos, radius, type_=None, steps: int = 1, precision: int = FP64,
+                capacity: int = 0, p_div: float = 0.0, seed: int = 0, euler_first: bool = False):
+    """Steps of the method, each followed by division (arrays in id order).  Returns
+    dict(pos, vprev, radius, type, n, per_step_n, interactions)."""
+    pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
+    n = pos.shape[0]
+    cap = max(capacity, n)
+    P = np.zeros((cap, 3)); P[:n] = pos
+    Rr = np.zeros(cap); Rr[:n] = radius
+    T = np.zeros(cap, np.int32)
+    if type_ is not None:
+        T[:n] = type_
+    VP = np.zeros((cap, 3))
+    per_n, inter = [], 0
+    L = lib()
+    for t in range(steps):
+        v, it, _ = velocity_voxel(p, P[:n], Rr[:n], T[:n], precision)
+        inter += it
+        x = np.ascontiguousarray(P[:n]); vp = np.ascontiguousarray(VP[:n])
+        v = np.ascontiguousarray(v)
+        _check(L.oracle_integrate(C.byref(p), n, _d(x), _d(v), _d(vp),
+                                  int(euler_first and t == 0)), "integrate")
+        P[:n] = x; VP[:n] = vp
+        if p_div > 0.0:
+            n_out = C.c_int64(0)
+            _check(L.oracle_divide(C.byref(p), n, cap, _d(P), _d(Rr), _i(T), _d(VP), seed, t,
+                                   float(p_div), C.byref(n_out)), "divide")
+            n = int(n_out.value)
+        per_n.append(n)
+    return dict(pos=P[:n].copy(), vprev=VP[:n].copy(), radius=Rr[:n].copy(), type=T[:n].copy(),
+                n=n, per_step_n=per_n, interactions=inter)

@@ -437,6 +437,70 @@ done:
     return rc;
 }
 
+/* ------------------------------------------------------------------ division */
+
+/* Growing populations (the source of the locality loss the paper studies, Section 5.4:
+ * cells created by division are appended at the end of the cell vector).  The paper
+ * gives no division rule; this is the one the library defines:
+ *   - after the walls of step t (t counts steps from creation, from 0), cell `id`
+ *     divides when u0 < p_div, with u_k = uniform(seed, id, t, k) below;
+ *   - dividing cells are ranked by ascending id; the first min(D, capacity - n) of them
+ *     divide (D of them drew a division), the daughter of rank k taking id n + k;
+ *   - direction e = v / |v| with v = (2 u1 - 1, 2 u2 - 1, 2 u3 - 1), or (0, 0, 1) when
+ *     |v|^2 < 1e-12; the parent moves to x - (r/2) e and the daughter sits at
+ *     x + (r/2) e, both through the walls of step 5 of the method;
+ *   - the daughter copies the parent's radius, type and v_prev.
+ * uniform(seed, id, t, k) = (m >> 11) * 2^-53 where m is the output function of
+ * SplitMix64 (Steele, Lea and Flood 2014, as in Vigna's reference code) applied to the
+ * state seed + 0x9E3779B97F4A7C15 * (4 (2^32 t + id) + k + 1), all mod 2^64. */
+uint64_t oracle_splitmix64(uint64_t state)
+{
+    uint64_t z = state;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+double oracle_uniform(uint64_t seed, uint64_t id, uint64_t t, uint64_t k)
+{
+    uint64_t counter = 4u * ((t << 32) + id) + k + 1u;
+    uint64_t m = oracle_splitmix64(seed + 0x9E3779B97F4A7C15ull * counter);
+    return (double)(m >> 11) * (1.0 / 9007199254740992.0);
+}
+
+/* Arrays in id order with room for `capacity` cells; returns the new size in *n_out. */
+int32_t oracle_divide(const OracleParams* p, int64_t n, int64_t capacity, double* pos,
+                      double* radius, int32_t* type, double* vprev, uint64_t seed, int64_t t,
+                      double p_div, int64_t* n_out)
+{
+    int64_t made = 0;
+    for (int64_t id = 0; id < n && n + made < capacity; ++id) {
+        if (!(oracle_uniform(seed, (uint64_t)id, (uint64_t)t, 0) < p_div)) continue;
+        double v[3];
+        for (int c = 0; c < 3; ++c)
+            v[c] = 2.0 * oracle_uniform(seed, (uint64_t)id, (uint64_t)t, (uint64_t)c + 1) - 1.0;
+        double l2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+        double e[3] = { 0.0, 0.0, 1.0 };
+        if (l2 >= 1e-12) {
+            double l = sqrt(l2);
+            for (int c = 0; c < 3; ++c) e[c] = v[c] / l;
+        }
+        int64_t q = n + made;
+        double half = 0.5 * radius[id];
+        for (int c = 0; c < 3; ++c) {
+            double x = pos[3 * id + c];
+            pos[3 * q + c] = reflect(x + half * e[c], p->lo[c], p->hi[c]);
+            pos[3 * id + c] = reflect(x - half * e[c], p->lo[c], p->hi[c]);
+            vprev[3 * q + c] = vprev[3 * id + c];
+        }
+        radius[q] = radius[id];
+        type[q] = type[id];
+        ++made;
+    }
+    *n_out = n + made;
+    return 0;
+}
+
 /* ------------------------------------------------------------------ threads */
 
 int32_t oracle_set_threads(int32_t t)

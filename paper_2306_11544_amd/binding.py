@@ -32,6 +32,7 @@ PRECISIONS = {"fp64": MECH_FP64, "fp32": MECH_FP32, "fp32k": MECH_FP32_KAHAN}
 EXPORTS = ("mech_last_error", "mech_abi_version", "mech_device_count",
            "population_workspace_bytes", "create_population", "create_population_in",
            "step_mechanics", "read_state", "read_binning", "read_stats", "profile_step",
+           "create_population_cap", "population_set_division", "population_size",
            "population_set_reorder", "population_get_tuning", "population_set_tuning",
            "population_info", "population_stream", "destroy_population",
            "batch_workspace_bytes", "batch_request_voxels", "create_batch", "create_batch_in",
@@ -100,6 +101,10 @@ def lib():
             "read_binning": (C.c_int, [vp, up, up, up, up, lp, lp]),
             "read_stats": (C.c_int, [vp, lp, lp, lp]),
             "profile_step": (C.c_int, [vp, C.c_int64, dp]),
+            "create_population_cap": (C.c_int, [P(MechParams), C.c_int64, C.c_int64, dp, dp, ip,
+                                                dp, vp, P(vp)]),
+            "population_set_division": (C.c_int, [vp, C.c_double, C.c_uint64]),
+            "population_size": (C.c_int, [vp, lp]),
             "population_set_reorder": (C.c_int, [vp, C.c_int32]),
             "population_get_tuning": (C.c_int, [vp, P(MechTuning)]),
             "population_set_tuning": (C.c_int, [vp, P(MechTuning)]),
@@ -210,6 +215,17 @@ def create_population(params: MechParams, pos, radius, type=None, prev_velocity=
     return h
 
 
+def create_population_cap(params: MechParams, pos, radius, type, prev_velocity, stream,
+                          max_cells: int) -> C.c_void_p:
+    pos, radius, t, vp = _cells(pos, radius, type, prev_velocity)
+    h = C.c_void_p()
+    _ck(lib().create_population_cap(C.byref(params), pos.shape[0], int(max_cells), _d(pos),
+                                    _d(radius),
+                                    None if t is None else t.ctypes.data_as(C.POINTER(C.c_int32)),
+                                    _d(vp), stream, C.byref(h)))
+    return h
+
+
 def create_population_in(params: MechParams, pos, radius, type, prev_velocity, stream,
                          workspace_ptr: int, workspace_bytes: int) -> C.c_void_p:
     pos, radius, t, vp = _cells(pos, radius, type, prev_velocity)
@@ -279,10 +295,13 @@ class Population:
     """Owns one device population; `with Population(...) as p:` destroys it on exit."""
 
     def __init__(self, params: MechParams, pos, radius, type=None, prev_velocity=None,
-                 stream=None, workspace=None):
+                 stream=None, workspace=None, max_cells=None):
         self.n = int(np.asarray(pos).reshape(-1, 3).shape[0])
         self._ws = workspace  # keeps a caller's device buffer (e.g. a torch tensor) alive
-        if workspace is not None:
+        if max_cells is not None:
+            self.h = create_population_cap(params, pos, radius, type, prev_velocity, stream,
+                                           max_cells)
+        elif workspace is not None:
             self.h = create_population_in(params, pos, radius, type, prev_velocity, stream,
                                           int(workspace.data_ptr()),
                                           int(workspace.numel() * workspace.element_size()))
@@ -304,6 +323,15 @@ class Population:
 
     def profile(self, n_steps=1):
         return profile_step(self.h, n_steps)
+
+    def set_division(self, p_div: float, seed: int = 0):
+        """Cells divide with probability p_div per step (the population needs max_cells)."""
+        _ck(lib().population_set_division(self.h, float(p_div), C.c_uint64(seed)))
+
+    def size(self) -> int:
+        n = C.c_int64()
+        _ck(lib().population_size(self.h, C.byref(n)))
+        return int(n.value)
 
     def set_reorder(self, every: int):
         """Reorder the cells every `every` steps (1: every step); 0: never, cells in id

@@ -93,6 +93,9 @@ static_assert(SCAN_PER_THREAD % XSUB == 0 && SCAN_TILE % XSUB == 0, "scan tiles 
 
 // device header words
 constexpr int H_CELLS = 0, H_VOXELS = 1, H_OCC = 2;
+constexpr int H_STEP = 3;    // steps taken since creation (division draws)
+constexpr int H_DIV = 4;     // cells that drew a division this step
+constexpr int HDR_WORDS = 8;
 
 // ------------------------------------------------------------------------ kernel args
 
@@ -498,6 +501,177 @@ __global__ __launch_bounds__(BLOCK) void k_order_by_id(const uint32_t* __restric
     }
 }
 
+// ------------------------------------------------------------------------ division
+
+// Reflecting walls on a cell centre: mirror at each face, then clamp.
+__device__ __forceinline__ double reflect(double x, double lo, double hi)
+{
+    if (x < lo) x = 2.0 * lo - x;
+    if (x > hi) x = 2.0 * hi - x;
+    return fmin(fmax(x, lo), hi);
+}
+
+
+// Growing populations: after the walls of step t, cell `id` divides when its first draw
+// is below p_div.  Draws are counter-based: the SplitMix64 output function (Steele, Lea
+// and Flood 2014) of the state seed + gamma * (4 (2^32 t + id) + k + 1), top 53 bits.
+__device__ __forceinline__ double division_draw(uint64_t seed, uint32_t id, uint32_t t, uint32_t k)
+{
+    const uint64_t gamma = 0x9E3779B97F4A7C15ull;
+    uint64_t z = seed + gamma * (4ull * (((uint64_t)t << 32) + id) + k + 1ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return (double)(z >> 11) * (1.0 / 9007199254740992.0);
+}
+
+struct DivArgs {
+    double* X[3];
+    double* R;
+    int32_t* T;
+    uint32_t* ID;
+    void* VP[3];               // float or double, as the precision keeps v_prev
+    uint32_t* slot_of;
+    SlotDesc* slots;
+    uint32_t* hdr;
+    uint32_t* flag;            // indexed by id: 1 if the cell draws a division, then its rank
+    uint64_t* tsum;            // tile sums of the rank scan
+    uint64_t seed;
+    double p_div;
+    uint32_t capacity;         // cells the population may grow to
+    uint32_t vp_bytes;         // 4 or 8
+};
+
+__global__ __launch_bounds__(BLOCK) void k_div_mark(DivArgs a)
+{
+    const uint32_t n = a.hdr[H_CELLS], t = a.hdr[H_STEP];
+    for (uint32_t s = blockIdx.x * BLOCK + threadIdx.x; s < n; s += gridDim.x * BLOCK) {
+        const uint32_t id = a.ID[s];
+        a.flag[id] = division_draw(a.seed, id, t, 0) < a.p_div ? 1u : 0u;
+    }
+}
+
+// Exclusive scan of flag[0, n) by tiles: rank of each dividing cell among the dividing
+// cells of smaller id.  The total goes to hdr[H_DIV].
+__global__ __launch_bounds__(BLOCK) void k_div_scan_reduce(DivArgs a)
+{
+    __shared__ uint64_t sh[BLOCK / WAVE];
+    const uint32_t n = a.hdr[H_CELLS];
+    const uint32_t nt = (n + SCAN_TILE - 1) / SCAN_TILE;
+    for (uint32_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
+        uint64_t acc = 0;
+        for (int k = 0; k < SCAN_PER_THREAD; ++k) {
+            const uint32_t v = tile * SCAN_TILE + k * BLOCK + threadIdx.x;
+            if (v < n) acc += a.flag[v];
+        }
+        acc = wave_sum(acc);
+        if ((threadIdx.x & (WAVE - 1)) == 0) sh[threadIdx.x / WAVE] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint64_t tot = 0;
+            for (int i = 0; i < BLOCK / WAVE; ++i) tot += sh[i];
+            a.tsum[tile] = tot;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_div_scan_top(DivArgs a)
+{
+    __shared__ uint64_t sh[BLOCK / WAVE];
+    const uint32_t n = a.hdr[H_CELLS];
+    const uint32_t nt = (n + SCAN_TILE - 1) / SCAN_TILE;
+    uint64_t carry = 0;
+    for (uint32_t base = 0; base < nt; base += BLOCK) {
+        const uint32_t i = base + threadIdx.x;
+        const uint64_t x = i < nt ? a.tsum[i] : 0;
+        uint64_t tot;
+        const uint64_t ex = block_excl_scan(x, sh, &tot);
+        if (i < nt) a.tsum[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) a.hdr[H_DIV] = (uint32_t)carry;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_div_scan_down(DivArgs a)
+{
+    __shared__ uint64_t sh[BLOCK / WAVE];
+    const uint32_t n = a.hdr[H_CELLS];
+    const uint32_t nt = (n + SCAN_TILE - 1) / SCAN_TILE;
+    for (uint32_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
+        const uint32_t base = tile * SCAN_TILE + threadIdx.x * SCAN_PER_THREAD;
+        uint32_t f[SCAN_PER_THREAD];
+        uint64_t sum = 0;
+        for (int k = 0; k < SCAN_PER_THREAD; ++k) {
+            f[k] = base + k < n ? a.flag[base + k] : 0u;
+            sum += f[k];
+        }
+        uint64_t tot;
+        uint64_t off = a.tsum[tile] + block_excl_scan(sum, sh, &tot);
+        for (int k = 0; k < SCAN_PER_THREAD; ++k) {
+            if (base + k < n) a.flag[base + k] = (uint32_t)off;
+            off += f[k];
+        }
+    }
+}
+
+// The dividing cells of rank below capacity - n divide: the daughter of rank k takes id
+// and storage index n + k (appended at the end), the parent's radius, type and v_prev;
+// parent and daughter move by -/+ r/2 along the drawn direction, through the walls.
+__global__ __launch_bounds__(BLOCK) void k_div_apply(DivArgs a)
+{
+    const uint32_t n = a.hdr[H_CELLS], t = a.hdr[H_STEP];
+    const uint32_t room = a.capacity - n;
+    for (uint32_t s = blockIdx.x * BLOCK + threadIdx.x; s < n; s += gridDim.x * BLOCK) {
+        const uint32_t id = a.ID[s];
+        if (!(division_draw(a.seed, id, t, 0) < a.p_div)) continue;
+        const uint32_t rank = a.flag[id];
+        if (rank >= room) continue;
+        double v[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) v[c] = 2.0 * division_draw(a.seed, id, t, (uint32_t)c + 1u) - 1.0;
+        double e[3] = {0.0, 0.0, 1.0};
+        {
+#pragma clang fp contract(off)
+            const double l2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+            if (l2 >= 1e-12) {
+                const double l = sqrt(l2);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) e[c] = v[c] / l;
+            }
+        }
+        const uint32_t q = n + rank;
+        const SlotDesc& d = a.slots[a.slot_of[s]];
+        const double half = 0.5 * a.R[s];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            {
+#pragma clang fp contract(off)
+                const double x = a.X[c][s];
+                a.X[c][q] = reflect(x + half * e[c], d.lo[c], d.hi[c]);
+                a.X[c][s] = reflect(x - half * e[c], d.lo[c], d.hi[c]);
+            }
+            if (a.vp_bytes == 4)
+                static_cast<float*>(a.VP[c])[q] = static_cast<const float*>(a.VP[c])[s];
+            else
+                static_cast<double*>(a.VP[c])[q] = static_cast<const double*>(a.VP[c])[s];
+        }
+        a.R[q] = a.R[s];
+        a.T[q] = a.T[s];
+        a.ID[q] = n + rank;
+        a.slot_of[q] = a.slot_of[s];
+    }
+}
+
+__global__ void k_div_commit(DivArgs a)
+{
+    const uint32_t n = a.hdr[H_CELLS];
+    const uint32_t room = a.capacity - n;
+    const uint32_t grown = min(a.hdr[H_DIV], room);
+    a.hdr[H_CELLS] = n + grown;
+    a.slots[a.slot_of[0]].n_cells += grown;
+}
+
 __global__ __launch_bounds__(BLOCK) void k_copy_positions(uint32_t n, const double* __restrict__ a0,
                                                           const double* __restrict__ a1,
                                                           const double* __restrict__ a2,
@@ -514,12 +688,6 @@ __global__ __launch_bounds__(BLOCK) void k_copy_positions(uint32_t n, const doub
 
 // ------------------------------------------------------------------------ a6 + a7 (shared)
 
-__device__ __forceinline__ double reflect(double x, double lo, double hi)
-{
-    if (x < lo) x = 2.0 * lo - x;
-    if (x > hi) x = 2.0 * hi - x;
-    return fmin(fmax(x, lo), hi);
-}
 
 template <typename VPT>
 struct ForceArgs {
@@ -1163,9 +1331,11 @@ __global__ __launch_bounds__(FL_WAVES * WAVE) void k_force_lds(PhysArgs P, Force
 
 // Counts down the steps of every slot still running; a slot that reaches 0 is frozen
 // from the next step on.  The first step has been taken, so no slot starts with Euler.
-__global__ __launch_bounds__(BLOCK) void k_step_end(SlotDesc* __restrict__ slots, uint32_t n_slots)
+__global__ __launch_bounds__(BLOCK) void k_step_end(SlotDesc* __restrict__ slots, uint32_t n_slots,
+                                                    uint32_t* __restrict__ hdr)
 {
     const uint32_t t = blockIdx.x * BLOCK + threadIdx.x;
+    if (t == 0) hdr[H_STEP] += 1u;
     if (t >= n_slots) return;
     if (slots[t].steps_left > 0) slots[t].steps_left -= 1;
     slots[t].euler = 0;
@@ -1255,7 +1425,7 @@ __global__ __launch_bounds__(BLOCK) void k_unpermute(uint32_t cell_off, uint32_t
 inline uint32_t blocks_for(uint64_t n, uint32_t per) { return (uint32_t)((n + per - 1) / per); }
 
 struct Layout {
-    size_t X[3], XS[3], R[2], T[2], ID[2], VP[2][3], SH, slot_of, vid_cur, off, tmp_key,
+    size_t X[3], XS[3], R[2], T[2], ID[2], VP[2][3], SH, slot_of, vid_cur, off, tmp_key, dtsum,
         tmp_src, vid_sorted, count, start, occ, hdr, tsum, stats, cadh, cadh_f, slots, stage;
     size_t total;
 };
@@ -1292,13 +1462,14 @@ Layout make_layout(const MechParams& p, int64_t ncap, uint64_t vcap, int32_t sca
     L.count = take(XSUB * vv * 4);          // per bin
     L.start = take((XSUB * vv + 1) * 4);    // per bin, plus the total
     L.occ = take(vv * 4);                   // per voxel
-    L.hdr = take(16);
+    L.hdr = take(HDR_WORDS * 4);
     L.tsum = take((size_t)blocks_for(XSUB * vv, SCAN_TILE) * 8);
     L.stats = take(STAT_SLOTS * 16);
     L.cadh = take(64 * 8);
     L.cadh_f = take(64 * 4);
     L.slots = take((size_t)std::max(scap, 1) * sizeof(SlotDesc));
     L.stage = take(nn * 48);
+    L.dtsum = take((size_t)blocks_for(nn, SCAN_TILE) * 8);
     L.total = cur;
     return L;
 }
@@ -1416,6 +1587,10 @@ struct MechBatch {
     MechTuning tune{0, 4, 4, 0};          // force-kernel launch configuration
     // locality study: reorder (gather) every reorder_every steps, 0 = never
     int32_t reorder_every = 1;
+    // growing populations: division probability per cell and step, draw seed
+    double p_div = 0.0;
+    uint64_t div_seed = 0;
+    bool growing = false;                 // the device may hold more cells than the host mirror
     int64_t reorder_phase = 0;            // steps since the mode was set
     bool last_gather = true;              // the last binning reordered the cells
     bool graphs_ready = false;
@@ -1679,7 +1854,40 @@ void enqueue_force_inplace_any(MechBatch* B)
 void enqueue_step_end(MechBatch* B)
 {
     hipLaunchKernelGGL(k_step_end, dim3(blocks_for((uint64_t)B->cap_slots, BLOCK)), dim3(BLOCK), 0, B->stream,
-                       B->at<SlotDesc>(B->L.slots), (uint32_t)B->cap_slots);
+                       B->at<SlotDesc>(B->L.slots), (uint32_t)B->cap_slots, B->at<uint32_t>(B->L.hdr));
+}
+
+// Division after the walls (growing populations): `buf` is the buffer pair that holds
+// the step's cells (the gathered one after a reorder, the current one in place).
+void enqueue_division(MechBatch* B, int buf)
+{
+    if (!(B->p_div > 0.0)) return;
+    const Layout& L = B->L;
+    DivArgs a{};
+    for (int c = 0; c < 3; ++c) {
+        a.X[c] = B->at<double>(L.X[c]);
+        a.VP[c] = B->arena + L.VP[buf][c];
+    }
+    a.R = B->at<double>(L.R[buf]);
+    a.T = B->at<int32_t>(L.T[buf]);
+    a.ID = B->at<uint32_t>(L.ID[buf]);
+    a.slot_of = B->at<uint32_t>(L.slot_of);
+    a.slots = B->at<SlotDesc>(L.slots);
+    a.hdr = B->at<uint32_t>(L.hdr);
+    a.flag = B->at<uint32_t>(L.tmp_key);   // free once a4 has used it
+    a.tsum = B->at<uint64_t>(L.dtsum);
+    a.seed = B->div_seed;
+    a.p_div = B->p_div;
+    a.capacity = (uint32_t)B->cap_cells;
+    a.vp_bytes = is_fp32(B->prm) ? 4u : 8u;
+    const uint32_t nbc = cell_grid(B);
+    const uint32_t nbt = std::min<uint32_t>(blocks_for((uint64_t)B->cap_cells, SCAN_TILE), TILE_GRID_MAX);
+    hipLaunchKernelGGL(k_div_mark, dim3(nbc), dim3(BLOCK), 0, B->stream, a);
+    hipLaunchKernelGGL(k_div_scan_reduce, dim3(nbt), dim3(BLOCK), 0, B->stream, a);
+    hipLaunchKernelGGL(k_div_scan_top, dim3(1), dim3(BLOCK), 0, B->stream, a);
+    hipLaunchKernelGGL(k_div_scan_down, dim3(nbt), dim3(BLOCK), 0, B->stream, a);
+    hipLaunchKernelGGL(k_div_apply, dim3(nbc), dim3(BLOCK), 0, B->stream, a);
+    hipLaunchKernelGGL(k_div_commit, dim3(1), dim3(1), 0, B->stream, a);
 }
 
 // One full step a1..a7 from `parity`; flips nothing on the host.  gather: reorder the
@@ -1695,6 +1903,7 @@ void enqueue_step(MechBatch* B, int parity, bool gather = true)
         enqueue_binning_inplace(B);
         enqueue_force_inplace_any(B);
     }
+    enqueue_division(B, gather ? parity ^ 1 : parity);
     enqueue_step_end(B);
     B->parity = saved;
 }
@@ -1854,7 +2063,7 @@ int create_batch_impl(const MechParams* params, int64_t max_cells, int64_t max_v
         hipMemsetAsync(B->arena + L.count, 0, (size_t)max_voxels * XSUB * 4, B->stream) != hipSuccess ||
         hipMemsetAsync(B->arena + L.stats, 0, STAT_SLOTS * 16, B->stream) != hipSuccess ||
         hipMemsetAsync(B->arena + L.start, 0, ((size_t)max_voxels * XSUB + 1) * 4, B->stream) != hipSuccess ||
-        hipMemsetAsync(B->arena + L.hdr, 0, 16, B->stream) != hipSuccess ||
+        hipMemsetAsync(B->arena + L.hdr, 0, HDR_WORDS * 4, B->stream) != hipSuccess ||
         hipMemsetAsync(B->arena + L.slots, 0, (size_t)max_slots * sizeof(SlotDesc), B->stream) != hipSuccess)
         return bail(fail(MECH_E_DEVICE, "arena initialisation failed"));
     rc = sync_check(B);
@@ -2189,6 +2398,7 @@ int profile_impl(MechBatch* B, int64_t n_steps, double* phase_ms)
         else
             enqueue_force_inplace_any(B);
         (void)hipEventRecord(ev[2], B->stream);
+        enqueue_division(B, gather ? p ^ 1 : p);
         enqueue_step_end(B);
         rc = after_step(B, gather);
         if (rc == MECH_OK) rc = sync_check(B);
@@ -2252,7 +2462,7 @@ int64_t population_workspace_bytes(const MechParams* params, int64_t n_cells)
 
 static int create_pop_impl(const MechParams* params, int64_t n_cells, const double* pos, const double* radius,
                            const int32_t* type, const double* prev_velocity, void* hip_stream, void* workspace,
-                           int64_t ws_bytes, MechPopulation** out)
+                           int64_t ws_bytes, MechPopulation** out, int64_t max_cells = -1)
 {
     if (!out) return fail(MECH_E_INVALID, "out is NULL");
     *out = nullptr;
@@ -2266,8 +2476,11 @@ static int create_pop_impl(const MechParams* params, int64_t n_cells, const doub
     rc = validate_cells(params, params->domain_lo, params->domain_hi, n_cells, pos, radius, type,
                         prev_velocity, &rmax);
     if (rc) return rc;
+    if (max_cells < 0) max_cells = n_cells;
+    if (max_cells < n_cells || max_cells >= (int64_t(1) << 31))
+        return fail(MECH_E_INVALID, "max_cells %lld out of range", (long long)max_cells);
     MechBatch* B = nullptr;
-    rc = create_batch_impl(params, n_cells, (int64_t)V, 1, hip_stream, workspace, ws_bytes, &B);
+    rc = create_batch_impl(params, max_cells, (int64_t)V, 1, hip_stream, workspace, ws_bytes, &B);
     if (rc) return rc;
     int32_t slot = -1;
     rc = admit_impl(B, params->domain_lo, params->domain_hi, n_cells, pos, radius, type, prev_velocity, -1, &slot);
@@ -2303,6 +2516,14 @@ int create_population(const MechParams* params, int64_t n_cells, const double* p
     return create_pop_impl(params, n_cells, pos, radius, type, prev_velocity, hip_stream, nullptr, 0, out);
 }
 
+int create_population_cap(const MechParams* params, int64_t n_cells, int64_t max_cells, const double* pos,
+                          const double* radius, const int32_t* type, const double* prev_velocity, void* hip_stream,
+                          MechPopulation** out)
+{
+    return create_pop_impl(params, n_cells, pos, radius, type, prev_velocity, hip_stream, nullptr, 0, out,
+                           max_cells);
+}
+
 int create_population_in(const MechParams* params, int64_t n_cells, const double* pos, const double* radius,
                          const int32_t* type, const double* prev_velocity, void* hip_stream, void* workspace,
                          int64_t workspace_bytes, MechPopulation** out)
@@ -2327,10 +2548,14 @@ int profile_step(MechPopulation* P, int64_t n_steps, double* phase_ms)
     return profile_impl(P->b, n_steps, phase_ms);
 }
 
+static int refresh_size(MechPopulation* P);
+
 int read_state(MechPopulation* P, double* pos, double* vel, int64_t n_cells)
 {
     if (!P) return fail(MECH_E_INVALID, "population is NULL");
     if (!pos) return fail(MECH_E_INVALID, "pos is NULL");
+    int rc = refresh_size(P);
+    if (rc) return rc;
     if (n_cells != P->n) return fail(MECH_E_INVALID, "n_cells %lld != population size %lld", (long long)n_cells, (long long)P->n);
     return read_slot(P->b, 0, pos, vel, n_cells);
 }
@@ -2339,9 +2564,11 @@ int read_binning(MechPopulation* P, uint32_t* voxel_of_cell, uint32_t* voxel_sta
                  uint32_t* occ, int64_t* n_occ, int64_t* n_voxels)
 {
     if (!P) return fail(MECH_E_INVALID, "population is NULL");
+    int rc = refresh_size(P);
+    if (rc) return rc;
     MechBatch* B = P->b;
     HIP_TRY(hipSetDevice(B->device));
-    int rc = sync_check(B);
+    rc = sync_check(B);
     if (rc) return rc;
     const Layout& L = B->L;
     const size_t n = (size_t)P->n;
@@ -2449,9 +2676,51 @@ int population_set_tuning(MechPopulation* P, const MechTuning* t)
     return batch_set_tuning(P->b, t);
 }
 
+// A growing population's size lives on the device: wait and copy it to the host mirrors.
+static int refresh_size(MechPopulation* P)
+{
+    MechBatch* B = P->b;
+    if (!B->growing) return MECH_OK;
+    HIP_TRY(hipSetDevice(B->device));
+    int rc = sync_check(B);
+    if (rc) return rc;
+    uint32_t n = 0;
+    HIP_TRY(hipMemcpy(&n, B->arena + B->L.hdr + 4 * H_CELLS, 4, hipMemcpyDeviceToHost));
+    P->n = n;
+    B->n_cells = n;
+    B->slots[0].d.n_cells = n;
+    return MECH_OK;
+}
+
+int population_size(MechPopulation* P, int64_t* n_cells)
+{
+    if (!P || !n_cells) return fail(MECH_E_INVALID, "population or n_cells is NULL");
+    int rc = refresh_size(P);
+    if (rc) return rc;
+    *n_cells = P->n;
+    return MECH_OK;
+}
+
+int population_set_division(MechPopulation* P, double p_div, uint64_t seed)
+{
+    if (!P) return fail(MECH_E_INVALID, "population is NULL");
+    if (!(p_div >= 0.0 && p_div <= 1.0)) return fail(MECH_E_INVALID, "p_div must lie in [0, 1]");
+    MechBatch* B = P->b;
+    if (B->cap_slots != 1) return fail(MECH_E_INVALID, "division needs a population");
+    HIP_TRY(hipSetDevice(B->device));
+    HIP_TRY(hipStreamSynchronize(B->stream));
+    drop_graphs(B);
+    B->p_div = p_div;
+    B->div_seed = seed;
+    if (p_div > 0.0) B->growing = true;
+    return MECH_OK;
+}
+
 int population_info(MechPopulation* P, int64_t* n_cells, int32_t dims[3])
 {
     if (!P) return fail(MECH_E_INVALID, "population is NULL");
+    int rc = refresh_size(P);
+    if (rc) return rc;
     if (n_cells) *n_cells = P->n;
     if (dims) {
         const SlotDesc& d = P->b->slots[0].d;

@@ -17,7 +17,8 @@ import oracle
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "mech_oracle.c")
 PINS = ["tests/test_oracle_closed_form.py", "tests/test_oracle_invariants.py",
-        "tests/test_oracle_bruteforce.py", "tests/test_oracle_binning.py", "tests/test_kahan.py"]
+        "tests/test_oracle_bruteforce.py", "tests/test_oracle_binning.py", "tests/test_kahan.py",
+        "tests/test_oracle_division.py"]
 
 # (name, text in mech_oracle.c, replacement); each text occurs exactly once
 MUTANTS = [
@@ -68,6 +69,16 @@ MUTANTS = [
      "        *c = (t - *sum) - y;", "        *c = (t - *sum) + y;"),
     ("float repulsion dropped",
      "        w += (float)p->c_rep * u * u;", "        w += 0.0f;"),
+    ("division draw from the direction counter",
+     "oracle_uniform(seed, (uint64_t)id, (uint64_t)t, 0) < p_div",
+     "oracle_uniform(seed, (uint64_t)id, (uint64_t)t, 1) < p_div"),
+    ("daughter placed on the parent's side",
+     "pos[3 * q + c] = reflect(x + half * e[c]", "pos[3 * q + c] = reflect(x - half * e[c]"),
+    ("daughters a full radius away",
+     "    double half = 0.5 * radius[id];", "    double half = radius[id];"),
+    ("capacity filled from the highest id",
+     "    for (int64_t id = 0; id < n && n + made < capacity; ++id) {",
+     "    for (int64_t id = n - 1; id >= 0 && n + made < capacity; --id) {"),
 ]
 
 
