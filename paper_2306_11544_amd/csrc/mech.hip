@@ -2176,9 +2176,14 @@ int admit_impl(MechBatch* B, const double lo[3], const double hi[3], int64_t n, 
         return fail(MECH_E_BUDGET, "request of %lld cells and %llu voxels does not fit (%lld/%lld cells, "
                     "%lld/%lld voxels in use)", (long long)n, (unsigned long long)V, (long long)live_c,
                     (long long)B->cap_cells, (long long)live_v, (long long)B->cap_voxels);
-    // retired slots hold their id and space until a compaction drops them
+    // Retired slots hold their id and space until a compaction drops them.  Compact when
+    // the new request needs the room or an id, or when retired cells or voxels outnumber
+    // the live ones: every step still bins and moves the retired cells and scans their
+    // voxels, so letting them pile up would slow the live simulations down.
+    const int64_t dead_c = (int64_t)B->n_cells - live_c, dead_v = (int64_t)B->n_voxels - live_v;
     if (free_id() < 0 || (int64_t)B->n_cells + n > B->cap_cells ||
-        (int64_t)B->n_voxels + (int64_t)V > B->cap_voxels) {
+        (int64_t)B->n_voxels + (int64_t)V > B->cap_voxels ||
+        (any_retired && (dead_c > live_c || dead_v > live_v))) {
         rc = repack(B);
         if (rc) return rc;
         // the compacted range may overlap cells that queued steps still write: the

@@ -3,14 +3,17 @@
 Requests (a population and a step count each) arrive over time.  The server keeps one
 batch (see include/mech.h) whose arena is sized from an HBM budget: a request is
 admitted as soon as it has arrived and its cells and voxels fit in the space the
-running simulations leave free (first come, first served); it then runs inside the same
+running simulations leave free (first come, first served), and, if a live-cell limit is
+set, while the cells already running stay below it; it then runs inside the same
 step launches as every other admitted request, its state stays on the device, and it
 is read back and retired when its last step completes.  Requests that do not fit wait
 in the queue until earlier ones finish.  Each request's result is bitwise the one it
 would get alone.
 
-The loop enqueues a chunk of steps, admits arrivals and reads finished requests while
-that chunk runs (admission copies go on a second stream), then waits for the chunk.
+The loop enqueues a chunk of steps, admits arrivals while that chunk runs (admission
+copies go on a second stream), waits for the chunk and reads the finished requests.
+Each request stops at its own step count inside a chunk (its slot freezes on the
+device), so chunks keep a fixed length whatever the requests still need.
 Latency is completion minus arrival, with completion taken when the step that finished
 the request is seen complete.
 
@@ -53,11 +56,12 @@ def capacity_for_budget(params: B.MechParams, budget_bytes: int, voxels_per_cell
     per = (B.batch_workspace_bytes(params, 1 << 20, int((1 << 20) * voxels_per_cell) + 1,
                                    max_slots) - base) / float(1 << 20)
     cells = int(max(0, budget_bytes - base - (1 << 20)) / per)
-    cells = min(cells, (1 << 31) - 1)
-    voxels = min(int(cells * voxels_per_cell) + 1, (1 << 31) - 2)
+    max_voxels = (1 << 30) - 1          # the library's limit on voxels per arena
+    cells = min(cells, (1 << 31) - 1, int(max_voxels / voxels_per_cell))
+    voxels = min(int(cells * voxels_per_cell) + 1, max_voxels)
     while cells > 0 and B.batch_workspace_bytes(params, cells, voxels, max_slots) > budget_bytes:
         cells = int(cells * 0.99)
-        voxels = int(cells * voxels_per_cell) + 1
+        voxels = min(int(cells * voxels_per_cell) + 1, max_voxels)
     return cells, voxels
 
 
@@ -68,6 +72,11 @@ class Server:
     max_slots: int = 1024
     voxels_per_cell: float = 1.6
     steps_per_chunk: int = 10
+    # Cells allowed on the device at once (None: as many as the budget holds).  Every
+    # live request advances one step per batch step, so the more run together, the
+    # slower each one goes; once the GPU is saturated (a few million cells), admitting
+    # more adds latency and no throughput.
+    max_live_cells: int | None = None
     stats: dict = field(default_factory=dict)
 
     def __post_init__(self):
@@ -93,6 +102,7 @@ class Server:
         running = {}   # slot -> (request, population size, admit time)
         done = []
         cell_steps = 0
+        live_cells = 0
         max_live = 0
         max_queue = 0
         busy_chunks = 0
@@ -107,15 +117,17 @@ class Server:
                 r = pending.popleft()
                 queue.append((r, make_population(r)))
             max_queue = max(max_queue, len(queue))
-            # enqueue a chunk of steps for the admitted requests
+            # enqueue a chunk of steps for the admitted requests; a request whose steps
+            # run out inside the chunk freezes on the device at its own last step
             if running:
-                k = min(self.steps_per_chunk,
-                        min(bt.slot_info(s)[1] for s in running))
-                bt.step(max(k, 1))
+                bt.step(self.steps_per_chunk)
                 busy_chunks += 1
             # admit while the chunk runs: first come, first served
             while queue:
                 r, pop = queue[0]
+                if (self.max_live_cells is not None and running
+                        and live_cells + pop.n > self.max_live_cells):
+                    break
                 try:
                     slot = bt.admit_pop(pop, n_steps=r.steps)
                 except B.MechError as e:
@@ -124,10 +136,12 @@ class Server:
                     raise
                 queue.popleft()
                 running[slot] = (r, pop.n, now())
+                live_cells += pop.n
             max_live = max(max_live, len(running))
             B.batch_sync(bt)
             for slot in bt.poll():
                 r, n, t_admit = running.pop(slot)
+                live_cells -= n
                 t_done = now()
                 pos = vel = None
                 if keep_results:
@@ -152,6 +166,7 @@ class Server:
             "max_live_slots": max_live,
             "max_queue": max_queue,
             "chunks": busy_chunks,
+            "max_live_cells": self.max_live_cells,
             "arena_bytes": self.arena_bytes,
             "cap_cells": self.cap_cells,
             "cap_voxels": self.cap_voxels,
@@ -172,12 +187,14 @@ def main(argv=None):
     ap.add_argument("--precision", default="fp32")
     ap.add_argument("--chunk", type=int, default=10)
     ap.add_argument("--max-slots", type=int, default=1024)
+    ap.add_argument("--max-live-cells", type=int, default=0,
+                    help="cells on the device at once (0: as many as the budget holds)")
     args = ap.parse_args(argv)
     reqs = workloads.request_stream(args.requests, args.rate)
     params = B.make_params((0, 0, 0), (1, 1, 1), c_adh=workloads.C_ADH_2,
                            precision=B.PRECISIONS[args.precision])
     srv = Server(params, int(args.budget_gb * (1 << 30)), args.max_slots,
-                 steps_per_chunk=args.chunk)
+                 steps_per_chunk=args.chunk, max_live_cells=args.max_live_cells or None)
     # populations are drawn before the clock starts
     pops = {r.rid: workloads.request_population(r) for r in reqs}
     done = srv.run(reqs, lambda r: pops[r.rid])

@@ -171,3 +171,14 @@ def test_population_workspace_is_a_one_slot_batch():
     p = B.params_of(pop)
     v = B.batch_request_voxels(p, pop.lo, pop.hi)
     assert B.population_workspace_bytes(p, pop.n) == B.batch_workspace_bytes(p, pop.n, v, 1)
+
+
+def test_serving_arena_fits_budget_and_limits():
+    """The server sizes its arena from an HBM budget within the library's limits (no GPU
+    needed: workspace sizes are computed on the host)."""
+    from paper_2306_11544_amd.serve import capacity_for_budget
+    p = B.make_params((0, 0, 0), (1, 1, 1), c_adh=workloads.C_ADH_2, precision=B.MECH_FP32)
+    for budget in (4 << 20, 1 << 30, 200 << 30):
+        cells, vox = capacity_for_budget(p, budget, 1.6, 1024)
+        assert 0 < cells < 2 ** 31 and 0 < vox < 2 ** 30
+        assert B.batch_workspace_bytes(p, cells, vox, 1024) <= budget

@@ -141,3 +141,23 @@ def test_force_variants_agree(variant):
             res[name] = [bt.read(s)[0] for s in slots]
     for pp, x, y in zip(pops, res["cells"], res[variant]):
         assert pos_err(x, y, pp.half_width) <= 1e-12
+
+
+def test_retired_space_is_reclaimed():
+    """Admitting and retiring over and over does not let retired cells pile up in the
+    arena, even when it has room for them (they would still be binned every step)."""
+    require_gpu()
+    pops = _sims(3, 1000, 3000, seed=4650)
+    p = _params(B.MECH_FP32)
+    cells, vox = _capacity(pops)
+    with B.Batch(p, cells * 20, vox * 20, 16) as bt:
+        for _ in range(6):
+            for x in pops:
+                bt.admit_pop(x, n_steps=3)
+            bt.step(3)
+            B.batch_sync(bt)
+            for s in bt.poll():
+                bt.retire(s)
+            info = bt.info()
+            assert info["n_live"] == 0
+            assert info["n_cells"] <= 2 * cells and info["n_voxels"] <= 2 * vox

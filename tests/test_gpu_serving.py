@@ -16,23 +16,23 @@ def _requests(k=10, rate=400.0):
                                     steps_lo=5, steps_hi=60)
 
 
-@pytest.mark.parametrize("budget_mb", [2048, 4])
-def test_serving_results_equal_solo(budget_mb):
+@pytest.mark.parametrize("budget_mb,live", [(2048, None), (4, None), (2048, 20000)])
+def test_serving_results_equal_solo(budget_mb, live):
     require_gpu()
     reqs = _requests()
     pops = {r.rid: workloads.request_population(r) for r in reqs}
     params = B.make_params((0, 0, 0), (1, 1, 1), c_adh=workloads.C_ADH_2, precision=B.MECH_FP32)
     say("serving", budget_mb, [r.n for r in reqs])
-    srv = Server(params, budget_mb << 20, max_slots=64, steps_per_chunk=7)
+    srv = Server(params, budget_mb << 20, max_slots=64, steps_per_chunk=7, max_live_cells=live)
     try:
         done = srv.run(reqs, lambda r: pops[r.rid], keep_results=True)
         stats = srv.stats
     finally:
         srv.close()
     assert sorted(d.rid for d in done) == [r.rid for r in reqs]
-    if budget_mb == 4:
-        assert stats["max_queue"] >= 1  # the budget made requests wait
-    else:
+    if budget_mb == 4 or live is not None:
+        assert stats["max_queue"] >= 1  # the budget or the live-cell limit made requests wait
+    if budget_mb > 4:
         assert stats["max_live_slots"] >= 2  # requests overlapped on the device
     for d in done:
         assert d.done_s >= d.admit_s >= d.arrival_s - 1e-6
