@@ -182,3 +182,11 @@ def test_serving_arena_fits_budget_and_limits():
         cells, vox = capacity_for_budget(p, budget, 1.6, 1024)
         assert 0 < cells < 2 ** 31 and 0 < vox < 2 ** 30
         assert B.batch_workspace_bytes(p, cells, vox, 1024) <= budget
+
+
+def test_binding_fails_loudly_without_the_library(monkeypatch, tmp_path):
+    """No CPU fallback: with libmech.so missing the binding raises."""
+    monkeypatch.setattr(B, "_lib", None)
+    monkeypatch.setattr(B, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(ImportError):
+        B.lib()

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 import workloads
-from gpu_helpers import pos_err, require_gpu, run_gpu, say
+from gpu_helpers import pos_err, record, require_gpu, run_gpu, say
 from paper_2306_11544_amd import binding as B
 
 pytestmark = pytest.mark.gpu
@@ -47,17 +47,21 @@ def test_batch_equals_solo_bitwise(prec):
         assert np.array_equal(pos, solo["pos"]) and np.array_equal(vel, solo["vel"])
 
 
-def test_batch_fp64_matches_oracle(orc):
+@pytest.mark.parametrize("prec,tol", [(B.MECH_FP64, 1e-10), (B.MECH_FP32, 1e-4)])
+def test_batch_matches_fp64_oracle(orc, prec, tol):
     require_gpu()
     pops = _sims(3, 1000, 5000, seed=4100)
     cells, vox = _capacity(pops)
-    with B.Batch(_params(B.MECH_FP64), cells, vox, 3) as bt:
+    with B.Batch(_params(prec), cells, vox, 3) as bt:
         slots = [bt.admit_pop(pp, n_steps=60) for pp in pops]
         bt.step(60)
         got = [bt.read(s)[0] for s in slots]
-    for pp, g in zip(pops, got):
+    for k, (pp, g) in enumerate(zip(pops, got)):
         want = orc.run_pop(pp, steps=60)["pos"]
-        assert pos_err(g, want, pp.half_width) <= 1e-10
+        err = pos_err(g, want, pp.half_width)
+        record(f"batch {'fp64' if prec == B.MECH_FP64 else 'fp32'} sim{k} ({pp.n} cells) 60 steps "
+               "vs fp64 oracle", err)
+        assert err <= tol
 
 
 def test_continuous_admission_and_repack():

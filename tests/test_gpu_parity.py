@@ -57,6 +57,27 @@ def test_fp64_trajectory(orc, name, maker, steps):
     assert 0 < got["candidates"] <= want["candidates"]
 
 
+_FP32_CASES = [
+    ("plain1k", lambda: workloads.plain(), 100),
+    ("sph20k", lambda: workloads.spheroid(20000, seed=21), 200),
+    ("tumour20k", lambda: _scaled_tumour(20000, 22), 100),
+]
+
+
+@pytest.mark.parametrize("name,maker,steps", _FP32_CASES, ids=[c[0] for c in _FP32_CASES])
+def test_fp32_and_kahan_error_vs_fp64_oracle(orc, name, maker, steps):
+    """The FP32 forms against the FP64 oracle on the small configurations, with the error
+    of each recorded (the 1M-cell and 100k-cell cases have tests of their own)."""
+    require_gpu()
+    pop = maker()
+    want = orc.run_pop(pop, steps=steps)
+    for prec, label in ((B.MECH_FP32, "fp32"), (B.MECH_FP32_KAHAN, "fp32k")):
+        got = run_gpu(pop, steps, precision=prec)
+        err = pos_err(got["pos"], want["pos"], pop.half_width)
+        record(f"{label} {name} {steps} steps vs fp64 oracle", err)
+        assert err <= FP32_TOL, (label, err)
+
+
 @pytest.mark.parametrize("kernel", ["rows", "voxel"])
 def test_full_neighbourhood_kernels_visit_every_candidate(orc, kernel):
     """The kernels without the slab window test every pair of the 27-voxel
