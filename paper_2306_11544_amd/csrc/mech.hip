@@ -1,20 +1,25 @@
 // mech.hip -- gfx950 kernels and C-ABI runtime of the agent-mechanics step (libmech.so).
 //
 // One step, all on the device, on the batch's stream:
-//   k_bin          a1+a2  voxel of every cell (FP64 key) and an integer-atomic histogram
-//   k_scan_reduce  a3     per-tile sums of (count, occupied) packed in 64 bits
+//   k_bin          a1+a2  storage bin of every cell (its voxel, cut into XSUB slabs along x;
+//                         FP64 key) and an integer-atomic histogram, one atomic per run of
+//                         equal bins in a wave
+//   k_scan_reduce  a3     per-tile sums of (count, occupied voxels) packed in 64 bits
 //   k_scan_top            exclusive scan of the tile sums (one workgroup)
-//   k_scan_down           voxel_start (exclusive prefix), occupied-voxel list, count reset
-//   k_scatter      a4     cells into their voxel's segment (arbitrary order inside it)
-//   k_rank_gather  a4+a5  rank inside the segment by ascending id -> final slot; gather of
-//                         the cell state into voxel order (+ the float shadow)
+//   k_scan_down           bin starts (exclusive prefix), occupied-voxel list, count reset
+//   k_scatter      a4     cells into their bin's segment (arbitrary order inside it)
+//   k_rank_gather  a4+a5  rank inside the bin by ascending id -> final slot; gather of the
+//                         cell state into that order (+ the float shadow)
 //   k_force_*      a6+a7  27-voxel neighbour forces -> velocity, Adams-Bashforth, walls
+//   k_div_*               growing populations only: division after the walls
 //   k_step_end            per-simulation step counters
 // The paper measures the mechanics "update velocity" loop as the region that degrades
 // when cells sit in memory in creation order rather than next to their neighbours in
 // space (Section 5.4); here every step re-sorts cells by voxel, so the force kernel
 // always reads neighbours that are contiguous in memory, and it visits only occupied
-// voxels' cells (Section 5.4: skip empty voxels).
+// voxels' cells (Section 5.4: skip empty voxels).  For the locality study the reorder
+// can be skipped between steps (k_rank_perm instead of the gather; the force kernel then
+// reads candidates through the sorted index), with bitwise the same results.
 //
 // Batches.  Every kernel serves a batch of independent simulations ("slots"): slot k
 // owns the cell range [cell_off, cell_off + n_cells) and the voxel range
@@ -28,14 +33,15 @@
 // one slot.
 //
 // State layout (structure of arrays, one entry per cell, capacity-sized):
-//   X[3]    f64  positions in the order of the last sort (integration output, binning input)
-//   XS[3]   f64  positions gathered into this step's voxel order (force input)
+//   X[3]    f64  positions in storage order (integration output, binning input)
+//   XS[3]   f64  positions gathered into this step's bin order (force input)
 //   R[2]    f64  radius, T[2] i32 type, ID[2] u32 cell id, VP[2][3] v_prev (f64 or f32):
 //                double-buffered; parity p holds them in the order of X
-//   SH      float4 (x, y, z, r) in voxel order, FP32 variants only
+//   SH      float4 (x, y, z, r) in bin order, FP32 variants only
 //   slot_of u32  slot of the cell at each index (constant between repacks)
 // Binning scratch: vid_cur, off, tmp_key, tmp_src, vid_sorted (u32 per cell);
-// count, voxel_start, occ (u32 per voxel); tile sums (u64 per 2048 voxels).
+// count, voxel_start (u32 per bin, XSUB bins per voxel), occ (u32 per voxel); tile sums
+// (u64 per 2048 bins).
 
 #include <hip/hip_runtime.h>
 

@@ -9,7 +9,8 @@
 
 `traffic` scales the per-dispatch FETCH_SIZE and WRITE_SIZE (KiB) of a kernel by what the
 same counters read for a streaming copy of known size, and records the SHA-256 of the
-kernel source so a reader can tell whether the figure still describes the current code.
+kernel source's code (comments and blank space removed) so a reader can tell whether the
+figure still describes the current code.
 """
 from __future__ import annotations
 
@@ -23,9 +24,33 @@ import sys
 SOURCE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "mech.hip")
 
 
+def code_of(text: str) -> str:
+    """The source without comments and blank space: edits to comments or layout leave
+    it, and so the figures taken on it, unchanged."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        if text.startswith("//", i):
+            i = text.find("\n", i)
+            i = n if i < 0 else i
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+        elif text[i] == '"':
+            j = i + 1
+            while j < n and text[j] != '"':
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        else:
+            out.append(text[i])
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def source_sha256() -> str:
-    with open(SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    """SHA-256 of the kernel source's code (comments and blank space removed)."""
+    with open(SOURCE, encoding="utf-8") as f:
+        return hashlib.sha256(code_of(f.read()).encode()).hexdigest()
 
 
 def _short(name: str) -> str:
@@ -40,7 +65,7 @@ def stats(path: str, command: str, top: int = 25) -> str:
     rows = list(csv.DictReader(open(path)))
     total = sum(float(r["TotalDurationNs"]) for r in rows)
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
-    out = [f"command: {command}", f"source_sha256(csrc/mech.hip): {source_sha256()}",
+    out = [f"command: {command}", f"source_sha256(csrc/mech.hip code): {source_sha256()}",
            f"kernels: {len(rows)}  total kernel time: {total / 1e6:.3f} ms", "",
            f"{'calls':>7} {'avg_us':>10} {'min_us':>10} {'max_us':>10} {'pct':>6}  name"]
     for r in rows[:top]:
@@ -94,7 +119,7 @@ def traffic(a) -> str:
     lines = [
         f"command (FETCH_SIZE): {a.command_fetch}",
         f"command (WRITE_SIZE): {a.command_write}",
-        f"source_sha256(csrc/mech.hip): {source_sha256()}",
+        f"source_sha256(csrc/mech.hip code): {source_sha256()}",
         f"kernel: {a.kernel}  ({len(kf)} dispatches; {'; '.join(_short(k) for k in kn)})",
         f"workload: {a.workload}",
         f"tuning: {a.tuning}",
@@ -114,7 +139,7 @@ def pmc(paths, kernel: str, commands) -> str:
     """Mean per dispatch of every counter in the counter-collection CSVs, for the
     dispatches of kernels whose name contains `kernel`."""
     lines = [f"command: {c}" for c in commands]
-    lines.append(f"source_sha256(csrc/mech.hip): {source_sha256()}")
+    lines.append(f"source_sha256(csrc/mech.hip code): {source_sha256()}")
     lines.append(f"kernel: {kernel}")
     for path in paths:
         acc = collections.defaultdict(lambda: collections.defaultdict(float))
@@ -137,7 +162,7 @@ def read_traffic(path: str):
     for line in open(path):
         k, _, v = line.partition(":")
         vals[k.strip()] = v.strip()
-    return (float(vals["traffic_bytes_per_launch"]), vals["source_sha256(csrc/mech.hip)"],
+    return (float(vals["traffic_bytes_per_launch"]), vals["source_sha256(csrc/mech.hip code)"],
             vals.get("workload", ""), vals.get("tuning", ""))
 
 

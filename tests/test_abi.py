@@ -190,3 +190,12 @@ def test_binding_fails_loudly_without_the_library(monkeypatch, tmp_path):
     monkeypatch.setattr(B, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(ImportError):
         B.lib()
+
+
+def test_profile_hash_ignores_comments_only():
+    from paper_2306_11544_amd.rocprof_summary import code_of
+    a = 'int f(int x) { return x + 1; } // one\n/* block */ const char* s = "a // b";\n'
+    b = 'int f(int x)  {\n  return x + 1;\n}\n// two\nconst char* s = "a // b";'
+    c = 'int f(int x) { return x + 2; }\nconst char* s = "a // b";'
+    assert code_of(a) == code_of(b) != code_of(c)
+    assert '"a // b"' in code_of(a)
