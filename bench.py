@@ -65,6 +65,33 @@ def measured_traffic(kernel: str, workload: str, precision: str, tuning: dict):
     return b if sha == RS.source_sha256() and tun == tuning_str(tuning) else None
 
 
+def measured_counters(kernel: str, workload: str, precision: str, tuning: dict):
+    """Issue and pipe utilisation of `kernel` from its committed PMC summary (None when
+    there is none, it was taken with another launch configuration, or the kernel source
+    has changed since):
+      valu_issue_frac  wave64 VALU instructions / issue slots (one per CU per cycle;
+                       GRBM_GUI_ACTIVE sums the 8 XCDs' cycles)
+      valu_lane_util   active lanes per VALU instruction / 64
+      td_busy_frac     texture-data (vector load return) busy cycles / cycles"""
+    import re
+    from paper_2306_11544_amd import rocprof_summary as RS
+    path = os.path.join(ROOT, "profiles", f"pmc_{kernel}_{workload}_{precision}.txt")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    sha = re.search(r"source_sha256\(csrc/mech.hip code\): (\w+)", text)
+    tun = re.search(r"--tuning (\S+)", text)
+    if not sha or sha.group(1) != RS.source_sha256() or not tun or tun.group(1) != tuning_str(tuning):
+        return None
+    v = {m.group(1): float(m.group(2)) for m in re.finditer(r"^(\w+): ([0-9.e+-]+)", text, re.M)}
+    cus, xcds = 256, 8
+    cycles = v["GRBM_GUI_ACTIVE"] / xcds
+    return {"valu_issue_frac": v["SQ_INSTS_VALU"] / (cus * cycles),
+            "valu_lane_util": v["SQ_THREAD_CYCLES_VALU"] / (64.0 * v["SQ_ACTIVE_INST_VALU"]),
+            "td_busy_frac": v["TD_TD_BUSY_sum"] / (cus * cycles),
+            "source": os.path.relpath(path, ROOT)}
+
+
 def copy_calibration(mb: int, stream):
     """A streaming kernel of known traffic (y = -x over mb MiB of float32: reads and
     writes mb MiB) for scaling the HBM counters of a profiled run."""
@@ -401,6 +428,7 @@ def main():
     if args.calibrate_copy_mb:
         copy_calibration(args.calibrate_copy_mb, stream)
     traffic = measured_traffic(kname, pop.name, precision, tuning)
+    counters = measured_counters(kname, pop.name, precision, tuning)
 
     out = {
         "metric": METRIC,
@@ -430,6 +458,7 @@ def main():
                      "traffic": traffic,
                      "traffic_GBs": None if traffic is None else traffic / (force_ms * 1e-3) / 1e9,
                      "force_ms_per_launch": force_ms,
+                     "counters": counters,
                      "hbm_algorithmic_GBs": force_gbs,
                      "hbm_frac": force_gbs / PEAK_HBM_GBS},
     }
