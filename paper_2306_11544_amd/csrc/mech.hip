@@ -1417,13 +1417,13 @@ __global__ __launch_bounds__(BLOCK) void k_unpermute(uint32_t cell_off, uint32_t
     const uint32_t t = blockIdx.x * BLOCK + threadIdx.x;
     if (t >= n) return;
     const uint32_t s = cell_off + t;
-    const uint32_t k = id[s] - cell_off;
-    pos[3 * k + 0] = x0[s];
-    pos[3 * k + 1] = x1[s];
-    pos[3 * k + 2] = x2[s];
-    vel[3 * k + 0] = (double)v0[s];
-    vel[3 * k + 1] = (double)v1[s];
-    vel[3 * k + 2] = (double)v2[s];
+    const size_t k = 3 * (size_t)(id[s] - cell_off);  // 64-bit: 3 * id passes 2^32 near 1.4e9 cells
+    pos[k + 0] = x0[s];
+    pos[k + 1] = x1[s];
+    pos[k + 2] = x2[s];
+    vel[k + 0] = (double)v0[s];
+    vel[k + 1] = (double)v1[s];
+    vel[k + 2] = (double)v2[s];
 }
 
 // ------------------------------------------------------------------------ host side
@@ -2589,11 +2589,15 @@ int read_binning(MechPopulation* P, uint32_t* voxel_of_cell, uint32_t* voxel_sta
     if (n > 0) HIP_TRY(hipMemcpy(&m, B->arena + L.hdr + 4 * H_OCC, 4, hipMemcpyDeviceToHost));
     if (n_occ) *n_occ = m;
     if (voxel_start) {
-        // voxel v starts at its first bin, XSUB * v
-        if (n > 0)
-            HIP_TRY(hipMemcpy2D(voxel_start, 4, B->arena + L.start, 4 * XSUB, 4, V + 1, hipMemcpyDeviceToHost));
-        else
+        // voxel v starts at its first bin, XSUB * v (one contiguous copy: a strided copy
+        // of tens of millions of 4-byte rows is far slower)
+        if (n > 0) {
+            std::vector<uint32_t> bins(XSUB * V + 1);
+            HIP_TRY(hipMemcpy(bins.data(), B->arena + L.start, bins.size() * 4, hipMemcpyDeviceToHost));
+            for (size_t v = 0; v <= V; ++v) voxel_start[v] = bins[XSUB * v];
+        } else {
             std::memset(voxel_start, 0, (V + 1) * 4);
+        }
     }
     if (occ && m) HIP_TRY(hipMemcpy(occ, B->arena + L.occ, (size_t)m * 4, hipMemcpyDeviceToHost));
     if (n == 0) return MECH_OK;
