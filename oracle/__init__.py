@@ -16,6 +16,13 @@ Parity status of each function (what pins it is listed in tests/test_oracle_*.py
                      in 50-digit arithmetic, reflecting-wall special cases
   FP32 variants      pinned: decisions equal FP64 on well-separated pairs; Kahan sum
                      within the textbook compensated-summation bound of math.fsum
+  velocity_sampled   pinned: equals velocity_voxel on the sampled cells
+  splitmix64         pinned: the generator's published reference outputs (tests/golden)
+  uniform / divide / pinned: uniformity, selection by the draws, ranks and ids, parent and
+  run_growing        daughter at distance r around the parent's position (no-force
+                     cases), capacity limit, walls, and p_div = 0 equal to run
+Every function is pinned; none is "parity unpinned".  The absolute many-cell
+trajectories rest on the pins above plus the GPU comparison (see the design notes).
 """
 from __future__ import annotations
 
