@@ -22,7 +22,7 @@ Parity status of each function (what pins it is listed in tests/test_oracle_*.py
   run_growing        daughter at distance r around the parent's position (no-force
                      cases), capacity limit, walls, and p_div = 0 equal to run
 Every function is pinned; none is "parity unpinned".  The absolute many-cell
-trajectories rest on the pins above plus the GPU comparison (see the design notes).
+trajectories rest on the pins above plus the comparison with the GPU path.
 """
 from __future__ import annotations
 

@@ -46,9 +46,10 @@ def run_gpu(pop, steps, precision=B.MECH_FP64, ab2_start=B.MECH_AB2_ZERO_HISTORY
 
 
 def record(case, err, **extra):
-    """Append a parity error to gpurun_out/parity_errors.jsonl (the error table)."""
-    out = os.environ.get("MECH_PARITY_LOG", os.path.join(ROOT, "gpurun_out", "parity_errors.jsonl"))
-    if os.path.isdir(os.path.dirname(out)):
+    """Append a parity error to the JSON-lines file named by MECH_PARITY_LOG, if set (the
+    error table of the design notes is built from it)."""
+    out = os.environ.get("MECH_PARITY_LOG")
+    if out and os.path.isdir(os.path.dirname(os.path.abspath(out))):
         with open(out, "a") as f:
             f.write(json.dumps({"case": case, "err": float(err), **extra}) + "\n")
 
