@@ -46,8 +46,8 @@ def run_gpu(pop, steps, precision=B.MECH_FP64, ab2_start=B.MECH_AB2_ZERO_HISTORY
 
 
 def record(case, err, **extra):
-    """Append a parity error to the JSON-lines file named by MECH_PARITY_LOG, if set (the
-    error table of the design notes is built from it)."""
+    """Append a parity error to the JSON-lines file named by MECH_PARITY_LOG, if set:
+    the per-configuration error table is collected this way."""
     out = os.environ.get("MECH_PARITY_LOG")
     if out and os.path.isdir(os.path.dirname(os.path.abspath(out))):
         with open(out, "a") as f:
