@@ -429,6 +429,124 @@ __global__ __launch_bounds__(BLOCK) void k_rank_gather(const uint32_t* __restric
     }
 }
 
+// ------------------------------------------------------------------------ a1..a5, small populations
+
+// A population of at most SMALL_CELLS cells in at most SMALL_BINS bins is binned by one
+// workgroup in one launch: counts, scan, scatter and the rank by id in LDS, then the
+// gather.  Small populations are bound by launch latency, not bandwidth, and this
+// replaces six dependent launches.  Same keys, scan, ranks and gather as the general
+// path: the same order and outputs, bitwise.
+constexpr uint32_t SMALL_CELLS = 8192;
+constexpr uint32_t SMALL_BINS = 8192;
+constexpr uint32_t SMALL_PER_THREAD = SMALL_CELLS / BLOCK;
+static_assert(SMALL_BINS / BLOCK == SMALL_PER_THREAD && SMALL_PER_THREAD % XSUB == 0, "scan layout");
+
+template <typename VPT>
+__global__ __launch_bounds__(BLOCK) void k_bin_small(const uint32_t* __restrict__ slot_of,
+                                                     const SlotDesc* __restrict__ slots,
+                                                     uint32_t* __restrict__ hdr,
+                                                     const uint32_t* __restrict__ id_cur,
+                                                     uint32_t* __restrict__ vid_cur,
+                                                     uint32_t* __restrict__ bin_start,
+                                                     uint32_t* __restrict__ occ, GatherArgs<VPT> a)
+{
+    __shared__ uint32_t s_start[SMALL_BINS + 1];   // counts, then bin starts
+    __shared__ uint32_t s_key[SMALL_CELLS];
+    __shared__ uint32_t s_src[SMALL_CELLS];
+    __shared__ uint32_t s_vid[SMALL_CELLS];
+    __shared__ uint64_t sh[BLOCK / WAVE];
+    const uint32_t n = hdr[H_CELLS];
+    const uint32_t S = XSUB * hdr[H_VOXELS];
+    const uint32_t t = threadIdx.x;
+    for (uint32_t b = t; b <= SMALL_BINS; b += BLOCK) s_start[b] = 0u;
+    __syncthreads();
+    // a1 + a2
+    uint32_t off[SMALL_PER_THREAD];
+#pragma unroll
+    for (uint32_t k = 0; k < SMALL_PER_THREAD; ++k) {
+        const uint32_t s = t + k * BLOCK;
+        off[k] = 0;
+        if (s < n) {
+            const SlotDesc& d = slots[slot_of[s]];
+            const uint32_t v = XSUB * d.voxel_off + bin_key(a.X[0][s], a.X[1][s], a.X[2][s], d);
+            s_vid[s] = v;
+            vid_cur[s] = v;
+            off[k] = atomicAdd(&s_start[v], 1u);
+        }
+    }
+    __syncthreads();
+    // a3: each thread scans SMALL_PER_THREAD consecutive bins (whole voxels)
+    const uint32_t b0 = t * SMALL_PER_THREAD;
+    uint32_t cnt[SMALL_PER_THREAD];
+    bool first_occ[SMALL_PER_THREAD];
+    uint64_t loc[SMALL_PER_THREAD];
+    uint64_t sum = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < SMALL_PER_THREAD; ++k) cnt[k] = b0 + k < S ? s_start[b0 + k] : 0u;
+#pragma unroll
+    for (uint32_t k = 0; k < SMALL_PER_THREAD; ++k) {
+        bool f = false;
+        if (k % XSUB == 0) {
+            uint32_t any = 0;
+#pragma unroll
+            for (uint32_t m = 0; m < XSUB; ++m) any |= cnt[k + m];
+            f = any != 0u;
+        }
+        first_occ[k] = f;
+        loc[k] = sum;
+        sum += (uint64_t)cnt[k] | ((uint64_t)f << 32);
+    }
+    uint64_t tot;
+    const uint64_t base = block_excl_scan(sum, sh, &tot);   // synchronises the workgroup
+#pragma unroll
+    for (uint32_t k = 0; k < SMALL_PER_THREAD; ++k) {
+        const uint32_t b = b0 + k;
+        if (b < S) {
+            const uint64_t e = base + loc[k];
+            s_start[b] = (uint32_t)e;
+            bin_start[b] = (uint32_t)e;
+            if (first_occ[k]) occ[(uint32_t)(e >> 32)] = b / XSUB;
+        }
+    }
+    if (t == 0) {
+        s_start[S] = (uint32_t)tot;
+        bin_start[S] = (uint32_t)tot;
+        hdr[H_OCC] = (uint32_t)(tot >> 32);
+    }
+    __syncthreads();
+    // a4: scatter into the bins, then rank by id
+#pragma unroll
+    for (uint32_t k = 0; k < SMALL_PER_THREAD; ++k) {
+        const uint32_t s = t + k * BLOCK;
+        if (s < n) {
+            const uint32_t p = s_start[s_vid[s]] + off[k];
+            s_key[p] = id_cur[s];
+            s_src[p] = s;
+        }
+    }
+    __syncthreads();
+    // a4 + a5: final slot and gather
+    for (uint32_t p = t; p < n; p += BLOCK) {
+        const uint32_t s = s_src[p], key = s_key[p], v = s_vid[s];
+        const uint32_t b = s_start[v], e = s_start[v + 1];
+        uint32_t rank = 0;
+        for (uint32_t q = b; q < e; ++q) rank += s_key[q] < key;
+        const uint32_t d = b + rank;
+        const double x = a.X[0][s], y = a.X[1][s], z = a.X[2][s];
+        const double r = a.R_cur[s];
+        a.XS[0][d] = x;
+        a.XS[1][d] = y;
+        a.XS[2][d] = z;
+        a.R_new[d] = r;
+        a.T_new[d] = a.T_cur[s];
+        a.ID_new[d] = key;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) a.VP_new[c][d] = a.VP_cur[c][s];
+        a.vid_sorted[d] = v;
+        if (a.SH) a.SH[d] = make_float4((float)x, (float)y, (float)z, (float)r);
+    }
+}
+
 // Cells left in place (the locality study): a4 only.  perm[slot] = storage index of the
 // cell that the sorted order puts in that slot (the same (bin, id) order as a4 + a5).
 __global__ __launch_bounds__(BLOCK) void k_rank_perm(const uint32_t* __restrict__ hdr,
@@ -1650,6 +1768,13 @@ void enqueue_keys(MechBatch* B)
                        B->at<uint32_t>(L.tmp_key), B->at<uint32_t>(L.tmp_src));
 }
 
+// A single small population takes the one-launch path (k_bin_small).
+bool small_binning(const MechBatch* B)
+{
+    return B->cap_slots == 1 && B->cap_cells <= (int64_t)SMALL_CELLS &&
+           (int64_t)XSUB * B->cap_voxels <= (int64_t)SMALL_BINS;
+}
+
 template <typename VPT>
 void enqueue_binning(MechBatch* B)
 {
@@ -1657,7 +1782,7 @@ void enqueue_binning(MechBatch* B)
     const int cur = B->parity, nxt = cur ^ 1;
     const uint32_t nbc = cell_grid(B);
     const uint32_t* hdr = B->at<uint32_t>(L.hdr);
-    enqueue_keys(B);
+    if (!small_binning(B)) enqueue_keys(B);
     GatherArgs<VPT> g{};
     for (int c = 0; c < 3; ++c) {
         g.X[c] = B->at<double>(L.X[c]);
@@ -1676,7 +1801,12 @@ void enqueue_binning(MechBatch* B)
     g.tmp_src = B->at<uint32_t>(L.tmp_src);
     g.voxel_start = B->at<uint32_t>(L.start);
     g.vid_sorted = B->at<uint32_t>(L.vid_sorted);
-    hipLaunchKernelGGL(k_rank_gather<VPT>, dim3(nbc), dim3(BLOCK), 0, B->stream, hdr, g);
+    if (small_binning(B))
+        hipLaunchKernelGGL(k_bin_small<VPT>, dim3(1), dim3(BLOCK), 0, B->stream, B->at<uint32_t>(L.slot_of),
+                           B->at<SlotDesc>(L.slots), B->at<uint32_t>(L.hdr), B->at<uint32_t>(L.ID[cur]),
+                           B->at<uint32_t>(L.vid_cur), B->at<uint32_t>(L.start), B->at<uint32_t>(L.occ), g);
+    else
+        hipLaunchKernelGGL(k_rank_gather<VPT>, dim3(nbc), dim3(BLOCK), 0, B->stream, hdr, g);
 }
 
 // Workgroups of a per-cell force kernel: one per WPB*64 cells of the arena's capacity,
