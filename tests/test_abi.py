@@ -199,3 +199,17 @@ def test_profile_hash_ignores_comments_only():
     c = 'int f(int x) { return x + 2; }\nconst char* s = "a // b";'
     assert code_of(a) == code_of(b) != code_of(c)
     assert '"a // b"' in code_of(a)
+
+
+def test_plain_c_client(tmp_path):
+    """The boundary is a C ABI: a C program built against include/mech.h alone links
+    libmech.so and gets the documented answers (no GPU needed for these calls)."""
+    B.lib()  # builds nothing; fails loudly if the library is missing
+    exe = tmp_path / "client"
+    src = os.path.join(ROOT, "tests", "c_abi_client.c")
+    subprocess.run(["gcc", "-std=c11", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"), src,
+                    B.LIB_PATH, f"-Wl,-rpath,{os.path.dirname(B.LIB_PATH)}", "-o", str(exe)],
+                   check=True)
+    res = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
+    assert res.returncode == 0, res.stdout + res.stderr
+    assert "client ok" in res.stdout
