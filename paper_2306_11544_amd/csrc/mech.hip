@@ -993,9 +993,10 @@ __device__ __forceinline__ int64_t row_first(const Cellgeo& g, const SlotDesc& d
 
 // ------------------------------------------------------------------------ a6 + a7, row kernel
 
-// One thread per cell in voxel order.  The 27 neighbour voxels are visited as 9 rows
-// (dz, dy); the three voxels of a row (dx = -1, 0, 1) are adjacent in voxel order, so a
-// row is one contiguous range of the sorted arrays, read in the oracle's order.
+// One thread per cell in storage (bin) order.  The 27 neighbour voxels are visited as 9
+// rows (dz, dy); the three voxels of a row (dx = -1, 0, 1) are adjacent in the sorted
+// order, so a row is one contiguous range of the sorted arrays, read in the oracle's
+// order.  Every candidate of the 27 voxels is tested (no slab window).
 // PREC: 0 FP64, 1 FP32, 2 FP32 + Kahan.  MULTI: more than one cell type.
 template <int PREC, bool MULTI, typename VPT>
 __device__ __forceinline__ void force_rows_cell(const PhysArgs& P, const ForceArgs<VPT>& a, uint32_t i,
@@ -1075,16 +1076,17 @@ __global__ __launch_bounds__(WPB * WAVE) void k_force_rows(PhysArgs P, ForceArgs
 constexpr int FC_LIST = 16;    // listed candidates a lane holds before a flush
 // UNROLL: candidates tested per loop trip (independent loads in flight), at most FC_LIST / 2
 
-// One thread per cell in voxel order.  Each lane walks its 9 neighbour rows and only
-// prefilters the candidates, four loads in flight per trip: a candidate is listed in
-// LDS when
+// One thread per cell in storage (bin) order.  Each lane walks its 9 neighbour rows,
+// reading in each only the x slabs within reach of its cell (a contiguous run: slabs of
+// x-adjacent voxels follow each other), and only prefilters the candidates, FC_UNROLL
+// loads in flight per trip: a candidate is listed in LDS when
 //   d2 < (alpha (r_i + r_max))^2,
 // which every interacting pair satisfies (r_j <= r_max and rounding is monotonic; d2
 // is the same expression as in the exact test).  When a list fills, and at the end,
 // the lanes evaluate their listed candidates together with the exact decision and
 // pair term of pair64 / pair32, in candidate order, so each sum is still taken in the
 // fixed neighbour order and the rare interacting pairs do not make the wave diverge.
-// Lanes of one voxel read the same candidate at the same time (one cache line).
+// Lanes of one slab read the same candidate at the same time (one cache line).
 // IND: the cells are left in storage order; candidate slot j of the sorted order is read
 // through perm[j] (the locality study).  The candidates, their order and the arithmetic
 // are those of the reordered path, so the results are bitwise the same.
