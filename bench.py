@@ -50,7 +50,7 @@ FORCE_BYTES_PER_CELL = {"fp64": 24 + 32 + 4 + 48 + 24, "fp32": 24 + 32 + 4 + 24 
 
 
 def tuning_str(t: dict) -> str:
-    return ",".join(str(t[k]) for k in ("force_kernel", "block_waves", "unroll", "blocks_per_cu"))
+    return ",".join(str(t[k]) for k in ("force_kernel", "block_waves", "unroll", "blocks_per_cu", "list_len"))
 
 
 def measured_traffic(kernel: str, workload: str, precision: str, tuning: dict):
@@ -321,8 +321,9 @@ def main():
     ap.add_argument("--locality", action="store_true",
                     help="run the locality ablation (reorder every 1, 10, 100 steps, never)")
     ap.add_argument("--tuning", default="",
-                    help="fixed force-kernel configuration K,W,U,G (kernel flag, waves per "
-                         "workgroup, candidates per trip, workgroups per CU); skips the tuner")
+                    help="fixed force-kernel configuration K,W,U,G[,L] (kernel flag, waves per "
+                         "workgroup, candidates per trip, workgroups per CU, list entries per "
+                         "lane); skips the tuner")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="after the run, a streaming copy of this size for counter scaling")
     args = ap.parse_args()

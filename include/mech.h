@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define MECH_ABI_VERSION 1
+#define MECH_ABI_VERSION 2
 
 enum {
     MECH_OK = 0,
@@ -103,6 +103,9 @@ typedef struct MechTuning {
                                    (default): one per block_waves*64 cells of capacity
                                    (at most 32768 wave64s) for the per-cell kernels and
                                    4 per compute unit for the voxel kernel              */
+    int32_t list_len;           /* in-range candidates a lane of the list kernel holds
+                                   before the wave evaluates them: 16, 32, 64, or 0
+                                   (default: 16)                                        */
 } MechTuning;
 
 typedef struct MechPopulation MechPopulation;

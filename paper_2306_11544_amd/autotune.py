@@ -2,8 +2,10 @@
 
 The force kernel has three variants (per-cell list kernel, per-cell inline kernel,
 wave-per-voxel LDS kernel) and, for the per-cell ones, a workgroup size (wave64s per
-workgroup), a tile (candidates tested per loop trip) and a grid size (workgroups per
-compute unit).  Which is fastest depends on the density and size mix of the
+workgroup), a tile (candidates tested per loop trip), a grid size (workgroups per
+compute unit) and, for the list kernel, the list length (in-range candidates a lane
+holds before the wave evaluates them: longer lists keep more lanes busy in each
+evaluation pass but take LDS that would hold more waves).  Which is fastest depends on the density and size mix of the
 simulations, so the tuner times each candidate configuration on a scratch copy of the
 workload (the real batch's trajectories are not advanced) and keeps the fastest.
 Every configuration gives the same results up to the summation order of the force sums.
@@ -30,13 +32,14 @@ NOISE = 0.02   # relative timing difference below which the default configuratio
 
 
 def search_space():
-    """Candidate configurations: the list kernel over workgroup size x tile x grid, the
-    inline kernel over workgroup size, the LDS kernel over grid size."""
+    """Candidate configurations: the list kernel over workgroup size x tile x grid x list
+    length, the inline kernel over workgroup size, the LDS kernel over grid size."""
     space = []
     for w in (1, 2, 4, 8):
         for u in (2, 4, 8):
             for g in (0, 16):
-                space.append(B.tuning("cells", w, u, g))
+                for ln in (0, 32):
+                    space.append(B.tuning("cells", w, u, g, ln))
     for w in (2, 4, 8):
         space.append(B.tuning("rows", w, 4, 0))
     for g in (2, 4, 8):

@@ -24,7 +24,7 @@ MECH_FLAG_SIMPLE_FORCE = 2
 MECH_FLAG_VOXEL_FORCE = 4
 MECH_FORCE_KERNEL_MASK = 6
 FORCE_KERNELS = {"cells": 0, "rows": MECH_FLAG_SIMPLE_FORCE, "voxel": MECH_FLAG_VOXEL_FORCE}
-MECH_ABI_VERSION = 1
+MECH_ABI_VERSION = 2
 
 PRECISIONS = {"fp64": MECH_FP64, "fp32": MECH_FP32, "fp32k": MECH_FP32_KAHAN}
 
@@ -57,16 +57,17 @@ class MechParams(C.Structure):
 
 class MechTuning(C.Structure):
     _fields_ = [("force_kernel", C.c_int32), ("block_waves", C.c_int32), ("unroll", C.c_int32),
-                ("blocks_per_cu", C.c_int32)]
+                ("blocks_per_cu", C.c_int32), ("list_len", C.c_int32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
-def tuning(force_kernel=0, block_waves=4, unroll=4, blocks_per_cu=0) -> MechTuning:
+def tuning(force_kernel=0, block_waves=4, unroll=4, blocks_per_cu=0, list_len=0) -> MechTuning:
     if isinstance(force_kernel, str):
         force_kernel = FORCE_KERNELS[force_kernel]
-    return MechTuning(int(force_kernel), int(block_waves), int(unroll), int(blocks_per_cu))
+    return MechTuning(int(force_kernel), int(block_waves), int(unroll), int(blocks_per_cu),
+                      int(list_len))
 
 
 _lib = None

@@ -1073,16 +1073,21 @@ __global__ __launch_bounds__(WPB * WAVE) void k_force_rows(PhysArgs P, ForceArgs
 
 // ------------------------------------------------------------------------ a6 + a7, list kernel
 
-constexpr int FC_LIST = 16;    // listed candidates a lane holds before a flush
-// UNROLL: candidates tested per loop trip (independent loads in flight), at most FC_LIST / 2
+// LIST: candidates a lane can hold listed before a flush (16, 32 or 64).
+// UNROLL: candidates tested per loop trip (independent loads in flight), at most LIST / 2.
 
 // One thread per cell in storage (bin) order.  Each lane walks its 9 neighbour rows,
 // reading in each only the x slabs within reach of its cell (a contiguous run: slabs of
 // x-adjacent voxels follow each other), and only prefilters the candidates, FC_UNROLL
-// loads in flight per trip: a candidate is listed in LDS when
-//   d2 < (alpha (r_i + r_max))^2,
-// which every interacting pair satisfies (r_j <= r_max and rounding is monotonic; d2
-// is the same expression as in the exact test).  When a list fills, and at the end,
+// loads in flight per trip.  A candidate is listed in LDS when
+//   FP64:  d2 < (alpha (r_i + r_max))^2
+//   FP32:  d2 < fl(s * s),  s = fma(a', r_j, fl(a' r_i)),  a' = fl(alpha (1 + 2^-18)),
+// which every interacting pair satisfies: d2 is the same expression as in the exact
+// test; in FP64 r_j <= r_max and rounding is monotonic; in FP32 the exact bound
+// fl(fl(alpha fl(r_i + r_j))^2) is at most alpha^2 (r_i + r_j)^2 (1 + 2^-24)^5, while
+// fl(s * s) is at least alpha^2 (r_i + r_j)^2 (1 + 2^-18)^2 (1 - 2^-24)^7, which is
+// larger.  The FP32 form uses r_j (the w of the float4 already loaded), so it lists
+// little beyond the interacting pairs.  When a list fills, and at the end,
 // the lanes evaluate their listed candidates together with the exact decision and
 // pair term of pair64 / pair32, in candidate order, so each sum is still taken in the
 // fixed neighbour order and the rare interacting pairs do not make the wave diverge.
@@ -1090,7 +1095,7 @@ constexpr int FC_LIST = 16;    // listed candidates a lane holds before a flush
 // IND: the cells are left in storage order; candidate slot j of the sorted order is read
 // through perm[j] (the locality study).  The candidates, their order and the arithmetic
 // are those of the reordered path, so the results are bitwise the same.
-template <int PREC, bool MULTI, typename VPT, int FC_UNROLL, bool IND = false>
+template <int PREC, bool MULTI, typename VPT, int FC_UNROLL, int LIST, bool IND = false>
 __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceArgs<VPT>& a, uint32_t i,
                                                  uint32_t n, uint32_t* const list0, uint32_t& inter,
                                                  uint32_t& cand)
@@ -1130,34 +1135,47 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
         zi = m.z;
         ri = m.w;
     }
-    Real T;
+    Real T;      // FP64: the prefilter bound
+    float al, ai;  // FP32: a' and fl(a' r_i)
     {
 #pragma clang fp contract(off)
-        const Real reach = (PREC == 0 ? (Real)P.alpha : (Real)P.alpha_f) *
-                           (ri + (PREC == 0 ? (Real)d.r_max : (Real)d.r_max_f));
-        T = reach * reach;
+        if constexpr (PREC == 0) {
+            const double reach = P.alpha * (ri + d.r_max);
+            T = reach * reach;
+        } else {
+            al = P.alpha_f * (1.0f + 0x1p-18f);
+            ai = al * ri;
+        }
     }
     const int ti = MULTI ? a.T[ii] : 0;
     Real acc[3] = {0, 0, 0}, cmp[3] = {0, 0, 0};
-    uint32_t* const list_hi = list0 + (FC_LIST - FC_UNROLL) * WAVE;
-    uint32_t* lp = list0;
+    // list0[k * WAVE], k < cnt: the listed candidates.  Every tested candidate is written
+    // at index cnt and counted only when it passed (no branch); cnt <= LIST - FC_UNROLL
+    // when a trip starts, so the writes stay below LIST.
+    uint32_t cnt = 0;
+    auto push = [&](uint32_t j, bool in) {
+        list0[cnt * WAVE] = j;
+        cnt += in ? 1u : 0u;
+    };
+    auto full = [&]() { return __any(cnt > (uint32_t)(LIST - FC_UNROLL)); };
 
-    auto near = [&](Real cx, Real cy, Real cz) -> bool {
+    // cw: the candidate's radius (FP32 only)
+    auto near = [&](Real cx, Real cy, Real cz, float cw) -> bool {
 #pragma clang fp contract(off)
         const Real dx = xi - cx, dy = yi - cy, dz = zi - cz;
-        Real d2;
-        if constexpr (PREC == 0)
-            d2 = dx * dx + dy * dy + dz * dz;
-        else
-            d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
-        return d2 < T;
+        if constexpr (PREC == 0) {
+            return dx * dx + dy * dy + dz * dz < T;
+        } else {
+            const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
+            const float s = __builtin_fmaf(al, cw, ai);
+            return d2 < s * s;
+        }
     };
     auto flush = [&]() {
-        const uint32_t cnt = (uint32_t)(lp - list0) / WAVE;
-        for (uint32_t q = 0; q < (uint32_t)FC_LIST; ++q) {
-            if (!__any(q < cnt)) break;
-            if (q < cnt) {
-                const uint32_t j = list0[q * WAVE];
+        for (uint32_t k = 0; k < (uint32_t)LIST; ++k) {
+            if (!__any(k < cnt)) break;
+            if (k < cnt) {
+                const uint32_t j = list0[k * WAVE];
                 if constexpr (PREC == 0) {
                     const double cadh = MULTI ? a.cadh[ti * P.n_types + a.T[j]] : P.c_adh0;
                     inter += pair64(xi, yi, zi, ri, a.XS[0][j], a.XS[1][j], a.XS[2][j], a.R[j],
@@ -1169,7 +1187,7 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
                 }
             }
         }
-        lp = list0;
+        cnt = 0;
     };
 
     for (int q = 0; q < 9; ++q) {
@@ -1182,18 +1200,13 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
             // gathers through the sorted order: no locality between consecutive lanes
             for (; j < e; ++j) {
                 const uint32_t jj = a.perm[j];
-                bool in;
                 if constexpr (PREC == 0) {
-                    in = near(a.XS[0][jj], a.XS[1][jj], a.XS[2][jj]);
+                    push(jj, near(a.XS[0][jj], a.XS[1][jj], a.XS[2][jj], 0.0f));
                 } else {
                     const float4 c = a.SH[jj];
-                    in = near(c.x, c.y, c.z);
+                    push(jj, near(c.x, c.y, c.z, c.w));
                 }
-                if (in) {
-                    *lp = jj;
-                    lp += WAVE;
-                }
-                if (__any(lp > list_hi)) flush();
+                if (full()) flush();
             }
             continue;
         }
@@ -1210,19 +1223,12 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
                     cz[u] = pz[u];
                 }
 #pragma unroll
-                for (int u = 0; u < FC_UNROLL; ++u)
-                    if (near(cx[u], cy[u], cz[u])) {
-                        *lp = j + u;
-                        lp += WAVE;
-                    }
-                if (__any(lp > list_hi)) flush();
+                for (int u = 0; u < FC_UNROLL; ++u) push(j + u, near(cx[u], cy[u], cz[u], 0.0f));
+                if (full()) flush();
             }
             for (; j < e; ++j, ++px, ++py, ++pz) {
-                if (near(*px, *py, *pz)) {
-                    *lp = j;
-                    lp += WAVE;
-                }
-                if (__any(lp > list_hi)) flush();
+                push(j, near(*px, *py, *pz, 0.0f));
+                if (full()) flush();
             }
         } else {
             const float4* sp = a.SH + j;
@@ -1231,20 +1237,13 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
 #pragma unroll
                 for (int u = 0; u < FC_UNROLL; ++u) c[u] = sp[u];
 #pragma unroll
-                for (int u = 0; u < FC_UNROLL; ++u)
-                    if (near(c[u].x, c[u].y, c[u].z)) {
-                        *lp = j + u;
-                        lp += WAVE;
-                    }
-                if (__any(lp > list_hi)) flush();
+                for (int u = 0; u < FC_UNROLL; ++u) push(j + u, near(c[u].x, c[u].y, c[u].z, c[u].w));
+                if (full()) flush();
             }
             for (; j < e; ++j, ++sp) {
                 const float4 c = *sp;
-                if (near(c.x, c.y, c.z)) {
-                    *lp = j;
-                    lp += WAVE;
-                }
-                if (__any(lp > list_hi)) flush();
+                push(j, near(c.x, c.y, c.z, c.w));
+                if (full()) flush();
             }
         }
     }
@@ -1260,12 +1259,12 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
     }
 }
 
-template <int PREC, bool MULTI, typename VPT, int WPB, int UNROLL, bool IND = false>
+template <int PREC, bool MULTI, typename VPT, int WPB, int UNROLL, int LIST, bool IND = false>
 __global__ __launch_bounds__(WPB * WAVE) void k_force_cells(PhysArgs P, ForceArgs<VPT> a)
 {
-    static_assert(2 * UNROLL <= FC_LIST, "a trip must fit the list above the flush mark");
+    static_assert(2 * UNROLL <= LIST, "a trip must fit the list above the flush mark");
     constexpr uint32_t TB = WPB * WAVE;
-    __shared__ uint32_t s_list[WPB][FC_LIST][WAVE];
+    __shared__ uint32_t s_list[WPB][LIST][WAVE];
     const uint32_t n = a.hdr[H_CELLS];
     const uint32_t nb = (n + TB - 1) / TB;
     uint32_t* const list0 = &s_list[threadIdx.x / WAVE][0][threadIdx.x & (WAVE - 1)];
@@ -1275,7 +1274,7 @@ __global__ __launch_bounds__(WPB * WAVE) void k_force_cells(PhysArgs P, ForceArg
         const uint32_t active = min(gridDim.x, nb - lb0);
         if (blockIdx.x >= active) break;
         const uint32_t i = (lb0 + xcd_block(blockIdx.x, active)) * TB + threadIdx.x;
-        force_cells_cell<PREC, MULTI, VPT, UNROLL, IND>(P, a, i, n, list0, inter, cand);
+        force_cells_cell<PREC, MULTI, VPT, UNROLL, LIST, IND>(P, a, i, n, list0, inter, cand);
     }
     add_stats(a.stats, inter, cand);
 }
@@ -1710,7 +1709,7 @@ struct MechBatch {
     int parity = 0;
     int64_t steps = 0;
     int32_t cus = 256;                    // compute units of the device
-    MechTuning tune{0, 4, 4, 0};          // force-kernel launch configuration
+    MechTuning tune{0, 4, 4, 0, 0};       // force-kernel launch configuration
     // locality study: reorder (gather) every reorder_every steps, 0 = never
     int32_t reorder_every = 1;
     // growing populations: division probability per cell and step, draw seed
@@ -1822,14 +1821,24 @@ uint32_t force_cell_grid(const MechBatch* B, int wpb)
     return std::min(tiles, cap);
 }
 
-template <int PREC, bool MULTI, typename VPT, int WPB>
-void launch_cells_w(MechBatch* B, const ForceArgs<VPT>& a)
+template <int PREC, bool MULTI, typename VPT, int WPB, int LIST>
+void launch_cells_l(MechBatch* B, const ForceArgs<VPT>& a)
 {
     const dim3 grid(force_cell_grid(B, WPB)), block(WPB * WAVE);
     switch (B->tune.unroll) {
-    case 2: hipLaunchKernelGGL((k_force_cells<PREC, MULTI, VPT, WPB, 2>), grid, block, 0, B->stream, B->phys, a); break;
-    case 8: hipLaunchKernelGGL((k_force_cells<PREC, MULTI, VPT, WPB, 8>), grid, block, 0, B->stream, B->phys, a); break;
-    default: hipLaunchKernelGGL((k_force_cells<PREC, MULTI, VPT, WPB, 4>), grid, block, 0, B->stream, B->phys, a); break;
+    case 2: hipLaunchKernelGGL((k_force_cells<PREC, MULTI, VPT, WPB, 2, LIST>), grid, block, 0, B->stream, B->phys, a); break;
+    case 8: hipLaunchKernelGGL((k_force_cells<PREC, MULTI, VPT, WPB, 8, LIST>), grid, block, 0, B->stream, B->phys, a); break;
+    default: hipLaunchKernelGGL((k_force_cells<PREC, MULTI, VPT, WPB, 4, LIST>), grid, block, 0, B->stream, B->phys, a); break;
+    }
+}
+
+template <int PREC, bool MULTI, typename VPT, int WPB>
+void launch_cells_w(MechBatch* B, const ForceArgs<VPT>& a)
+{
+    switch (B->tune.list_len) {
+    case 32: launch_cells_l<PREC, MULTI, VPT, WPB, 32>(B, a); break;
+    case 64: launch_cells_l<PREC, MULTI, VPT, WPB, 64>(B, a); break;
+    default: launch_cells_l<PREC, MULTI, VPT, WPB, 16>(B, a); break;
     }
 }
 
@@ -1954,9 +1963,9 @@ void enqueue_force_inplace(MechBatch* B)
     a.perm = B->at<uint32_t>(L.off);
     const dim3 grid(force_cell_grid(B, 4)), block(4 * WAVE);
     if (B->prm.n_types > 1)
-        hipLaunchKernelGGL((k_force_cells<PREC, true, VPT, 4, 4, true>), grid, block, 0, B->stream, B->phys, a);
+        hipLaunchKernelGGL((k_force_cells<PREC, true, VPT, 4, 4, 16, true>), grid, block, 0, B->stream, B->phys, a);
     else
-        hipLaunchKernelGGL((k_force_cells<PREC, false, VPT, 4, 4, true>), grid, block, 0, B->stream, B->phys, a);
+        hipLaunchKernelGGL((k_force_cells<PREC, false, VPT, 4, 4, 16, true>), grid, block, 0, B->stream, B->phys, a);
 }
 
 // a1..a4 without the reorder: keys, scan, scatter, perm (and the float shadow first).
@@ -3056,6 +3065,8 @@ int batch_set_tuning(MechBatch* B, const MechTuning* t)
         return fail(MECH_E_INVALID, "unroll %d not in {2, 4, 8}", t->unroll);
     if (t->blocks_per_cu < 0 || t->blocks_per_cu > 64)
         return fail(MECH_E_INVALID, "blocks_per_cu %d not in [0, 64]", t->blocks_per_cu);
+    if (t->list_len != 0 && t->list_len != 16 && t->list_len != 32 && t->list_len != 64)
+        return fail(MECH_E_INVALID, "list_len %d not in {0, 16, 32, 64}", t->list_len);
     HIP_TRY(hipSetDevice(B->device));
     HIP_TRY(hipStreamSynchronize(B->stream));
     drop_graphs(B);

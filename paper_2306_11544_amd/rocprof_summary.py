@@ -180,7 +180,7 @@ def main(argv=None):
     t.add_argument("--copy-kernel", required=True)
     t.add_argument("--copy-bytes", type=float, required=True)
     t.add_argument("--workload", required=True)
-    t.add_argument("--tuning", default="", help="launch configuration the run used, as K,W,U,G")
+    t.add_argument("--tuning", default="", help="launch configuration the run used, as K,W,U,G,L")
     t.add_argument("--command-fetch", required=True)
     t.add_argument("--command-write", required=True)
     m = sub.add_parser("pmc")

@@ -43,10 +43,10 @@ def test_params_struct_matches_header_layout():
 
 
 def test_tuning_struct_matches_header_layout():
-    assert C.sizeof(B.MechTuning) == 16
-    t = B.tuning("voxel", 8, 2, 16)
+    assert C.sizeof(B.MechTuning) == 20
+    t = B.tuning("voxel", 8, 2, 16, 32)
     assert t.as_dict() == {"force_kernel": B.MECH_FLAG_VOXEL_FORCE, "block_waves": 8, "unroll": 2,
-                           "blocks_per_cu": 16}
+                           "blocks_per_cu": 16, "list_len": 32}
 
 
 def test_tuning_search_space_is_valid():
@@ -57,6 +57,7 @@ def test_tuning_search_space_is_valid():
         assert t.force_kernel in (0, B.MECH_FLAG_SIMPLE_FORCE, B.MECH_FLAG_VOXEL_FORCE)
         assert t.block_waves in (1, 2, 4, 8) and t.unroll in (2, 4, 8)
         assert 0 <= t.blocks_per_cu <= 64
+        assert t.list_len in (0, 16, 32, 64) and 2 * t.unroll <= (t.list_len or 16)
 
 
 def test_tuning_calls_reject_null_handles():

@@ -51,6 +51,23 @@ def test_every_configuration_agrees_with_default():
             assert pos_err(p1, p0, pp.half_width) <= 1e-12
 
 
+@pytest.mark.parametrize("prec", [B.MECH_FP64, B.MECH_FP32, B.MECH_FP32_KAHAN])
+def test_list_kernel_equals_inline_kernel_bitwise(prec):
+    """The list kernel's prefilter and slab window drop no interacting pair and its lists
+    keep the neighbour order: at every list length and tile its trajectories are bitwise
+    those of the inline kernel, which evaluates every pair of the 27 voxels in order."""
+    require_gpu()
+    pops = _sims(3, 3000, 8000, seed=4650)
+    ref, inter_ref = _run(pops, B.tuning("rows", 4, 4, 0), 15, prec)
+    for cfg in [("cells", 4, 4, 0, 16), ("cells", 4, 4, 0, 32), ("cells", 4, 4, 0, 64),
+                ("cells", 1, 8, 0, 64), ("cells", 8, 2, 16, 32), ("cells", 2, 8, 0, 16)]:
+        say("list kernel", prec, cfg)
+        got, inter = _run(pops, B.tuning(*cfg), 15, prec)
+        assert inter == inter_ref
+        for (p0, v0), (p1, v1) in zip(ref, got):
+            assert np.array_equal(p0, p1) and np.array_equal(v0, v1), cfg
+
+
 @pytest.mark.parametrize("cfg", [("cells", 8, 2, 16), ("cells", 1, 8, 0), ("rows", 2, 4, 0),
                                  ("voxel", 4, 4, 2)])
 def test_configuration_is_deterministic(cfg):
@@ -70,7 +87,7 @@ def test_bad_configurations_are_rejected():
     with B.Batch(p, pops[0].n, B.batch_request_voxels(p, pops[0].lo, pops[0].hi), 1) as bt:
         for bad in (B.tuning(6, 4, 4, 0), B.tuning(0, 3, 4, 0), B.tuning(0, 16, 4, 0),
                     B.tuning(0, 4, 16, 0), B.tuning(0, 4, 1, 0), B.tuning(0, 4, 4, 65),
-                    B.tuning(0, 4, 4, -1)):
+                    B.tuning(0, 4, 4, -1), B.tuning(0, 4, 4, 0, 8), B.tuning(0, 4, 4, 0, 48)):
             with pytest.raises(B.MechError) as e:
                 bt.set_tuning(bad)
             assert e.value.code == B.MECH_E_INVALID
