@@ -61,8 +61,10 @@ def measured_traffic(kernel: str, workload: str, precision: str, tuning: dict):
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}_{precision}.txt")
     if not os.path.exists(path):
         return None
-    b, sha, _, tun = RS.read_traffic(path)
-    return b if sha == RS.source_sha256() and tun == tuning_str(tuning) else None
+    for b, sha, _, tun in RS.read_traffic(path):
+        if sha == RS.source_sha256() and tun == tuning_str(tuning):
+            return b
+    return None
 
 
 def measured_counters(kernel: str, workload: str, precision: str, tuning: dict):
@@ -78,10 +80,12 @@ def measured_counters(kernel: str, workload: str, precision: str, tuning: dict):
     path = os.path.join(ROOT, "profiles", f"pmc_{kernel}_{workload}_{precision}.txt")
     if not os.path.exists(path):
         return None
-    text = open(path).read()
-    sha = re.search(r"source_sha256\(csrc/mech.hip code\): (\w+)", text)
-    tun = re.search(r"--tuning (\S+)", text)
-    if not sha or sha.group(1) != RS.source_sha256() or not tun or tun.group(1) != tuning_str(tuning):
+    for text in RS.sections(path):
+        sha = re.search(r"source_sha256\(csrc/mech.hip code\): (\w+)", text)
+        tun = re.search(r"--tuning (\S+)", text)
+        if sha and sha.group(1) == RS.source_sha256() and tun and tun.group(1) == tuning_str(tuning):
+            break
+    else:
         return None
     v = {m.group(1): float(m.group(2)) for m in re.finditer(r"^(\w+): ([0-9.e+-]+)", text, re.M)}
     cus, xcds = 256, 8

@@ -38,7 +38,7 @@ def search_space():
     for w in (1, 2, 4, 8):
         for u in (2, 4, 8):
             for g in (0, 16):
-                for ln in (0, 32):
+                for ln in (0, 32, 64):
                     space.append(B.tuning("cells", w, u, g, ln))
     for w in (2, 4, 8):
         space.append(B.tuning("rows", w, 4, 0))

@@ -10,7 +10,8 @@
 `traffic` scales the per-dispatch FETCH_SIZE and WRITE_SIZE (KiB) of a kernel by what the
 same counters read for a streaming copy of known size, and records the SHA-256 of the
 kernel source's code (comments and blank space removed) so a reader can tell whether the
-figure still describes the current code.
+figure still describes the current code.  A summary file may hold several blocks (one
+per launch configuration), separated by blank lines.
 """
 from __future__ import annotations
 
@@ -155,15 +156,26 @@ def pmc(paths, kernel: str, commands) -> str:
     return "\n".join(lines) + "\n"
 
 
+def sections(path: str):
+    """The blocks of a summary file: one per profiled launch configuration, separated by
+    blank lines."""
+    return [b for b in open(path).read().split("\n\n") if b.strip()]
+
+
 def read_traffic(path: str):
-    """(traffic bytes per launch, source sha256, workload, tuning) from a `traffic`
-    summary."""
-    vals = {}
-    for line in open(path):
-        k, _, v = line.partition(":")
-        vals[k.strip()] = v.strip()
-    return (float(vals["traffic_bytes_per_launch"]), vals["source_sha256(csrc/mech.hip code)"],
-            vals.get("workload", ""), vals.get("tuning", ""))
+    """[(traffic bytes per launch, source sha256, workload, tuning), ...], one per block
+    of a file of `traffic` summaries."""
+    out = []
+    for block in sections(path):
+        vals = {}
+        for line in block.splitlines():
+            k, _, v = line.partition(":")
+            vals[k.strip()] = v.strip()
+        if "traffic_bytes_per_launch" in vals:
+            out.append((float(vals["traffic_bytes_per_launch"]),
+                        vals["source_sha256(csrc/mech.hip code)"], vals.get("workload", ""),
+                        vals.get("tuning", "")))
+    return out
 
 
 def main(argv=None):
