@@ -1171,20 +1171,55 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
             return d2 < s * s;
         }
     };
+    // The candidate data a flush evaluates.  With the longer lists (picked for small
+    // populations, where a few waves per SIMD hide little latency) the next entry's data
+    // is fetched before the current one is evaluated; with 16 entries the extra
+    // registers would cost a wave per SIMD, which matters more.
+    struct Cand {
+        Real x, y, z, r;
+        int t;
+    };
+    auto fetch = [&](uint32_t j) {
+        Cand c;
+        if constexpr (PREC == 0) {
+            c.x = a.XS[0][j];
+            c.y = a.XS[1][j];
+            c.z = a.XS[2][j];
+            c.r = a.R[j];
+        } else {
+            const float4 v = a.SH[j];
+            c.x = v.x;
+            c.y = v.y;
+            c.z = v.z;
+            c.r = v.w;
+        }
+        c.t = MULTI ? a.T[j] : 0;
+        return c;
+    };
+    auto eval = [&](const Cand& c) {
+        if constexpr (PREC == 0) {
+            const double cadh = MULTI ? a.cadh[ti * P.n_types + c.t] : P.c_adh0;
+            inter += pair64(xi, yi, zi, ri, c.x, c.y, c.z, c.r, P.alpha, P.c_rep, cadh, acc[0], acc[1], acc[2]);
+        } else {
+            const float cadh = MULTI ? a.cadh_f[ti * P.n_types + c.t] : P.c_adh0_f;
+            inter += pair32<PREC == 2>(xi, yi, zi, ri, make_float4(c.x, c.y, c.z, c.r), P.alpha_f, P.c_rep_f,
+                                       cadh, acc, cmp);
+        }
+    };
     auto flush = [&]() {
-        for (uint32_t k = 0; k < (uint32_t)LIST; ++k) {
-            if (!__any(k < cnt)) break;
-            if (k < cnt) {
-                const uint32_t j = list0[k * WAVE];
-                if constexpr (PREC == 0) {
-                    const double cadh = MULTI ? a.cadh[ti * P.n_types + a.T[j]] : P.c_adh0;
-                    inter += pair64(xi, yi, zi, ri, a.XS[0][j], a.XS[1][j], a.XS[2][j], a.R[j],
-                                    P.alpha, P.c_rep, cadh, acc[0], acc[1], acc[2]);
-                } else {
-                    const float cadh = MULTI ? a.cadh_f[ti * P.n_types + a.T[j]] : P.c_adh0_f;
-                    inter += pair32<PREC == 2>(xi, yi, zi, ri, a.SH[j], P.alpha_f, P.c_rep_f, cadh,
-                                               acc, cmp);
-                }
+        if constexpr (LIST >= 32) {
+            Cand cn = fetch(cnt > 0 ? list0[0] : ii);
+            for (uint32_t k = 0; k < (uint32_t)LIST; ++k) {
+                if (!__any(k < cnt)) break;
+                const Cand c = cn;
+                // entries at and above cnt are stale: the own cell stands in for them
+                cn = fetch(k + 1 < cnt ? list0[(k + 1) * WAVE] : ii);
+                if (k < cnt) eval(c);
+            }
+        } else {
+            for (uint32_t k = 0; k < (uint32_t)LIST; ++k) {
+                if (!__any(k < cnt)) break;
+                if (k < cnt) eval(fetch(list0[k * WAVE]));
             }
         }
         cnt = 0;
