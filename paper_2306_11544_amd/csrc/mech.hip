@@ -5,7 +5,8 @@
 //                         FP64 key) and an integer-atomic histogram, one atomic per run of
 //                         equal bins in a wave
 //   k_scan_reduce  a3     per-tile sums of (count, occupied voxels) packed in 64 bits
-//   k_scan_top            exclusive scan of the tile sums (one workgroup)
+//   k_scan_top            exclusive scan of the tile sums (one workgroup; on grids of at
+//                         most FUSED_SCAN_TILES tiles k_scan_down adds them up itself)
 //   k_scan_down           bin starts (exclusive prefix), occupied-voxel list, count reset
 //   k_scatter      a4     cells into their bin's segment (arbitrary order inside it)
 //   k_rank_gather  a4+a5  rank inside the bin by ascending id -> final slot; gather of the
@@ -306,8 +307,15 @@ __global__ __launch_bounds__(BLOCK) void k_scan_top(uint64_t* __restrict__ tsum,
     }
 }
 
+// FUSED (grids of at most FUSED_SCAN_TILES tiles): toff holds the raw tile sums and each
+// workgroup adds up those before its tile itself, which saves the k_scan_top launch; the
+// last tile's workgroup writes the totals.  Otherwise toff holds k_scan_top's exclusive
+// prefix of the tile sums.
+constexpr uint32_t FUSED_SCAN_TILES = 2048;
+
+template <bool FUSED>
 __global__ __launch_bounds__(BLOCK) void k_scan_down(uint32_t* __restrict__ count,
-                                                     const uint32_t* __restrict__ hdr,
+                                                     uint32_t* __restrict__ hdr,
                                                      const uint64_t* __restrict__ toff,
                                                      uint32_t* __restrict__ voxel_start,
                                                      uint32_t* __restrict__ occ)
@@ -316,8 +324,20 @@ __global__ __launch_bounds__(BLOCK) void k_scan_down(uint32_t* __restrict__ coun
     __shared__ uint64_t sh[BLOCK / WAVE];
     const uint32_t S = XSUB * hdr[H_VOXELS];
     const uint32_t nt = (S + SCAN_TILE - 1) / SCAN_TILE;
+    if (FUSED && nt == 0 && blockIdx.x == 0 && threadIdx.x == 0) {
+        voxel_start[0] = 0u;
+        hdr[H_OCC] = 0u;
+    }
     for (uint32_t ti = blockIdx.x; ti < nt; ti += gridDim.x) {
         const uint32_t base = ti * SCAN_TILE;
+        uint64_t off0;
+        if constexpr (FUSED) {
+            uint64_t part = 0;
+            for (uint32_t t = threadIdx.x; t < ti; t += BLOCK) part += toff[t];
+            (void)block_excl_scan(part, sh, &off0);
+        } else {
+            off0 = toff[ti];
+        }
 #pragma unroll
         for (int k = 0; k < SCAN_PER_THREAD; ++k) {
             uint32_t v = base + k * BLOCK + threadIdx.x;
@@ -343,7 +363,13 @@ __global__ __launch_bounds__(BLOCK) void k_scan_down(uint32_t* __restrict__ coun
             sum += (uint64_t)mine[k] | ((uint64_t)f << 32);
         }
         uint64_t tot;
-        uint64_t off = toff[ti] + block_excl_scan(sum, sh, &tot);
+        uint64_t off = off0 + block_excl_scan(sum, sh, &tot);
+        if constexpr (FUSED) {
+            if (ti == nt - 1 && threadIdx.x == 0) {
+                voxel_start[S] = (uint32_t)(off0 + tot);
+                hdr[H_OCC] = (uint32_t)((off0 + tot) >> 32);
+            }
+        }
 #pragma unroll
         for (int k = 0; k < SCAN_PER_THREAD; ++k) {
             uint32_t v = base + threadIdx.x * SCAN_PER_THREAD + k;
@@ -1795,10 +1821,17 @@ void enqueue_keys(MechBatch* B)
                        B->at<uint32_t>(L.off));
     hipLaunchKernelGGL(k_scan_reduce, dim3(nbt), dim3(BLOCK), 0, B->stream, B->at<uint32_t>(L.count), hdr,
                        B->at<uint64_t>(L.tsum));
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(BLOCK), 0, B->stream, B->at<uint64_t>(L.tsum),
-                       B->at<uint32_t>(L.start), B->at<uint32_t>(L.hdr));
-    hipLaunchKernelGGL(k_scan_down, dim3(nbt), dim3(BLOCK), 0, B->stream, B->at<uint32_t>(L.count), hdr,
-                       B->at<uint64_t>(L.tsum), B->at<uint32_t>(L.start), B->at<uint32_t>(L.occ));
+    if (blocks_for((uint64_t)B->cap_voxels * XSUB, SCAN_TILE) <= FUSED_SCAN_TILES) {
+        hipLaunchKernelGGL(k_scan_down<true>, dim3(nbt), dim3(BLOCK), 0, B->stream, B->at<uint32_t>(L.count),
+                           B->at<uint32_t>(L.hdr), B->at<uint64_t>(L.tsum), B->at<uint32_t>(L.start),
+                           B->at<uint32_t>(L.occ));
+    } else {
+        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(BLOCK), 0, B->stream, B->at<uint64_t>(L.tsum),
+                           B->at<uint32_t>(L.start), B->at<uint32_t>(L.hdr));
+        hipLaunchKernelGGL(k_scan_down<false>, dim3(nbt), dim3(BLOCK), 0, B->stream, B->at<uint32_t>(L.count),
+                           B->at<uint32_t>(L.hdr), B->at<uint64_t>(L.tsum), B->at<uint32_t>(L.start),
+                           B->at<uint32_t>(L.occ));
+    }
     hipLaunchKernelGGL(k_scatter, dim3(nbc), dim3(BLOCK), 0, B->stream, hdr, B->at<uint32_t>(L.vid_cur),
                        B->at<uint32_t>(L.off), B->at<uint32_t>(L.start), B->at<uint32_t>(L.ID[cur]),
                        B->at<uint32_t>(L.tmp_key), B->at<uint32_t>(L.tmp_src));
