@@ -1782,6 +1782,7 @@ struct MechBatch {
     bool graphs_ready = false;
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     hipGraphExec_t gexec_inplace[2] = {nullptr, nullptr};
+    hipGraphExec_t gexec_run[2] = {nullptr, nullptr};  // RUN_STEPS reordering steps
 
     template <typename T>
     T* at(size_t off) const { return reinterpret_cast<T*>(arena + off); }
@@ -2148,24 +2149,38 @@ int drop_graphs(MechBatch* B)
             (void)hipGraphExecDestroy(B->gexec_inplace[p]);
             B->gexec_inplace[p] = nullptr;
         }
+        if (B->gexec_run[p]) {
+            (void)hipGraphExecDestroy(B->gexec_run[p]);
+            B->gexec_run[p] = nullptr;
+        }
     }
     B->graphs_ready = false;
     return MECH_OK;
 }
 
 // One graph per parity for reordering steps and, when cells may be left in place, one
-// per parity for those steps.
+// per parity for those steps.  When every step reorders, also one per parity for a run
+// of RUN_STEPS steps: small populations are bound by the host's launch rate, and one
+// launch per run instead of per step takes most of it away.
+constexpr int RUN_STEPS = 8;
+static_assert(RUN_STEPS % 2 == 0, "a run ends on the parity it started from");
+
 int build_graphs(MechBatch* B)
 {
-    for (int kind = 0; kind < 2; ++kind) {
-        if (kind == 1 && B->reorder_every == 1) break;
+    for (int kind = 0; kind < 3; ++kind) {
+        if (kind == 1 && B->reorder_every == 1) continue;
+        if (kind == 2 && B->reorder_every != 1) break;
         for (int p = 0; p < 2; ++p) {
             hipGraph_t g = nullptr;
             HIP_TRY(hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal));
-            enqueue_step(B, p, kind == 0);
+            if (kind == 2)
+                for (int i = 0; i < RUN_STEPS; ++i) enqueue_step(B, p ^ (i & 1), true);
+            else
+                enqueue_step(B, p, kind == 0);
             hipError_t e = hipStreamEndCapture(B->stream, &g);
             if (e != hipSuccess) return fail(MECH_E_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
-            e = hipGraphInstantiate(kind == 0 ? &B->gexec[p] : &B->gexec_inplace[p], g, nullptr, nullptr, 0);
+            hipGraphExec_t* dst = kind == 0 ? &B->gexec[p] : kind == 1 ? &B->gexec_inplace[p] : &B->gexec_run[p];
+            e = hipGraphInstantiate(dst, g, nullptr, nullptr, 0);
             (void)hipGraphDestroy(g);
             if (e != hipSuccess) return fail(MECH_E_DEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
         }
@@ -2514,12 +2529,38 @@ int after_step(MechBatch* B, bool gather)
     return MECH_OK;
 }
 
+// A slot whose step counter reaches 0 within the next m steps: its completion event
+// must be recorded after that very step, so such steps are launched one at a time.
+bool slot_ends_within(const MechBatch* B, int m)
+{
+    for (int32_t id : B->order) {
+        const int32_t left = B->slots[id].d.steps_left;
+        if (left >= 1 && left <= m) return true;
+    }
+    return false;
+}
+
 int step_impl(MechBatch* B, int64_t n_steps)
 {
     if (n_steps < 0) return fail(MECH_E_INVALID, "n_steps must be >= 0");
     HIP_TRY(hipSetDevice(B->device));
     const bool eager = (B->prm.flags & MECH_FLAG_NO_GRAPH) != 0;
     for (int64_t k = 0; k < n_steps; ++k) {
+        if (!eager && B->reorder_every == 1 && B->n_cells > 0 && n_steps - k >= RUN_STEPS &&
+            !slot_ends_within(B, RUN_STEPS - 1)) {
+            if (!B->graphs_ready) {
+                int rc = build_graphs(B);
+                if (rc) return rc;
+            }
+            HIP_TRY(hipGraphLaunch(B->gexec_run[B->parity], B->stream));
+            HIP_TRY(hipGetLastError());
+            for (int i = 0; i < RUN_STEPS; ++i) {
+                int rc = after_step(B, true);
+                if (rc) return rc;
+            }
+            k += RUN_STEPS - 1;
+            continue;
+        }
         const bool gather = gather_now(B);
         if (B->n_cells > 0) {
             if (eager) {
