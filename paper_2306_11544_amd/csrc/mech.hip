@@ -1099,7 +1099,7 @@ __global__ __launch_bounds__(WPB * WAVE) void k_force_rows(PhysArgs P, ForceArgs
 
 // ------------------------------------------------------------------------ a6 + a7, list kernel
 
-// LIST: candidates a lane can hold listed before a flush (16, 32 or 64).
+// LIST: candidates a lane can hold listed before a flush (20, 32 or 64).
 // UNROLL: candidates tested per loop trip (independent loads in flight), at most LIST / 2.
 
 // One thread per cell in storage (bin) order.  Each lane walks its 9 neighbour rows,
@@ -1199,7 +1199,7 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
     };
     // The candidate data a flush evaluates.  With the longer lists (picked for small
     // populations, where a few waves per SIMD hide little latency) the next entry's data
-    // is fetched before the current one is evaluated; with 16 entries the extra
+    // is fetched before the current one is evaluated; with the short list the extra
     // registers would cost a wave per SIMD, which matters more.
     struct Cand {
         Real x, y, z, r;
@@ -1907,7 +1907,7 @@ void launch_cells_w(MechBatch* B, const ForceArgs<VPT>& a)
     switch (B->tune.list_len) {
     case 32: launch_cells_l<PREC, MULTI, VPT, WPB, 32>(B, a); break;
     case 64: launch_cells_l<PREC, MULTI, VPT, WPB, 64>(B, a); break;
-    default: launch_cells_l<PREC, MULTI, VPT, WPB, 16>(B, a); break;
+    default: launch_cells_l<PREC, MULTI, VPT, WPB, 20>(B, a); break;
     }
 }
 
@@ -2032,9 +2032,9 @@ void enqueue_force_inplace(MechBatch* B)
     a.perm = B->at<uint32_t>(L.off);
     const dim3 grid(force_cell_grid(B, 4)), block(4 * WAVE);
     if (B->prm.n_types > 1)
-        hipLaunchKernelGGL((k_force_cells<PREC, true, VPT, 4, 4, 16, true>), grid, block, 0, B->stream, B->phys, a);
+        hipLaunchKernelGGL((k_force_cells<PREC, true, VPT, 4, 4, 20, true>), grid, block, 0, B->stream, B->phys, a);
     else
-        hipLaunchKernelGGL((k_force_cells<PREC, false, VPT, 4, 4, 16, true>), grid, block, 0, B->stream, B->phys, a);
+        hipLaunchKernelGGL((k_force_cells<PREC, false, VPT, 4, 4, 20, true>), grid, block, 0, B->stream, B->phys, a);
 }
 
 // a1..a4 without the reorder: keys, scan, scatter, perm (and the float shadow first).
@@ -3174,8 +3174,8 @@ int batch_set_tuning(MechBatch* B, const MechTuning* t)
         return fail(MECH_E_INVALID, "unroll %d not in {2, 4, 8}", t->unroll);
     if (t->blocks_per_cu < 0 || t->blocks_per_cu > 64)
         return fail(MECH_E_INVALID, "blocks_per_cu %d not in [0, 64]", t->blocks_per_cu);
-    if (t->list_len != 0 && t->list_len != 16 && t->list_len != 32 && t->list_len != 64)
-        return fail(MECH_E_INVALID, "list_len %d not in {0, 16, 32, 64}", t->list_len);
+    if (t->list_len != 0 && t->list_len != 20 && t->list_len != 32 && t->list_len != 64)
+        return fail(MECH_E_INVALID, "list_len %d not in {0, 20, 32, 64}", t->list_len);
     HIP_TRY(hipSetDevice(B->device));
     HIP_TRY(hipStreamSynchronize(B->stream));
     drop_graphs(B);
