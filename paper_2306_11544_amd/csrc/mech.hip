@@ -1136,7 +1136,8 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
     // |x_j - x_i| < alpha (r_i + r_max).  The window is taken in FP64 from the exact
     // position and widened by a margin that covers the float rounding of the FP32
     // decision (a few ulp of |x|) and of R_A, so it never drops a pair either
-    // precision counts.  s0, s1: slot-local slab indices, inside the row's voxels.
+    // precision counts.  w0, w1: the window's first and one-past-last slab, counted from
+    // the first slab of the row's voxels and clipped to them.
     uint32_t w0, w1;
     {
         const double xg = a.XS[0][ii];
