@@ -104,8 +104,8 @@ typedef struct MechTuning {
                                    (at most 32768 wave64s) for the per-cell kernels and
                                    4 per compute unit for the voxel kernel              */
     int32_t list_len;           /* in-range candidates a lane of the list kernel holds
-                                   before the wave evaluates them: 20, 32, 64, or 0
-                                   (default: 20)                                        */
+                                   before the wave evaluates them: 16, 32, 64, or 0
+                                   (default: 16)                                        */
 } MechTuning;
 
 typedef struct MechPopulation MechPopulation;

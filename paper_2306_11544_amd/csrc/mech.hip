@@ -1099,7 +1099,7 @@ __global__ __launch_bounds__(WPB * WAVE) void k_force_rows(PhysArgs P, ForceArgs
 
 // ------------------------------------------------------------------------ a6 + a7, list kernel
 
-// LIST: candidates a lane can hold listed before a flush (20, 32 or 64).
+// LIST: candidates a lane can hold listed before a flush (16, 32 or 64).
 // UNROLL: candidates tested per loop trip (independent loads in flight), at most LIST / 2.
 
 // One thread per cell in storage (bin) order.  Each lane walks its 9 neighbour rows,
@@ -1176,15 +1176,28 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
     }
     const int ti = MULTI ? a.T[ii] : 0;
     Real acc[3] = {0, 0, 0}, cmp[3] = {0, 0, 0};
-    // list0[k * WAVE], k < cnt: the listed candidates.  Every tested candidate is written
-    // at index cnt and counted only when it passed (no branch); cnt <= LIST - FC_UNROLL
-    // when a trip starts, so the writes stay below LIST.
-    uint32_t cnt = 0;
+    // The short list (LIST = 16, picked for dense populations) is a ring,
+    // list0[(k mod LIST) * WAVE]: the listed candidates run from head up to tail
+    // (excluded), oldest first, and a flush inside the walk evaluates only the oldest
+    // entries (below).  The long lists (32, 64: small populations, few waves per SIMD)
+    // are plain arrays from list0, emptied whole.  Every tested candidate is written at
+    // tail, which advances only when it passed (no branch).  A trip starts with fewer
+    // than LIST - FC_UNROLL entries, so a list never holds more than LIST - 1 and, in the
+    // ring, (tail - head) mod LIST is its exact length.
+    constexpr bool RING = LIST < 32;
+    constexpr uint32_t MASK = RING ? (uint32_t)LIST - 1u : 0xffffffffu;
+    static_assert(!RING || (LIST & (LIST - 1)) == 0, "the ring length is a power of two");
+    // entries a lane may keep after a flush inside the walk
+    constexpr uint32_t KEEP =
+        RING ? std::min<uint32_t>((uint32_t)LIST * 5u / 8u, (uint32_t)(LIST - FC_UNROLL) - 1u) : 0u;
+    static_assert(KEEP < (uint32_t)(LIST - FC_UNROLL), "a flush makes room for the next trip");
+    uint32_t head = 0, tail = 0;
     auto push = [&](uint32_t j, bool in) {
-        list0[cnt * WAVE] = j;
-        cnt += in ? 1u : 0u;
+        list0[tail * WAVE] = j;
+        tail = (tail + (in ? 1u : 0u)) & MASK;
     };
-    auto full = [&]() { return __any(cnt > (uint32_t)(LIST - FC_UNROLL)); };
+    auto count = [&]() { return (tail - head) & MASK; };
+    auto full = [&]() { return __any(count() >= (uint32_t)(LIST - FC_UNROLL)); };
 
     // cw: the candidate's radius (FP32 only)
     auto near = [&](Real cx, Real cy, Real cz, float cw) -> bool {
@@ -1198,10 +1211,10 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
             return d2 < s * s;
         }
     };
-    // The candidate data a flush evaluates.  With the longer lists (picked for small
-    // populations, where a few waves per SIMD hide little latency) the next entry's data
-    // is fetched before the current one is evaluated; with the short list the extra
-    // registers would cost a wave per SIMD, which matters more.
+    // The candidate data a flush evaluates.  With the long lists (few waves per SIMD
+    // hide little latency) the next entry's data is fetched before the current one is
+    // evaluated; with the short list the extra registers would cost a wave per SIMD,
+    // which matters more.
     struct Cand {
         Real x, y, z, r;
         int t;
@@ -1233,23 +1246,33 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
                                        cadh, acc, cmp);
         }
     };
-    auto flush = [&]() {
-        if constexpr (LIST >= 32) {
-            Cand cn = fetch(cnt > 0 ? list0[0] : ii);
+    // The ring evaluates in every lane its oldest entries, as many as bring the fullest
+    // list down to `keep` (all of them when keep is 0).  Each pass then keeps every lane
+    // that still holds that many entries busy, where emptying whole lists would leave the
+    // lanes with short lists idle for most of the passes.  A long list is emptied whole,
+    // the next entry's data fetched before the current one is evaluated.
+    auto flush = [&](uint32_t keep) {
+        const uint32_t c = count();
+        if constexpr (!RING) {
+            Cand cn = fetch(c > 0 ? list0[0] : ii);
+#pragma unroll 1
             for (uint32_t k = 0; k < (uint32_t)LIST; ++k) {
-                if (!__any(k < cnt)) break;
-                const Cand c = cn;
-                // entries at and above cnt are stale: the own cell stands in for them
-                cn = fetch(k + 1 < cnt ? list0[(k + 1) * WAVE] : ii);
-                if (k < cnt) eval(c);
+                if (!__any(k < c)) break;
+                const Cand cur = cn;
+                // entries at and above c are stale: the own cell stands in for them
+                cn = fetch(k + 1 < c ? list0[(k + 1) * WAVE] : ii);
+                if (k < c) eval(cur);
             }
+            tail = 0;
         } else {
-            for (uint32_t k = 0; k < (uint32_t)LIST; ++k) {
-                if (!__any(k < cnt)) break;
-                if (k < cnt) eval(fetch(list0[k * WAVE]));
+            uint32_t k = 0;
+#pragma unroll 1
+            for (; k < (uint32_t)LIST; ++k) {
+                if (!__any(k + keep < c)) break;
+                if (k < c) eval(fetch(list0[((head + k) & MASK) * WAVE]));
             }
+            head = (head + min(c, k)) & MASK;
         }
-        cnt = 0;
     };
 
     for (int q = 0; q < 9; ++q) {
@@ -1268,7 +1291,7 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
                     const float4 c = a.SH[jj];
                     push(jj, near(c.x, c.y, c.z, c.w));
                 }
-                if (full()) flush();
+                if (full()) flush(KEEP);
             }
             continue;
         }
@@ -1286,11 +1309,11 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
                 }
 #pragma unroll
                 for (int u = 0; u < FC_UNROLL; ++u) push(j + u, near(cx[u], cy[u], cz[u], 0.0f));
-                if (full()) flush();
+                if (full()) flush(KEEP);
             }
             for (; j < e; ++j, ++px, ++py, ++pz) {
                 push(j, near(*px, *py, *pz, 0.0f));
-                if (full()) flush();
+                if (full()) flush(KEEP);
             }
         } else {
             const float4* sp = a.SH + j;
@@ -1300,16 +1323,16 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
                 for (int u = 0; u < FC_UNROLL; ++u) c[u] = sp[u];
 #pragma unroll
                 for (int u = 0; u < FC_UNROLL; ++u) push(j + u, near(c[u].x, c[u].y, c[u].z, c[u].w));
-                if (full()) flush();
+                if (full()) flush(KEEP);
             }
             for (; j < e; ++j, ++sp) {
                 const float4 c = *sp;
                 push(j, near(c.x, c.y, c.z, c.w));
-                if (full()) flush();
+                if (full()) flush(KEEP);
             }
         }
     }
-    flush();
+    flush(0);
     if (valid) {
         cand -= 1;  // the cell itself
         double v[3];
@@ -1908,7 +1931,7 @@ void launch_cells_w(MechBatch* B, const ForceArgs<VPT>& a)
     switch (B->tune.list_len) {
     case 32: launch_cells_l<PREC, MULTI, VPT, WPB, 32>(B, a); break;
     case 64: launch_cells_l<PREC, MULTI, VPT, WPB, 64>(B, a); break;
-    default: launch_cells_l<PREC, MULTI, VPT, WPB, 20>(B, a); break;
+    default: launch_cells_l<PREC, MULTI, VPT, WPB, 16>(B, a); break;
     }
 }
 
@@ -2033,9 +2056,9 @@ void enqueue_force_inplace(MechBatch* B)
     a.perm = B->at<uint32_t>(L.off);
     const dim3 grid(force_cell_grid(B, 4)), block(4 * WAVE);
     if (B->prm.n_types > 1)
-        hipLaunchKernelGGL((k_force_cells<PREC, true, VPT, 4, 4, 20, true>), grid, block, 0, B->stream, B->phys, a);
+        hipLaunchKernelGGL((k_force_cells<PREC, true, VPT, 4, 4, 16, true>), grid, block, 0, B->stream, B->phys, a);
     else
-        hipLaunchKernelGGL((k_force_cells<PREC, false, VPT, 4, 4, 20, true>), grid, block, 0, B->stream, B->phys, a);
+        hipLaunchKernelGGL((k_force_cells<PREC, false, VPT, 4, 4, 16, true>), grid, block, 0, B->stream, B->phys, a);
 }
 
 // a1..a4 without the reorder: keys, scan, scatter, perm (and the float shadow first).
@@ -3175,8 +3198,8 @@ int batch_set_tuning(MechBatch* B, const MechTuning* t)
         return fail(MECH_E_INVALID, "unroll %d not in {2, 4, 8}", t->unroll);
     if (t->blocks_per_cu < 0 || t->blocks_per_cu > 64)
         return fail(MECH_E_INVALID, "blocks_per_cu %d not in [0, 64]", t->blocks_per_cu);
-    if (t->list_len != 0 && t->list_len != 20 && t->list_len != 32 && t->list_len != 64)
-        return fail(MECH_E_INVALID, "list_len %d not in {0, 20, 32, 64}", t->list_len);
+    if (t->list_len != 0 && t->list_len != 16 && t->list_len != 32 && t->list_len != 64)
+        return fail(MECH_E_INVALID, "list_len %d not in {0, 16, 32, 64}", t->list_len);
     HIP_TRY(hipSetDevice(B->device));
     HIP_TRY(hipStreamSynchronize(B->stream));
     drop_graphs(B);

@@ -57,7 +57,7 @@ def test_tuning_search_space_is_valid():
         assert t.force_kernel in (0, B.MECH_FLAG_SIMPLE_FORCE, B.MECH_FLAG_VOXEL_FORCE)
         assert t.block_waves in (1, 2, 4, 8) and t.unroll in (2, 4, 8)
         assert 0 <= t.blocks_per_cu <= 64
-        assert t.list_len in (0, 20, 32, 64) and 2 * t.unroll <= (t.list_len or 20)
+        assert t.list_len in (0, 16, 32, 64) and 2 * t.unroll <= (t.list_len or 16)
 
 
 def test_tuning_calls_reject_null_handles():
