@@ -174,7 +174,9 @@ __device__ __forceinline__ uint64_t wave_incl_scan(uint64_t x)
     return x;
 }
 
-// Exclusive scan over the workgroup; *total receives the workgroup sum.
+// Exclusive scan over a workgroup of NT threads (sh: NT / WAVE words); *total receives
+// the workgroup sum.
+template <int NT = BLOCK>
 __device__ __forceinline__ uint64_t block_excl_scan(uint64_t x, uint64_t* sh, uint64_t* total)
 {
     uint64_t inc = wave_incl_scan(x);
@@ -183,7 +185,7 @@ __device__ __forceinline__ uint64_t block_excl_scan(uint64_t x, uint64_t* sh, ui
     __syncthreads();
     uint64_t off = 0, tot = 0;
 #pragma unroll
-    for (int i = 0; i < BLOCK / WAVE; ++i) {
+    for (int i = 0; i < NT / WAVE; ++i) {
         if (i < w) off += sh[i];
         tot += sh[i];
     }
@@ -464,11 +466,12 @@ __global__ __launch_bounds__(BLOCK) void k_rank_gather(const uint32_t* __restric
 // path: the same order and outputs, bitwise.
 constexpr uint32_t SMALL_CELLS = 8192;
 constexpr uint32_t SMALL_BINS = 8192;
-constexpr uint32_t SMALL_PER_THREAD = SMALL_CELLS / BLOCK;
-static_assert(SMALL_BINS / BLOCK == SMALL_PER_THREAD && SMALL_PER_THREAD % XSUB == 0, "scan layout");
+constexpr int SMALL_BLOCK = 1024;          // 16 waves: more loads in flight per phase
+constexpr uint32_t SMALL_PER_THREAD = SMALL_CELLS / SMALL_BLOCK;
+static_assert(SMALL_BINS / SMALL_BLOCK == SMALL_PER_THREAD && SMALL_PER_THREAD % XSUB == 0, "scan layout");
 
 template <typename VPT>
-__global__ __launch_bounds__(BLOCK) void k_bin_small(const uint32_t* __restrict__ slot_of,
+__global__ __launch_bounds__(SMALL_BLOCK) void k_bin_small(const uint32_t* __restrict__ slot_of,
                                                      const SlotDesc* __restrict__ slots,
                                                      uint32_t* __restrict__ hdr,
                                                      const uint32_t* __restrict__ id_cur,
@@ -480,17 +483,17 @@ __global__ __launch_bounds__(BLOCK) void k_bin_small(const uint32_t* __restrict_
     __shared__ uint32_t s_key[SMALL_CELLS];
     __shared__ uint32_t s_src[SMALL_CELLS];
     __shared__ uint32_t s_vid[SMALL_CELLS];
-    __shared__ uint64_t sh[BLOCK / WAVE];
+    __shared__ uint64_t sh[SMALL_BLOCK / WAVE];
     const uint32_t n = hdr[H_CELLS];
     const uint32_t S = XSUB * hdr[H_VOXELS];
     const uint32_t t = threadIdx.x;
-    for (uint32_t b = t; b <= SMALL_BINS; b += BLOCK) s_start[b] = 0u;
+    for (uint32_t b = t; b <= SMALL_BINS; b += SMALL_BLOCK) s_start[b] = 0u;
     __syncthreads();
     // a1 + a2
     uint32_t off[SMALL_PER_THREAD];
 #pragma unroll
     for (uint32_t k = 0; k < SMALL_PER_THREAD; ++k) {
-        const uint32_t s = t + k * BLOCK;
+        const uint32_t s = t + k * SMALL_BLOCK;
         off[k] = 0;
         if (s < n) {
             const SlotDesc& d = slots[slot_of[s]];
@@ -523,7 +526,7 @@ __global__ __launch_bounds__(BLOCK) void k_bin_small(const uint32_t* __restrict_
         sum += (uint64_t)cnt[k] | ((uint64_t)f << 32);
     }
     uint64_t tot;
-    const uint64_t base = block_excl_scan(sum, sh, &tot);   // synchronises the workgroup
+    const uint64_t base = block_excl_scan<SMALL_BLOCK>(sum, sh, &tot);   // synchronises the workgroup
 #pragma unroll
     for (uint32_t k = 0; k < SMALL_PER_THREAD; ++k) {
         const uint32_t b = b0 + k;
@@ -543,7 +546,7 @@ __global__ __launch_bounds__(BLOCK) void k_bin_small(const uint32_t* __restrict_
     // a4: scatter into the bins, then rank by id
 #pragma unroll
     for (uint32_t k = 0; k < SMALL_PER_THREAD; ++k) {
-        const uint32_t s = t + k * BLOCK;
+        const uint32_t s = t + k * SMALL_BLOCK;
         if (s < n) {
             const uint32_t p = s_start[s_vid[s]] + off[k];
             s_key[p] = id_cur[s];
@@ -552,7 +555,7 @@ __global__ __launch_bounds__(BLOCK) void k_bin_small(const uint32_t* __restrict_
     }
     __syncthreads();
     // a4 + a5: final slot and gather
-    for (uint32_t p = t; p < n; p += BLOCK) {
+    for (uint32_t p = t; p < n; p += SMALL_BLOCK) {
         const uint32_t s = s_src[p], key = s_key[p], v = s_vid[s];
         const uint32_t b = s_start[v], e = s_start[v + 1];
         uint32_t rank = 0;
@@ -1896,7 +1899,7 @@ void enqueue_binning(MechBatch* B)
     g.voxel_start = B->at<uint32_t>(L.start);
     g.vid_sorted = B->at<uint32_t>(L.vid_sorted);
     if (small_binning(B))
-        hipLaunchKernelGGL(k_bin_small<VPT>, dim3(1), dim3(BLOCK), 0, B->stream, B->at<uint32_t>(L.slot_of),
+        hipLaunchKernelGGL(k_bin_small<VPT>, dim3(1), dim3(SMALL_BLOCK), 0, B->stream, B->at<uint32_t>(L.slot_of),
                            B->at<SlotDesc>(L.slots), B->at<uint32_t>(L.hdr), B->at<uint32_t>(L.ID[cur]),
                            B->at<uint32_t>(L.vid_cur), B->at<uint32_t>(L.start), B->at<uint32_t>(L.occ), g);
     else
