@@ -43,9 +43,10 @@ PEAK_FP64_VECTOR_TFLOPS = 78.6
 FLOP_PER_CANDIDATE = 11
 FLOP_PER_INTERACTION = {"fp64": 18, "fp32": 18, "fp32k": 27}
 # algorithmic HBM bytes per cell of the force kernel: own f64 position (24) + own and
-# neighbour float shadow read once each (16 + 16) or f64 position + radius (32) +
-# v_prev in/out + voxel id (4) + new f64 position (24)
-FORCE_BYTES_PER_CELL = {"fp64": 24 + 32 + 4 + 48 + 24, "fp32": 24 + 32 + 4 + 24 + 24,
+# neighbour float shadow read once each (16 + 16; the prefilter in every precision) +
+# in FP64 the neighbour's f64 position and radius once (32) + v_prev in/out + voxel id
+# (4) + new f64 position (24)
+FORCE_BYTES_PER_CELL = {"fp64": 24 + 32 + 32 + 4 + 48 + 24, "fp32": 24 + 32 + 4 + 24 + 24,
                         "fp32k": 24 + 32 + 4 + 24 + 24}
 
 

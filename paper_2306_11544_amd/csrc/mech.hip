@@ -1108,15 +1108,19 @@ __global__ __launch_bounds__(WPB * WAVE) void k_force_rows(PhysArgs P, ForceArgs
 // One thread per cell in storage (bin) order.  Each lane walks its 9 neighbour rows,
 // reading in each only the x slabs within reach of its cell (a contiguous run: slabs of
 // x-adjacent voxels follow each other), and only prefilters the candidates, FC_UNROLL
-// loads in flight per trip.  A candidate is listed in LDS when
-//   FP64:  d2 < (alpha (r_i + r_max))^2
-//   FP32:  d2 < fl(s * s),  s = fma(a', r_j, fl(a' r_i)),  a' = fl(alpha (1 + 2^-18)),
-// which every interacting pair satisfies: d2 is the same expression as in the exact
-// test; in FP64 r_j <= r_max and rounding is monotonic; in FP32 the exact bound
-// fl(fl(alpha fl(r_i + r_j))^2) is at most alpha^2 (r_i + r_j)^2 (1 + 2^-24)^5, while
-// fl(s * s) is at least alpha^2 (r_i + r_j)^2 (1 + 2^-18)^2 (1 - 2^-24)^7, which is
-// larger.  The FP32 form uses r_j (the w of the float4 already loaded), so it lists
-// little beyond the interacting pairs.  When a list fills, and at the end,
+// loads in flight per trip.  The prefilter runs on the float shadow (x, y, z, r) in
+// every precision: a candidate is listed in LDS when
+//   d2 < fl(s * s),  s = fma(a', r_j, fl(a' r_i) [+ E]),  a' = fl(alpha (1 + 2^-18)),
+// d2 the same float expression as in pair32, which every interacting pair satisfies.
+// FP32: the exact bound fl(fl(alpha fl(r_i + r_j))^2) is at most
+// alpha^2 (r_i + r_j)^2 (1 + 2^-24)^5, while fl(s * s) is at least
+// alpha^2 (r_i + r_j)^2 (1 + 2^-18)^2 (1 - 2^-24)^7, which is larger.  FP64: the exact
+// decision is on the double positions; rounding each coordinate (at most P in size, P
+// the largest |lo| or |hi| of the slot's domain) to float moves the float distance by at
+// most 2 sqrt(3) 2^-24 P and the float arithmetic by a few 2^-24 relative, which the
+// pad E = 2^-21 P and the 2^-18 margin cover.  Using r_j (the w of the float4 already
+// loaded) the prefilter lists little beyond the interacting pairs, and one float4 load
+// per candidate replaces three double loads in FP64.  When a list fills, and at the end,
 // the lanes evaluate their listed candidates together with the exact decision and
 // pair term of pair64 / pair32, in candidate order, so each sum is still taken in the
 // fixed neighbour order and the rare interacting pairs do not make the wave diverge.
@@ -1165,16 +1169,18 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
         zi = m.z;
         ri = m.w;
     }
-    Real T;      // FP64: the prefilter bound
-    float al, ai;  // FP32: a' and fl(a' r_i)
+    // the prefilter works on the float shadow in every precision: a' and fl(a' r_i),
+    // plus in FP64 the pad E for the rounding of the positions to float
+    const float4 mf = a.SH[ii];
+    float al, ai;
     {
 #pragma clang fp contract(off)
+        al = P.alpha_f * (1.0f + 0x1p-18f);
+        ai = al * mf.w;
         if constexpr (PREC == 0) {
-            const double reach = P.alpha * (ri + d.r_max);
-            T = reach * reach;
-        } else {
-            al = P.alpha_f * (1.0f + 0x1p-18f);
-            ai = al * ri;
+            const double pmax = fmax(fmax(fmax(fabs(d.lo[0]), fabs(d.hi[0])), fmax(fabs(d.lo[1]), fabs(d.hi[1]))),
+                                     fmax(fabs(d.lo[2]), fabs(d.hi[2])));
+            ai = ai + (float)(pmax * 0x1p-21);
         }
     }
     const int ti = MULTI ? a.T[ii] : 0;
@@ -1202,17 +1208,13 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
     auto count = [&]() { return (tail - head) & MASK; };
     auto full = [&]() { return __any(count() >= (uint32_t)(LIST - FC_UNROLL)); };
 
-    // cw: the candidate's radius (FP32 only)
-    auto near = [&](Real cx, Real cy, Real cz, float cw) -> bool {
+    // the prefilter on a candidate's float shadow (x, y, z, r)
+    auto near = [&](float cx, float cy, float cz, float cw) -> bool {
 #pragma clang fp contract(off)
-        const Real dx = xi - cx, dy = yi - cy, dz = zi - cz;
-        if constexpr (PREC == 0) {
-            return dx * dx + dy * dy + dz * dz < T;
-        } else {
-            const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
-            const float s = __builtin_fmaf(al, cw, ai);
-            return d2 < s * s;
-        }
+        const float dx = mf.x - cx, dy = mf.y - cy, dz = mf.z - cz;
+        const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
+        const float s = __builtin_fmaf(al, cw, ai);
+        return d2 < s * s;
     };
     // The candidate data a flush evaluates.  With the long lists (few waves per SIMD
     // hide little latency) the next entry's data is fetched before the current one is
@@ -1288,51 +1290,25 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
             // gathers through the sorted order: no locality between consecutive lanes
             for (; j < e; ++j) {
                 const uint32_t jj = a.perm[j];
-                if constexpr (PREC == 0) {
-                    push(jj, near(a.XS[0][jj], a.XS[1][jj], a.XS[2][jj], 0.0f));
-                } else {
-                    const float4 c = a.SH[jj];
-                    push(jj, near(c.x, c.y, c.z, c.w));
-                }
+                const float4 c = a.SH[jj];
+                push(jj, near(c.x, c.y, c.z, c.w));
                 if (full()) flush(KEEP);
             }
             continue;
         }
-        if constexpr (PREC == 0) {
-            const double* px = a.XS[0] + j;
-            const double* py = a.XS[1] + j;
-            const double* pz = a.XS[2] + j;
-            for (; j + FC_UNROLL <= e; j += FC_UNROLL, px += FC_UNROLL, py += FC_UNROLL, pz += FC_UNROLL) {
-                double cx[FC_UNROLL], cy[FC_UNROLL], cz[FC_UNROLL];
+        const float4* sp = a.SH + j;
+        for (; j + FC_UNROLL <= e; j += FC_UNROLL, sp += FC_UNROLL) {
+            float4 c[FC_UNROLL];
 #pragma unroll
-                for (int u = 0; u < FC_UNROLL; ++u) {
-                    cx[u] = px[u];
-                    cy[u] = py[u];
-                    cz[u] = pz[u];
-                }
+            for (int u = 0; u < FC_UNROLL; ++u) c[u] = sp[u];
 #pragma unroll
-                for (int u = 0; u < FC_UNROLL; ++u) push(j + u, near(cx[u], cy[u], cz[u], 0.0f));
-                if (full()) flush(KEEP);
-            }
-            for (; j < e; ++j, ++px, ++py, ++pz) {
-                push(j, near(*px, *py, *pz, 0.0f));
-                if (full()) flush(KEEP);
-            }
-        } else {
-            const float4* sp = a.SH + j;
-            for (; j + FC_UNROLL <= e; j += FC_UNROLL, sp += FC_UNROLL) {
-                float4 c[FC_UNROLL];
-#pragma unroll
-                for (int u = 0; u < FC_UNROLL; ++u) c[u] = sp[u];
-#pragma unroll
-                for (int u = 0; u < FC_UNROLL; ++u) push(j + u, near(c[u].x, c[u].y, c[u].z, c[u].w));
-                if (full()) flush(KEEP);
-            }
-            for (; j < e; ++j, ++sp) {
-                const float4 c = *sp;
-                push(j, near(c.x, c.y, c.z, c.w));
-                if (full()) flush(KEEP);
-            }
+            for (int u = 0; u < FC_UNROLL; ++u) push(j + u, near(c[u].x, c[u].y, c[u].z, c[u].w));
+            if (full()) flush(KEEP);
+        }
+        for (; j < e; ++j, ++sp) {
+            const float4 c = *sp;
+            push(j, near(c.x, c.y, c.z, c.w));
+            if (full()) flush(KEEP);
         }
     }
     flush(0);
@@ -1665,7 +1641,7 @@ Layout make_layout(const MechParams& p, int64_t ncap, uint64_t vcap, int32_t sca
         L.ID[k] = take(nn * 4);
         for (int c = 0; c < 3; ++c) L.VP[k][c] = take(nn * vpb);
     }
-    L.SH = is_fp32(p) ? take(nn * 16) : 0;
+    L.SH = take(nn * 16);
     L.slot_of = take(nn * 4);
     L.vid_cur = take(nn * 4);
     L.off = take(nn * 4);
@@ -1892,7 +1868,7 @@ void enqueue_binning(MechBatch* B)
     g.T_cur = B->at<int32_t>(L.T[cur]);
     g.T_new = B->at<int32_t>(L.T[nxt]);
     g.ID_new = B->at<uint32_t>(L.ID[nxt]);
-    g.SH = is_fp32(B->prm) ? B->at<float4>(L.SH) : nullptr;
+    g.SH = B->at<float4>(L.SH);
     g.vid_cur = B->at<uint32_t>(L.vid_cur);
     g.tmp_key = B->at<uint32_t>(L.tmp_key);
     g.tmp_src = B->at<uint32_t>(L.tmp_src);
@@ -1980,7 +1956,7 @@ void enqueue_force(MechBatch* B, int parity_after_sort)
     }
     a.R = B->at<double>(L.R[p]);
     a.T = B->at<int32_t>(L.T[p]);
-    a.SH = is_fp32(B->prm) ? B->at<float4>(L.SH) : nullptr;
+    a.SH = B->at<float4>(L.SH);
     a.vid_sorted = B->at<uint32_t>(L.vid_sorted);
     a.voxel_start = B->at<uint32_t>(L.start);
     a.slot_of = B->at<uint32_t>(L.slot_of);
@@ -2047,7 +2023,7 @@ void enqueue_force_inplace(MechBatch* B)
     }
     a.R = B->at<double>(L.R[cur]);
     a.T = B->at<int32_t>(L.T[cur]);
-    a.SH = is_fp32(B->prm) ? B->at<float4>(L.SH) : nullptr;
+    a.SH = B->at<float4>(L.SH);
     a.vid_sorted = B->at<uint32_t>(L.vid_cur);
     a.voxel_start = B->at<uint32_t>(L.start);
     a.slot_of = B->at<uint32_t>(L.slot_of);
@@ -2071,10 +2047,9 @@ void enqueue_binning_inplace(MechBatch* B)
     const int cur = B->parity;
     const uint32_t nbc = cell_grid(B);
     const uint32_t* hdr = B->at<uint32_t>(L.hdr);
-    if (is_fp32(B->prm))
-        hipLaunchKernelGGL(k_shadow, dim3(nbc), dim3(BLOCK), 0, B->stream, hdr, B->at<double>(L.X[0]),
-                           B->at<double>(L.X[1]), B->at<double>(L.X[2]), B->at<double>(L.R[cur]),
-                           B->at<float4>(L.SH));
+    hipLaunchKernelGGL(k_shadow, dim3(nbc), dim3(BLOCK), 0, B->stream, hdr, B->at<double>(L.X[0]),
+                       B->at<double>(L.X[1]), B->at<double>(L.X[2]), B->at<double>(L.R[cur]),
+                       B->at<float4>(L.SH));
     enqueue_keys(B);
     hipLaunchKernelGGL(k_rank_perm, dim3(nbc), dim3(BLOCK), 0, B->stream, hdr, B->at<uint32_t>(L.vid_cur),
                        B->at<uint32_t>(L.tmp_key), B->at<uint32_t>(L.tmp_src), B->at<uint32_t>(L.start),
