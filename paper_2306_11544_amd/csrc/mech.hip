@@ -287,21 +287,53 @@ __global__ __launch_bounds__(BLOCK) void k_scan_reduce(const uint32_t* __restric
     }
 }
 
-__global__ __launch_bounds__(BLOCK) void k_scan_top(uint64_t* __restrict__ tsum,
-                                                    uint32_t* __restrict__ voxel_start,
-                                                    uint32_t* __restrict__ hdr)
+// One workgroup of TOP_BLOCK threads, in passes of TOP_CHUNK tile sums: a pass stages its
+// sums in LDS with coalesced loads, each thread adds up a run of consecutive ones, and
+// one workgroup scan per pass gives the prefixes, stored back coalesced.
+constexpr int TOP_BLOCK = 1024;
+constexpr uint32_t TOP_CHUNK = 8192;       // 64 KiB of LDS
+constexpr uint32_t TOP_PER_THREAD = TOP_CHUNK / TOP_BLOCK;
+
+__global__ __launch_bounds__(TOP_BLOCK) void k_scan_top(uint64_t* __restrict__ tsum,
+                                                        uint32_t* __restrict__ voxel_start,
+                                                        uint32_t* __restrict__ hdr)
 {
-    __shared__ uint64_t sh[BLOCK / WAVE];
+    __shared__ uint64_t s_t[TOP_CHUNK];
+    __shared__ uint64_t sh[TOP_BLOCK / WAVE];
     const uint32_t S = XSUB * hdr[H_VOXELS];
     const uint32_t nt = (S + SCAN_TILE - 1) / SCAN_TILE;
+    const uint32_t b0 = threadIdx.x * TOP_PER_THREAD;
     uint64_t carry = 0;
-    for (uint32_t base = 0; base < nt; base += BLOCK) {
-        uint32_t i = base + threadIdx.x;
-        uint64_t x = i < nt ? tsum[i] : 0;
+    for (uint32_t base = 0; base < nt; base += TOP_CHUNK) {
+        const uint32_t m = min(TOP_CHUNK, nt - base);
+#pragma unroll
+        for (uint32_t k = 0; k < TOP_PER_THREAD; ++k) {
+            const uint32_t i = threadIdx.x + k * TOP_BLOCK;
+            if (i < m) s_t[i] = tsum[base + i];
+        }
+        __syncthreads();
+        uint64_t sum = 0;
+#pragma unroll
+        for (uint32_t k = 0; k < TOP_PER_THREAD; ++k)
+            if (b0 + k < m) sum += s_t[b0 + k];
         uint64_t tot;
-        uint64_t ex = block_excl_scan(x, sh, &tot);
-        if (i < nt) tsum[i] = carry + ex;
+        uint64_t off = carry + block_excl_scan<TOP_BLOCK>(sum, sh, &tot);
+#pragma unroll
+        for (uint32_t k = 0; k < TOP_PER_THREAD; ++k) {
+            if (b0 + k < m) {
+                const uint64_t v = s_t[b0 + k];
+                s_t[b0 + k] = off;
+                off += v;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (uint32_t k = 0; k < TOP_PER_THREAD; ++k) {
+            const uint32_t i = threadIdx.x + k * TOP_BLOCK;
+            if (i < m) tsum[base + i] = s_t[i];
+        }
         carry += tot;
+        __syncthreads();
     }
     if (threadIdx.x == 0) {
         voxel_start[S] = (uint32_t)carry;
@@ -1830,7 +1862,7 @@ void enqueue_keys(MechBatch* B)
                            B->at<uint32_t>(L.hdr), B->at<uint64_t>(L.tsum), B->at<uint32_t>(L.start),
                            B->at<uint32_t>(L.occ));
     } else {
-        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(BLOCK), 0, B->stream, B->at<uint64_t>(L.tsum),
+        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(TOP_BLOCK), 0, B->stream, B->at<uint64_t>(L.tsum),
                            B->at<uint32_t>(L.start), B->at<uint32_t>(L.hdr));
         hipLaunchKernelGGL(k_scan_down<false>, dim3(nbt), dim3(BLOCK), 0, B->stream, B->at<uint32_t>(L.count),
                            B->at<uint32_t>(L.hdr), B->at<uint64_t>(L.tsum), B->at<uint32_t>(L.start),
