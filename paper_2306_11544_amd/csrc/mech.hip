@@ -413,11 +413,12 @@ __global__ __launch_bounds__(BLOCK) void k_scan_down(uint32_t* __restrict__ coun
                 if (first_occ[k]) occ[(uint32_t)(e >> 32)] = v / XSUB;
             }
         }
-        // the histogram of the next step starts from zero
+        // the histogram of the next step starts from zero (empty bins already are: most
+        // of a sparse grid's bins are not written at all)
 #pragma unroll
         for (int k = 0; k < SCAN_PER_THREAD; ++k) {
             uint32_t v = base + k * BLOCK + threadIdx.x;
-            if (v < S) count[v] = 0u;
+            if (v < S && tile[k * BLOCK + threadIdx.x] != 0u) count[v] = 0u;
         }
         __syncthreads();
     }
