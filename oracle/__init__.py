@@ -21,6 +21,10 @@ Parity status of each function (what pins it is listed in tests/test_oracle_*.py
   uniform / divide / pinned: uniformity, selection by the draws, ranks and ids, parent and
   run_growing        daughter at distance r around the parent's position (no-force
                      cases), capacity limit, walls, and p_div = 0 equal to run
+  die / death_draw   pinned: survivors are exactly the cells whose draw (recomputed from
+                     splitmix64 in the test) is at or above p_death, in id order with
+                     their state unchanged; p_death = 0 and 1; the death and division
+                     streams differ
 Every function is pinned; none is "parity unpinned".  The absolute many-cell
 trajectories rest on the pins above plus the comparison with the GPU path.
 """
@@ -94,6 +98,8 @@ def lib():
         L.oracle_divide.argtypes = [P(OracleParams), C.c_int64, C.c_int64, dp, dp, ip, dp,
                                     C.c_uint64, C.c_int64, C.c_double, lp]
         L.oracle_divide.restype = C.c_int32
+        L.oracle_die.argtypes = [C.c_int64, dp, dp, ip, dp, C.c_uint64, C.c_int64, C.c_double, lp]
+        L.oracle_die.restype = C.c_int32
         L.oracle_sum_f32.argtypes = [P(C.c_float), C.c_int64, C.c_int32]
         L.oracle_sum_f32.restype = C.c_float
         for f in ("oracle_grid_dims", "oracle_bin", "oracle_velocity_allpairs",
@@ -269,10 +275,16 @@ def uniform(seed: int, cell_id: int, t: int, k: int) -> float:
     return float(lib().oracle_uniform(seed, cell_id, t, k))
 
 
+def death_draw(seed: int, cell_id: int, t: int) -> float:
+    """The death draw of cell `cell_id` after step t (see oracle_die in mech_oracle.c)."""
+    return uniform(seed ^ (1 << 63), cell_id, t, 0)
+
+
 def run_growing(p: OracleParams, pos, radius, type_=None, steps: int = 1, precision: int = FP64,
-                capacity: int = 0, p_div: float = 0.0, seed: int = 0, euler_first: bool = False):
-    """Steps of the method, each followed by division (arrays in id order).  Returns
-    dict(pos, vprev, radius, type, n, per_step_n, interactions)."""
+                capacity: int = 0, p_div: float = 0.0, seed: int = 0, euler_first: bool = False,
+                p_death: float = 0.0):
+    """Steps of the method, each followed by division and then death (arrays in id
+    order).  Returns dict(pos, vprev, radius, type, n, per_step_n, interactions)."""
     pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
     n = pos.shape[0]
     cap = max(capacity, n)
@@ -296,6 +308,11 @@ def run_growing(p: OracleParams, pos, radius, type_=None, steps: int = 1, precis
             n_out = C.c_int64(0)
             _check(L.oracle_divide(C.byref(p), n, cap, _d(P), _d(Rr), _i(T), _d(VP), seed, t,
                                    float(p_div), C.byref(n_out)), "divide")
+            n = int(n_out.value)
+        if p_death > 0.0:
+            n_out = C.c_int64(0)
+            _check(L.oracle_die(n, _d(P), _d(Rr), _i(T), _d(VP), seed, t, float(p_death),
+                                C.byref(n_out)), "die")
             n = int(n_out.value)
         per_n.append(n)
     return dict(pos=P[:n].copy(), vprev=VP[:n].copy(), radius=Rr[:n].copy(), type=T[:n].copy(),

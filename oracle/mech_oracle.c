@@ -501,6 +501,36 @@ int32_t oracle_divide(const OracleParams* p, int64_t n, int64_t capacity, double
     return 0;
 }
 
+/* Death (the other half of a dynamic population; the paper gives no rule either), after
+ * division in the same step:
+ *   - every cell, daughters of this step included, dies when
+ *     uniform(seed XOR 2^63, id, t, 0) < p_death: the draw of division's generator with
+ *     the seed's top bit flipped.  Its states differ from those of the division draws by
+ *     gamma times (counter difference + 2^63), nonzero mod 2^64 for t < 2^29: the two
+ *     streams never share a state;
+ *   - the dead are removed and the survivors keep their order, renumbered 0, 1, ... by
+ *     ascending old id, with their position, radius, type and v_prev unchanged. */
+int32_t oracle_die(int64_t n, double* pos, double* radius, int32_t* type, double* vprev,
+                   uint64_t seed, int64_t t, double p_death, int64_t* n_out)
+{
+    const uint64_t seed_d = seed ^ 0x8000000000000000ull;
+    int64_t kept = 0;
+    for (int64_t id = 0; id < n; ++id) {
+        if (oracle_uniform(seed_d, (uint64_t)id, (uint64_t)t, 0) < p_death) continue;
+        if (kept != id) {
+            for (int c = 0; c < 3; ++c) {
+                pos[3 * kept + c] = pos[3 * id + c];
+                vprev[3 * kept + c] = vprev[3 * id + c];
+            }
+            radius[kept] = radius[id];
+            type[kept] = type[id];
+        }
+        ++kept;
+    }
+    *n_out = kept;
+    return 0;
+}
+
 /* ------------------------------------------------------------------ threads */
 
 int32_t oracle_set_threads(int32_t t)

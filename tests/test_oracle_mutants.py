@@ -18,7 +18,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "mech_oracle.c")
 PINS = ["tests/test_oracle_closed_form.py", "tests/test_oracle_invariants.py",
         "tests/test_oracle_bruteforce.py", "tests/test_oracle_binning.py", "tests/test_kahan.py",
-        "tests/test_oracle_division.py"]
+        "tests/test_oracle_division.py", "tests/test_oracle_death.py"]
 
 # (name, text in mech_oracle.c, replacement); each text occurs exactly once
 MUTANTS = [
@@ -79,6 +79,14 @@ MUTANTS = [
     ("capacity filled from the highest id",
      "    for (int64_t id = 0; id < n && n + made < capacity; ++id) {",
      "    for (int64_t id = n - 1; id >= 0 && n + made < capacity; --id) {"),
+    ("death drawn from the division stream",
+     "    const uint64_t seed_d = seed ^ 0x8000000000000000ull;", "    const uint64_t seed_d = seed;"),
+    ("the drawn cells survive instead of dying",
+     "        if (oracle_uniform(seed_d, (uint64_t)id, (uint64_t)t, 0) < p_death) continue;",
+     "        if (!(oracle_uniform(seed_d, (uint64_t)id, (uint64_t)t, 0) < p_death)) continue;"),
+    ("a survivor's type left behind",
+     "            radius[kept] = radius[id];\n            type[kept] = type[id];",
+     "            radius[kept] = radius[id];"),
 ]
 
 
