@@ -201,6 +201,17 @@ int profile_step(MechPopulation* pop, int64_t n_steps, double* phase_ms);
  * [0, 1]. */
 int population_set_division(MechPopulation* pop, double p_div, uint64_t seed);
 
+/* Dying population: after division in step t (daughters included), cell `id` dies when
+ * its draw u0 -- the division rule's, with the seed's top bit flipped (seed ^ 2^63), so
+ * that the two streams never meet for t < 2^29 -- is below p_death.  The paper gives no
+ * death rule; this one is the library's, written to exercise a population that shrinks
+ * as well as grows.  Survivors keep their order by id and are renumbered 0, 1, ...; the
+ * cell arrays hold them in that order after the step.  The seed is the one the last
+ * population_set_division call gave (0 if none).  p_death = 0 stops death.  Waits for
+ * the stream.  MECH_E_INVALID if p_death is outside [0, 1] or the handle came from
+ * batch_create. */
+int population_set_death(MechPopulation* pop, double p_death);
+
 /* Current number of cells (waits for the stream; a growing population's size is known
  * on the device only).  read_state and read_binning take this many cells. */
 int population_size(MechPopulation* pop, int64_t* n_cells);

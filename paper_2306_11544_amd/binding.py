@@ -32,7 +32,8 @@ PRECISIONS = {"fp64": MECH_FP64, "fp32": MECH_FP32, "fp32k": MECH_FP32_KAHAN}
 EXPORTS = ("mech_last_error", "mech_abi_version", "mech_device_count",
            "population_workspace_bytes", "create_population", "create_population_in",
            "step_mechanics", "read_state", "read_binning", "read_stats", "profile_step",
-           "create_population_cap", "population_set_division", "population_size",
+           "create_population_cap", "population_set_division", "population_set_death",
+           "population_size",
            "population_set_reorder", "population_get_tuning", "population_set_tuning",
            "population_info", "population_stream", "destroy_population",
            "batch_workspace_bytes", "batch_request_voxels", "create_batch", "create_batch_in",
@@ -105,6 +106,7 @@ def lib():
             "create_population_cap": (C.c_int, [P(MechParams), C.c_int64, C.c_int64, dp, dp, ip,
                                                 dp, vp, P(vp)]),
             "population_set_division": (C.c_int, [vp, C.c_double, C.c_uint64]),
+            "population_set_death": (C.c_int, [vp, C.c_double]),
             "population_size": (C.c_int, [vp, lp]),
             "population_set_reorder": (C.c_int, [vp, C.c_int32]),
             "population_get_tuning": (C.c_int, [vp, P(MechTuning)]),
@@ -328,6 +330,11 @@ class Population:
     def set_division(self, p_div: float, seed: int = 0):
         """Cells divide with probability p_div per step (the population needs max_cells)."""
         _ck(lib().population_set_division(self.h, float(p_div), C.c_uint64(seed)))
+
+    def set_death(self, p_death: float):
+        """Cells die with probability p_death per step, after division (draws from the
+        division seed's stream with its top bit flipped)."""
+        _ck(lib().population_set_death(self.h, float(p_death)))
 
     def size(self) -> int:
         n = C.c_int64()

@@ -13,6 +13,7 @@
 //                         cell state into that order (+ the float shadow)
 //   k_force_*      a6+a7  27-voxel neighbour forces -> velocity, Adams-Bashforth, walls
 //   k_div_*               growing populations only: division after the walls
+//   k_die_*               dying populations only: death after division
 //   k_step_end            per-simulation step counters
 // The paper measures the mechanics "update velocity" loop as the region that degrades
 // when cells sit in memory in creation order rather than next to their neighbours in
@@ -726,6 +727,13 @@ struct DivArgs {
     double p_div;
     uint32_t capacity;         // cells the population may grow to
     uint32_t vp_bytes;         // 4 or 8
+    // death: the probability, and the free buffers the survivors are gathered into
+    double p_death;
+    double* X_alt[3];
+    double* R_alt;
+    int32_t* T_alt;
+    uint32_t* ID_alt;
+    void* VP_alt[3];
 };
 
 __global__ __launch_bounds__(BLOCK) void k_div_mark(DivArgs a)
@@ -856,6 +864,74 @@ __global__ void k_div_commit(DivArgs a)
     const uint32_t grown = min(a.hdr[H_DIV], room);
     a.hdr[H_CELLS] = n + grown;
     a.slots[a.slot_of[0]].n_cells += grown;
+}
+
+// ------------------------------------------------------------------------ death
+
+// Dying populations: after division in step t, cell `id` dies when its draw from the
+// division generator with the seed's top bit flipped is below p_death (the two streams
+// never share a state for t < 2^29).  The survivors keep their order by id and are
+// renumbered 0, 1, ...: flag[id] = 1 for a survivor, scanned into its new id by the
+// division scan kernels (the survivor count goes to hdr[H_DIV]); k_die_move gathers the
+// survivors into the free buffers at their new ids, k_die_back copies them home, so the
+// cells are stored in id order after the step.
+__device__ __forceinline__ bool dies(const DivArgs& a, uint32_t id, uint32_t t)
+{
+    return division_draw(a.seed ^ 0x8000000000000000ull, id, t, 0) < a.p_death;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_die_mark(DivArgs a)
+{
+    const uint32_t n = a.hdr[H_CELLS], t = a.hdr[H_STEP];
+    for (uint32_t s = blockIdx.x * BLOCK + threadIdx.x; s < n; s += gridDim.x * BLOCK) {
+        const uint32_t id = a.ID[s];
+        a.flag[id] = dies(a, id, t) ? 0u : 1u;
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_die_move(DivArgs a)
+{
+    const uint32_t n = a.hdr[H_CELLS], t = a.hdr[H_STEP];
+    for (uint32_t s = blockIdx.x * BLOCK + threadIdx.x; s < n; s += gridDim.x * BLOCK) {
+        const uint32_t id = a.ID[s];
+        if (dies(a, id, t)) continue;
+        const uint32_t d = a.flag[id];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            a.X_alt[c][d] = a.X[c][s];
+            if (a.vp_bytes == 4)
+                static_cast<float*>(a.VP_alt[c])[d] = static_cast<const float*>(a.VP[c])[s];
+            else
+                static_cast<double*>(a.VP_alt[c])[d] = static_cast<const double*>(a.VP[c])[s];
+        }
+        a.R_alt[d] = a.R[s];
+        a.T_alt[d] = a.T[s];
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_die_back(DivArgs a)
+{
+    const uint32_t n = a.hdr[H_DIV];
+    for (uint32_t d = blockIdx.x * BLOCK + threadIdx.x; d < n; d += gridDim.x * BLOCK) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            a.X[c][d] = a.X_alt[c][d];
+            if (a.vp_bytes == 4)
+                static_cast<float*>(a.VP[c])[d] = static_cast<const float*>(a.VP_alt[c])[d];
+            else
+                static_cast<double*>(a.VP[c])[d] = static_cast<const double*>(a.VP_alt[c])[d];
+        }
+        a.R[d] = a.R_alt[d];
+        a.T[d] = a.T_alt[d];
+        a.ID[d] = d;
+    }
+}
+
+__global__ void k_die_commit(DivArgs a)
+{
+    const uint32_t kept = a.hdr[H_DIV];
+    a.slots[a.slot_of[0]].n_cells = kept;
+    a.hdr[H_CELLS] = kept;
 }
 
 __global__ __launch_bounds__(BLOCK) void k_copy_positions(uint32_t n, const double* __restrict__ a0,
@@ -1812,6 +1888,7 @@ struct MechBatch {
     // growing populations: division probability per cell and step, draw seed
     double p_div = 0.0;
     uint64_t div_seed = 0;
+    double p_death = 0.0;                 // dying populations: death probability per step
     bool growing = false;                 // the device may hold more cells than the host mirror
     int64_t reorder_phase = 0;            // steps since the mode was set
     bool last_gather = true;              // the last binning reordered the cells
@@ -2141,6 +2218,45 @@ void enqueue_division(MechBatch* B, int buf)
     hipLaunchKernelGGL(k_div_commit, dim3(1), dim3(1), 0, B->stream, a);
 }
 
+// Death after division (dying populations): `buf` as for division; the survivors are
+// gathered into the other buffer pair and the positions' gathered copy XS (both free
+// once the force kernel has run), then copied back.
+void enqueue_death(MechBatch* B, int buf)
+{
+    if (!(B->p_death > 0.0)) return;
+    const Layout& L = B->L;
+    DivArgs a{};
+    for (int c = 0; c < 3; ++c) {
+        a.X[c] = B->at<double>(L.X[c]);
+        a.VP[c] = B->arena + L.VP[buf][c];
+        a.X_alt[c] = B->at<double>(L.XS[c]);
+        a.VP_alt[c] = B->arena + L.VP[buf ^ 1][c];
+    }
+    a.R = B->at<double>(L.R[buf]);
+    a.T = B->at<int32_t>(L.T[buf]);
+    a.ID = B->at<uint32_t>(L.ID[buf]);
+    a.R_alt = B->at<double>(L.R[buf ^ 1]);
+    a.T_alt = B->at<int32_t>(L.T[buf ^ 1]);
+    a.ID_alt = B->at<uint32_t>(L.ID[buf ^ 1]);
+    a.slot_of = B->at<uint32_t>(L.slot_of);
+    a.slots = B->at<SlotDesc>(L.slots);
+    a.hdr = B->at<uint32_t>(L.hdr);
+    a.flag = B->at<uint32_t>(L.tmp_key);
+    a.tsum = B->at<uint64_t>(L.dtsum);
+    a.seed = B->div_seed;
+    a.p_death = B->p_death;
+    a.vp_bytes = is_fp32(B->prm) ? 4u : 8u;
+    const uint32_t nbc = cell_grid(B);
+    const uint32_t nbt = std::min<uint32_t>(blocks_for((uint64_t)B->cap_cells, SCAN_TILE), TILE_GRID_MAX);
+    hipLaunchKernelGGL(k_die_mark, dim3(nbc), dim3(BLOCK), 0, B->stream, a);
+    hipLaunchKernelGGL(k_div_scan_reduce, dim3(nbt), dim3(BLOCK), 0, B->stream, a);
+    hipLaunchKernelGGL(k_div_scan_top, dim3(1), dim3(BLOCK), 0, B->stream, a);
+    hipLaunchKernelGGL(k_div_scan_down, dim3(nbt), dim3(BLOCK), 0, B->stream, a);
+    hipLaunchKernelGGL(k_die_move, dim3(nbc), dim3(BLOCK), 0, B->stream, a);
+    hipLaunchKernelGGL(k_die_back, dim3(nbc), dim3(BLOCK), 0, B->stream, a);
+    hipLaunchKernelGGL(k_die_commit, dim3(1), dim3(1), 0, B->stream, a);
+}
+
 // One full step a1..a7 from `parity`; flips nothing on the host.  gather: reorder the
 // cells (the default); otherwise leave them in place (the step keeps the parity).
 void enqueue_step(MechBatch* B, int parity, bool gather = true)
@@ -2155,6 +2271,7 @@ void enqueue_step(MechBatch* B, int parity, bool gather = true)
         enqueue_force_inplace_any(B);
     }
     enqueue_division(B, gather ? parity ^ 1 : parity);
+    enqueue_death(B, gather ? parity ^ 1 : parity);
     enqueue_step_end(B);
     B->parity = saved;
 }
@@ -2695,6 +2812,7 @@ int profile_impl(MechBatch* B, int64_t n_steps, double* phase_ms)
             enqueue_force_inplace_any(B);
         (void)hipEventRecord(ev[2], B->stream);
         enqueue_division(B, gather ? p ^ 1 : p);
+        enqueue_death(B, gather ? p ^ 1 : p);
         enqueue_step_end(B);
         rc = after_step(B, gather);
         if (rc == MECH_OK) rc = sync_check(B);
@@ -3013,6 +3131,20 @@ int population_set_division(MechPopulation* P, double p_div, uint64_t seed)
     B->p_div = p_div;
     B->div_seed = seed;
     if (p_div > 0.0) B->growing = true;
+    return MECH_OK;
+}
+
+int population_set_death(MechPopulation* P, double p_death)
+{
+    if (!P) return fail(MECH_E_INVALID, "population is NULL");
+    if (!(p_death >= 0.0 && p_death <= 1.0)) return fail(MECH_E_INVALID, "p_death must lie in [0, 1]");
+    MechBatch* B = P->b;
+    if (B->cap_slots != 1) return fail(MECH_E_INVALID, "death needs a population");
+    HIP_TRY(hipSetDevice(B->device));
+    HIP_TRY(hipStreamSynchronize(B->stream));
+    drop_graphs(B);
+    B->p_death = p_death;
+    if (p_death > 0.0) B->growing = true;
     return MECH_OK;
 }
 

@@ -51,27 +51,30 @@ def test_graph_replays_equal_eager(precision):
 def test_step_runs_equal_single_steps(precision):
     """A call of many steps launches them in runs of several steps per graph; the
     trajectory, interaction counts and step count equal those of one call per step, for
-    a fixed-size and for a growing population, replayed several times."""
+    a fixed-size population, a growing one and one whose cells divide and die, replayed
+    several times."""
     require_gpu()
     pop = workloads.spheroid(8000, seed=35)
     say("step runs", precision)
-    for grow in (False, True):
+    for p_div, p_death in ((0.0, 0.0), (0.01, 0.0), (0.01, 0.008)):
+        grow = p_div > 0.0
         kw = dict(max_cells=int(pop.n * 1.5)) if grow else {}
         pr = B.Population(B.params_of(pop, precision), pop.pos, pop.radius, pop.type, **kw)
         ps = B.Population(B.params_of(pop, precision), pop.pos, pop.radius, pop.type, **kw)
         try:
             if grow:
-                pr.set_division(0.01, seed=9)
-                ps.set_division(0.01, seed=9)
+                for q in (pr, ps):
+                    q.set_division(p_div, seed=9)
+                    q.set_death(p_death)
             for n in (19, 8, 3, 16):
                 pr.step(n)
                 for _ in range(n):
                     ps.step(1)
                 if grow:
-                    assert pr.size() == ps.size() > pop.n
+                    assert pr.size() == ps.size() != pop.n
                 a, va = pr.state()
                 b, vb = ps.state()
-                assert np.array_equal(a, b) and np.array_equal(va, vb), (grow, n)
+                assert np.array_equal(a, b) and np.array_equal(va, vb), (p_div, p_death, n)
                 assert pr.stats() == ps.stats()
         finally:
             pr.close()
