@@ -120,7 +120,8 @@ struct SlotDesc {
     uint32_t n_cells;          // 0 marks a retired slot during a repack
     int32_t steps_left;        // > 0 steps to run, < 0 no limit, 0 frozen
     int32_t euler;             // the next step takes v_prev = v
-    int32_t pad_[2];
+    float q_scale;             // units per um of the quantised shadow: a power of two, h q_scale <= 2^13
+    float q_pad;               // extra prefilter margin in units for float positions
 };
 static_assert(sizeof(SlotDesc) % 16 == 0, "SlotDesc alignment");
 
@@ -130,6 +131,25 @@ struct PhysArgs {
     float c_rep_f, alpha_f, c_adh0_f, pad_;
     int32_t n_types, pad2_;
 };
+
+typedef unsigned short ushort2v __attribute__((ext_vector_type(2)));
+typedef short short2v __attribute__((ext_vector_type(2)));
+// margin of the prefilter's reach in units of the quantised shadow (3 > sqrt(3) + 1)
+constexpr uint32_t Q_MARGIN = 3;
+
+// The quantised shadow of a cell, the prefilter's input: each coordinate as
+// round(x S) mod 2^16 (S = q_scale, a power of two, so x S is exact) and the reach
+// ceil(alpha r S), packed (x | y << 16, z | reach << 16).  Differences of two cells of one
+// 27-voxel neighbourhood are below 2 h S + 1 <= 2^14 + 1 units, so the 16-bit wrapped
+// difference is the exact difference of the rounded coordinates.
+__device__ __forceinline__ uint2 quantise(double x, double y, double z, double r, double S, double alpha)
+{
+    const uint32_t qx = (uint32_t)__double2ll_rn(x * S) & 0xffffu;
+    const uint32_t qy = (uint32_t)__double2ll_rn(y * S) & 0xffffu;
+    const uint32_t qz = (uint32_t)__double2ll_rn(z * S) & 0xffffu;
+    const uint32_t qr = (uint32_t)ceil(alpha * r * S);
+    return make_uint2(qx | (qy << 16), qz | (qr << 16));
+}
 
 // Workgroups are dealt to the 8 XCDs round robin; renumber the first nb of them so that
 // each XCD gets a contiguous run of the voxel-ordered cells and its own L2 keeps the
@@ -455,6 +475,10 @@ struct GatherArgs {
     const VPT* VP_cur[3];
     VPT* VP_new[3];
     float4* SH;              // nullptr in FP64
+    uint2* QS;               // quantised shadow (prefilter)
+    const uint32_t* slot_of;
+    const SlotDesc* slots;
+    double alpha;
     const uint32_t* vid_cur;
     const uint32_t* tmp_key;
     const uint32_t* tmp_src;
@@ -488,6 +512,7 @@ __global__ __launch_bounds__(BLOCK) void k_rank_gather(const uint32_t* __restric
         for (int c = 0; c < 3; ++c) a.VP_new[c][d] = a.VP_cur[c][s];
         a.vid_sorted[d] = v;
         if (a.SH) a.SH[d] = make_float4((float)x, (float)y, (float)z, (float)r);
+        a.QS[d] = quantise(x, y, z, r, (double)a.slots[a.slot_of[s]].q_scale, a.alpha);
     }
 }
 
@@ -607,6 +632,7 @@ __global__ __launch_bounds__(SMALL_BLOCK) void k_bin_small(const uint32_t* __res
         for (int c = 0; c < 3; ++c) a.VP_new[c][d] = a.VP_cur[c][s];
         a.vid_sorted[d] = v;
         if (a.SH) a.SH[d] = make_float4((float)x, (float)y, (float)z, (float)r);
+        a.QS[d] = quantise(x, y, z, r, (double)a.slots[a.slot_of[s]].q_scale, a.alpha);
     }
 }
 
@@ -648,11 +674,15 @@ __global__ __launch_bounds__(BLOCK) void k_commit(const uint32_t* __restrict__ h
 // Cells left in place: the float shadow of the positions, in storage order.
 __global__ __launch_bounds__(BLOCK) void k_shadow(const uint32_t* __restrict__ hdr, const double* __restrict__ x0,
                                                   const double* __restrict__ x1, const double* __restrict__ x2,
-                                                  const double* __restrict__ r, float4* __restrict__ sh)
+                                                  const double* __restrict__ r, float4* __restrict__ sh,
+                                                  uint2* __restrict__ qs, const uint32_t* __restrict__ slot_of,
+                                                  const SlotDesc* __restrict__ slots, double alpha)
 {
     const uint32_t n = hdr[H_CELLS];
-    for (uint32_t s = blockIdx.x * BLOCK + threadIdx.x; s < n; s += gridDim.x * BLOCK)
+    for (uint32_t s = blockIdx.x * BLOCK + threadIdx.x; s < n; s += gridDim.x * BLOCK) {
         sh[s] = make_float4((float)x0[s], (float)x1[s], (float)x2[s], (float)r[s]);
+        qs[s] = quantise(x0[s], x1[s], x2[s], r[s], (double)slots[slot_of[s]].q_scale, alpha);
+    }
 }
 
 // Before the cells are left in place: put them in id order (the order they were given
@@ -957,6 +987,7 @@ struct ForceArgs {
     const double* R;
     const int32_t* T;
     const float4* SH;
+    const uint2* QS;
     const uint32_t* vid_sorted;
     const uint32_t* voxel_start;
     const uint32_t* slot_of;
@@ -1217,19 +1248,14 @@ __global__ __launch_bounds__(WPB * WAVE) void k_force_rows(PhysArgs P, ForceArgs
 // One thread per cell in storage (bin) order.  Each lane walks its 9 neighbour rows,
 // reading in each only the x slabs within reach of its cell (a contiguous run: slabs of
 // x-adjacent voxels follow each other), and only prefilters the candidates, FC_UNROLL
-// loads in flight per trip.  The prefilter runs on the float shadow (x, y, z, r) in
-// every precision: a candidate is listed in LDS when
-//   d2 < fl(s * s),  s = fma(a', r_j, fl(a' r_i) [+ E]),  a' = fl(alpha (1 + 2^-18)),
-// d2 the same float expression as in pair32, which every interacting pair satisfies.
-// FP32: the exact bound fl(fl(alpha fl(r_i + r_j))^2) is at most
-// alpha^2 (r_i + r_j)^2 (1 + 2^-24)^5, while fl(s * s) is at least
-// alpha^2 (r_i + r_j)^2 (1 + 2^-18)^2 (1 - 2^-24)^7, which is larger.  FP64: the exact
-// decision is on the double positions; rounding each coordinate (at most P in size, P
-// the largest |lo| or |hi| of the slot's domain) to float moves the float distance by at
-// most 2 sqrt(3) 2^-24 P and the float arithmetic by a few 2^-24 relative, which the
-// pad E = 2^-21 P and the 2^-18 margin cover.  Using r_j (the w of the float4 already
-// loaded) the prefilter lists little beyond the interacting pairs, and one float4 load
-// per candidate replaces three double loads in FP64.  When a list fills, and at the end,
+// loads in flight per trip.  The prefilter runs on the quantised shadow (8 bytes per
+// cell: the coordinates in units of 1/S um wrapped to 16 bits, and the reach
+// ceil(alpha r S)) in every precision, in exact integer arithmetic: a candidate is
+// listed in LDS when its squared distance in units is below (reach_i + reach_j)^2, the
+// lane's reach carrying a margin that covers the rounding of the coordinates and of the
+// exact decision (see `near`).  Half the bytes of the float shadow per candidate, and a
+// 16-bit packed difference and an int16 dot product in place of float arithmetic.
+// When a list fills, and at the end,
 // the lanes evaluate their listed candidates together with the exact decision and
 // pair term of pair64 / pair32, in candidate order, so each sum is still taken in the
 // fixed neighbour order and the rare interacting pairs do not make the wave diverge.
@@ -1278,52 +1304,58 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
         zi = m.z;
         ri = m.w;
     }
-    // the prefilter works on the float shadow in every precision: a' and fl(a' r_i),
-    // plus in FP64 the pad E for the rounding of the positions to float
-    const float4 mf = a.SH[ii];
-    float al, ai;
-    {
-#pragma clang fp contract(off)
-        al = P.alpha_f * (1.0f + 0x1p-18f);
-        ai = al * mf.w;
-        if constexpr (PREC == 0) {
-            const double pmax = fmax(fmax(fmax(fabs(d.lo[0]), fabs(d.hi[0])), fmax(fabs(d.lo[1]), fabs(d.hi[1]))),
-                                     fmax(fabs(d.lo[2]), fabs(d.hi[2])));
-            ai = ai + (float)(pmax * 0x1p-21);
-        }
-    }
+    // the prefilter's lane constants: the quantised (x | y << 16) and (z | 0) of the cell,
+    // and its reach ceil(alpha r_i S) plus the margin (below)
+    const uint2 qi = a.QS[ii];
+    const uint32_t q_xy = qi.x, q_z = qi.y & 0xffffu;
+    const uint32_t q_a = (uint32_t)ceil(P.alpha * a.R[ii] * (double)d.q_scale) + Q_MARGIN + (uint32_t)d.q_pad;
     const int ti = MULTI ? a.T[ii] : 0;
     Real acc[3] = {0, 0, 0}, cmp[3] = {0, 0, 0};
     // The short list (LIST = 16, picked for dense populations) is a ring,
-    // list0[(k mod LIST) * WAVE]: the listed candidates run from head up to tail
+    // list0[(k mod LIST) * WAVE]: the listed entries run from head up to tail
     // (excluded), oldest first, and a flush inside the walk evaluates only the oldest
-    // entries (below).  The long lists (32, 64: small populations, few waves per SIMD)
-    // are plain arrays from list0, emptied whole.  Every tested candidate is written at
-    // tail, which advances only when it passed (no branch).  A trip starts with fewer
-    // than LIST - FC_UNROLL entries, so a list never holds more than LIST - 1 and, in the
-    // ring, (tail - head) mod LIST is its exact length.
+    // entries (below).  In the ring an entry is up to 4 candidates of a trip:
+    // (j << 4) | m, the candidates j + u with bit u of m set (j < 2^28), so a trip of 4
+    // writes one entry and moves tail at most once.  The
+    // long lists (32, 64: small populations, few waves per SIMD) and the walk through
+    // perm hold one candidate per entry, from list0, emptied whole.  Every trip writes
+    // its entry at tail, which advances only when the entry holds a candidate (no
+    // branch).  The ring stays below LIST - EPT entries before a trip and the lists below
+    // LIST - FC_UNROLL, so a list never holds more than LIST - 1 and, in the ring,
+    // (tail - head) mod LIST is its exact length.
     constexpr bool RING = LIST < 32;
+    constexpr bool PACK = RING && !IND;
     constexpr uint32_t MASK = RING ? (uint32_t)LIST - 1u : 0xffffffffu;
     static_assert(!RING || (LIST & (LIST - 1)) == 0, "the ring length is a power of two");
-    // entries a lane may keep after a flush inside the walk
-    constexpr uint32_t KEEP =
-        RING ? std::min<uint32_t>((uint32_t)LIST * 5u / 8u, (uint32_t)(LIST - FC_UNROLL) - 1u) : 0u;
-    static_assert(KEEP < (uint32_t)(LIST - FC_UNROLL), "a flush makes room for the next trip");
-    uint32_t head = 0, tail = 0;
-    auto push = [&](uint32_t j, bool in) {
-        list0[tail * WAVE] = j;
+    // packed entries a trip writes (4 candidates each at most), entries after which a
+    // trip flushes, and entries a lane may keep after a flush
+    constexpr uint32_t EPT = (uint32_t)(FC_UNROLL + 3) / 4u;
+    constexpr uint32_t FULL = PACK ? (uint32_t)LIST - EPT : (uint32_t)(LIST - FC_UNROLL);
+    constexpr uint32_t KEEP = RING ? (uint32_t)LIST * 5u / 8u : 0u;
+    static_assert(KEEP < FULL, "a flush makes room for the next trip");
+    uint32_t head = 0, tail = 0, done = 0;  // done: bits of the head entry already evaluated
+    auto push = [&](uint32_t e, bool in) {
+        list0[tail * WAVE] = e;
         tail = (tail + (in ? 1u : 0u)) & MASK;
     };
     auto count = [&]() { return (tail - head) & MASK; };
-    auto full = [&]() { return __any(count() >= (uint32_t)(LIST - FC_UNROLL)); };
+    auto full = [&]() { return __any(count() >= FULL); };
 
-    // the prefilter on a candidate's float shadow (x, y, z, r)
-    auto near = [&](float cx, float cy, float cz, float cw) -> bool {
-#pragma clang fp contract(off)
-        const float dx = mf.x - cx, dy = mf.y - cy, dz = mf.z - cz;
-        const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
-        const float s = __builtin_fmaf(al, cw, ai);
-        return d2 < s * s;
+    // The prefilter on a candidate's quantised shadow c: with D the squared distance of
+    // the rounded coordinates in units (exact: 16-bit wrapped differences, an int16
+    // dot product) and t = q_a + ceil(alpha r_j S), the candidate is listed when D < t^2.
+    // Each rounded difference is within 1 unit of (x_i - x_j) S, so sqrt(D) is within
+    // sqrt(3) of d S; an interacting pair has d < alpha (r_i + r_j) up to the relative
+    // rounding of its decision (2^-50 in FP64, a few 2^-24 in FP32, there plus the
+    // rounding of the positions to float, at most 2^-22 P S units, which q_pad covers),
+    // so sqrt(D) < t - Q_MARGIN + 2 and every interacting pair is listed.
+    auto near = [&](uint2 c) -> bool {
+        const ushort2v du = __builtin_bit_cast(ushort2v, q_xy) - __builtin_bit_cast(ushort2v, c.x);
+        const int dz = (int)(short)(uint16_t)(q_z - c.y);
+        const int d2 = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2v, du), __builtin_bit_cast(short2v, du),
+                                              dz * dz, false);
+        const uint32_t t = q_a + (c.y >> 16);
+        return (uint32_t)d2 < __umul24(t, t);
     };
     // The candidate data a flush evaluates.  With the long lists (few waves per SIMD
     // hide little latency) the next entry's data is fetched before the current one is
@@ -1360,14 +1392,30 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
                                        cadh, acc, cmp);
         }
     };
-    // The ring evaluates in every lane its oldest entries, as many as bring the fullest
-    // list down to `keep` (all of them when keep is 0).  Each pass then keeps every lane
-    // that still holds that many entries busy, where emptying whole lists would leave the
-    // lanes with short lists idle for most of the passes.  A long list is emptied whole,
-    // the next entry's data fetched before the current one is evaluated.
+    // The ring evaluates in every lane the candidates of its oldest entries, one per pass
+    // and in candidate order, until the fullest list is down to `keep` entries (all of
+    // them when keep is 0).  Each pass keeps every lane that still holds an entry busy,
+    // where emptying whole lists would leave the lanes with short lists idle for most of
+    // the passes.  A long list is emptied whole, the next entry's data fetched before
+    // the current one is evaluated.
     auto flush = [&](uint32_t keep) {
-        const uint32_t c = count();
-        if constexpr (!RING) {
+        if constexpr (PACK) {
+#pragma unroll 1
+            for (;;) {
+                const uint32_t c = count();
+                if (!__any(c > keep)) break;
+                if (c > 0) {
+                    const uint32_t e = list0[head * WAVE];
+                    const uint32_t m = e & 15u & ~done;
+                    const uint32_t b = (uint32_t)__builtin_ctz(m);
+                    eval(fetch((e >> 4) + b));
+                    const bool last = (m & (m - 1u)) == 0u;
+                    done = last ? 0u : done | (1u << b);
+                    head = (head + (last ? 1u : 0u)) & MASK;
+                }
+            }
+        } else if constexpr (!RING) {
+            const uint32_t c = count();
             Cand cn = fetch(c > 0 ? list0[0] : ii);
 #pragma unroll 1
             for (uint32_t k = 0; k < (uint32_t)LIST; ++k) {
@@ -1379,6 +1427,7 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
             }
             tail = 0;
         } else {
+            const uint32_t c = count();
             uint32_t k = 0;
 #pragma unroll 1
             for (; k < (uint32_t)LIST; ++k) {
@@ -1399,24 +1448,36 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
             // gathers through the sorted order: no locality between consecutive lanes
             for (; j < e; ++j) {
                 const uint32_t jj = a.perm[j];
-                const float4 c = a.SH[jj];
-                push(jj, near(c.x, c.y, c.z, c.w));
+                push(jj, near(a.QS[jj]));
                 if (full()) flush(KEEP);
             }
             continue;
         }
-        const float4* sp = a.SH + j;
+        const uint2* sp = a.QS + j;
         for (; j + FC_UNROLL <= e; j += FC_UNROLL, sp += FC_UNROLL) {
-            float4 c[FC_UNROLL];
+            uint2 c[FC_UNROLL];
 #pragma unroll
             for (int u = 0; u < FC_UNROLL; ++u) c[u] = sp[u];
+            if constexpr (PACK) {
 #pragma unroll
-            for (int u = 0; u < FC_UNROLL; ++u) push(j + u, near(c[u].x, c[u].y, c[u].z, c[u].w));
+                for (int g4 = 0; g4 < FC_UNROLL; g4 += 4) {
+                    uint32_t m = 0;
+#pragma unroll
+                    for (int u = g4; u < FC_UNROLL && u < g4 + 4; ++u) m |= (near(c[u]) ? 1u : 0u) << (u - g4);
+                    push(((j + g4) << 4) | m, m != 0u);
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < FC_UNROLL; ++u) push(j + u, near(c[u]));
+            }
             if (full()) flush(KEEP);
         }
         for (; j < e; ++j, ++sp) {
-            const float4 c = *sp;
-            push(j, near(c.x, c.y, c.z, c.w));
+            const bool in = near(*sp);
+            if constexpr (PACK)
+                push((j << 4) | 1u, in);
+            else
+                push(j, in);
             if (full()) flush(KEEP);
         }
     }
@@ -1723,7 +1784,7 @@ __global__ __launch_bounds__(BLOCK) void k_unpermute(uint32_t cell_off, uint32_t
 inline uint32_t blocks_for(uint64_t n, uint32_t per) { return (uint32_t)((n + per - 1) / per); }
 
 struct Layout {
-    size_t X[3], XS[3], R[2], T[2], ID[2], VP[2][3], SH, slot_of, vid_cur, off, tmp_key, dtsum,
+    size_t X[3], XS[3], R[2], T[2], ID[2], VP[2][3], SH, QS, slot_of, vid_cur, off, tmp_key, dtsum,
         tmp_src, vid_sorted, count, start, occ, hdr, tsum, stats, cadh, cadh_f, slots, stage;
     size_t total;
 };
@@ -1751,6 +1812,7 @@ Layout make_layout(const MechParams& p, int64_t ncap, uint64_t vcap, int32_t sca
         for (int c = 0; c < 3; ++c) L.VP[k][c] = take(nn * vpb);
     }
     L.SH = take(nn * 16);
+    L.QS = take(nn * 8);
     L.slot_of = take(nn * 4);
     L.vid_cur = take(nn * 4);
     L.off = take(nn * 4);
@@ -1979,6 +2041,10 @@ void enqueue_binning(MechBatch* B)
     g.T_new = B->at<int32_t>(L.T[nxt]);
     g.ID_new = B->at<uint32_t>(L.ID[nxt]);
     g.SH = B->at<float4>(L.SH);
+    g.QS = B->at<uint2>(L.QS);
+    g.slot_of = B->at<uint32_t>(L.slot_of);
+    g.slots = B->at<SlotDesc>(L.slots);
+    g.alpha = B->phys.alpha;
     g.vid_cur = B->at<uint32_t>(L.vid_cur);
     g.tmp_key = B->at<uint32_t>(L.tmp_key);
     g.tmp_src = B->at<uint32_t>(L.tmp_src);
@@ -2017,7 +2083,11 @@ void launch_cells_l(MechBatch* B, const ForceArgs<VPT>& a)
 template <int PREC, bool MULTI, typename VPT, int WPB>
 void launch_cells_w(MechBatch* B, const ForceArgs<VPT>& a)
 {
-    switch (B->tune.list_len) {
+    // the ring's packed entries hold candidate indices below 2^28: larger arenas take
+    // the 32-entry list
+    const int len = (B->tune.list_len == 16 || B->tune.list_len == 0) && B->cap_cells >= ((int64_t)1 << 28)
+                        ? 32 : B->tune.list_len;
+    switch (len) {
     case 32: launch_cells_l<PREC, MULTI, VPT, WPB, 32>(B, a); break;
     case 64: launch_cells_l<PREC, MULTI, VPT, WPB, 64>(B, a); break;
     default: launch_cells_l<PREC, MULTI, VPT, WPB, 16>(B, a); break;
@@ -2067,6 +2137,7 @@ void enqueue_force(MechBatch* B, int parity_after_sort)
     a.R = B->at<double>(L.R[p]);
     a.T = B->at<int32_t>(L.T[p]);
     a.SH = B->at<float4>(L.SH);
+    a.QS = B->at<uint2>(L.QS);
     a.vid_sorted = B->at<uint32_t>(L.vid_sorted);
     a.voxel_start = B->at<uint32_t>(L.start);
     a.slot_of = B->at<uint32_t>(L.slot_of);
@@ -2134,6 +2205,7 @@ void enqueue_force_inplace(MechBatch* B)
     a.R = B->at<double>(L.R[cur]);
     a.T = B->at<int32_t>(L.T[cur]);
     a.SH = B->at<float4>(L.SH);
+    a.QS = B->at<uint2>(L.QS);
     a.vid_sorted = B->at<uint32_t>(L.vid_cur);
     a.voxel_start = B->at<uint32_t>(L.start);
     a.slot_of = B->at<uint32_t>(L.slot_of);
@@ -2159,7 +2231,8 @@ void enqueue_binning_inplace(MechBatch* B)
     const uint32_t* hdr = B->at<uint32_t>(L.hdr);
     hipLaunchKernelGGL(k_shadow, dim3(nbc), dim3(BLOCK), 0, B->stream, hdr, B->at<double>(L.X[0]),
                        B->at<double>(L.X[1]), B->at<double>(L.X[2]), B->at<double>(L.R[cur]),
-                       B->at<float4>(L.SH));
+                       B->at<float4>(L.SH), B->at<uint2>(L.QS), B->at<uint32_t>(L.slot_of),
+                       B->at<SlotDesc>(L.slots), B->phys.alpha);
     enqueue_keys(B);
     hipLaunchKernelGGL(k_rank_perm, dim3(nbc), dim3(BLOCK), 0, B->stream, hdr, B->at<uint32_t>(L.vid_cur),
                        B->at<uint32_t>(L.tmp_key), B->at<uint32_t>(L.tmp_src), B->at<uint32_t>(L.start),
@@ -2584,6 +2657,14 @@ int admit_impl(MechBatch* B, const double lo[3], const double hi[3], int64_t n, 
     d.inv_h = 1.0 / B->prm.voxel_size;
     d.r_max = rmax;
     d.r_max_f = (float)rmax;
+    // the largest power of two with h S <= 2^13, and the margin for float positions
+    // (2^-20 P S units, P the largest coordinate magnitude of the domain)
+    d.q_scale = (float)std::ldexp(1.0, (int)std::floor(std::log2(8192.0 / B->prm.voxel_size)));
+    {
+        double pm = 0.0;
+        for (int a = 0; a < 3; ++a) pm = std::max(pm, std::max(std::fabs(lo[a]), std::fabs(hi[a])));
+        d.q_pad = (float)std::ceil(pm * (double)d.q_scale * 0x1p-20);
+    }
     d.nx = dims[0];
     d.ny = dims[1];
     d.nz = dims[2];
