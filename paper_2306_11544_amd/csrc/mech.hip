@@ -40,6 +40,7 @@
 //   R[2]    f64  radius, T[2] i32 type, ID[2] u32 cell id, VP[2][3] v_prev (f64 or f32):
 //                double-buffered; parity p holds them in the order of X
 //   SH      float4 (x, y, z, r) in bin order, FP32 variants only
+//   QS      8 bytes per cell in bin order: the quantised shadow the prefilter reads
 //   slot_of u32  slot of the cell at each index (constant between repacks)
 // Binning scratch: vid_cur, off, tmp_key, tmp_src, vid_sorted (u32 per cell);
 // count, voxel_start (u32 per bin, XSUB bins per voxel), occ (u32 per voxel); tile sums
@@ -680,7 +681,7 @@ __global__ __launch_bounds__(BLOCK) void k_shadow(const uint32_t* __restrict__ h
 {
     const uint32_t n = hdr[H_CELLS];
     for (uint32_t s = blockIdx.x * BLOCK + threadIdx.x; s < n; s += gridDim.x * BLOCK) {
-        sh[s] = make_float4((float)x0[s], (float)x1[s], (float)x2[s], (float)r[s]);
+        if (sh) sh[s] = make_float4((float)x0[s], (float)x1[s], (float)x2[s], (float)r[s]);
         qs[s] = quantise(x0[s], x1[s], x2[s], r[s], (double)slots[slot_of[s]].q_scale, alpha);
     }
 }
@@ -1440,11 +1441,19 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
         }
     };
 
-    for (int q = 0; q < 9; ++q) {
+    // the candidate range [j, e) of neighbour row q (empty outside the grid); the next
+    // row's range is read while the current row is walked
+    auto range = [&](int q, uint32_t& j, uint32_t& e) {
         const int64_t r0 = valid ? row_first(g, d, q) : -1;
-        if (r0 < 0) continue;
-        uint32_t j = a.voxel_start[XSUB * r0 + w0];
-        const uint32_t e = a.voxel_start[XSUB * r0 + w1];
+        j = r0 < 0 ? 0u : a.voxel_start[XSUB * r0 + w0];
+        e = r0 < 0 ? 0u : a.voxel_start[XSUB * r0 + w1];
+    };
+    uint32_t j_next, e_next;
+    range(0, j_next, e_next);
+    for (int q = 0; q < 9; ++q) {
+        uint32_t j = j_next;
+        const uint32_t e = e_next;
+        if (q < 8) range(q + 1, j_next, e_next);
         cand += e - j;
         if constexpr (IND) {
             // gathers through the sorted order: no locality between consecutive lanes
@@ -1813,7 +1822,7 @@ Layout make_layout(const MechParams& p, int64_t ncap, uint64_t vcap, int32_t sca
         L.ID[k] = take(nn * 4);
         for (int c = 0; c < 3; ++c) L.VP[k][c] = take(nn * vpb);
     }
-    L.SH = take(nn * 16);
+    L.SH = take(is_fp32(p) ? nn * 16 : 0);   // read by the FP32 kernels only
     L.QS = take(nn * 8);
     L.slot_of = take(nn * 4);
     L.vid_cur = take(nn * 4);
@@ -2042,7 +2051,7 @@ void enqueue_binning(MechBatch* B)
     g.T_cur = B->at<int32_t>(L.T[cur]);
     g.T_new = B->at<int32_t>(L.T[nxt]);
     g.ID_new = B->at<uint32_t>(L.ID[nxt]);
-    g.SH = B->at<float4>(L.SH);
+    g.SH = is_fp32(B->prm) ? B->at<float4>(L.SH) : nullptr;
     g.QS = B->at<uint2>(L.QS);
     g.slot_of = B->at<uint32_t>(L.slot_of);
     g.slots = B->at<SlotDesc>(L.slots);
@@ -2138,7 +2147,7 @@ void enqueue_force(MechBatch* B, int parity_after_sort)
     }
     a.R = B->at<double>(L.R[p]);
     a.T = B->at<int32_t>(L.T[p]);
-    a.SH = B->at<float4>(L.SH);
+    a.SH = is_fp32(B->prm) ? B->at<float4>(L.SH) : nullptr;
     a.QS = B->at<uint2>(L.QS);
     a.vid_sorted = B->at<uint32_t>(L.vid_sorted);
     a.voxel_start = B->at<uint32_t>(L.start);
@@ -2206,7 +2215,7 @@ void enqueue_force_inplace(MechBatch* B)
     }
     a.R = B->at<double>(L.R[cur]);
     a.T = B->at<int32_t>(L.T[cur]);
-    a.SH = B->at<float4>(L.SH);
+    a.SH = is_fp32(B->prm) ? B->at<float4>(L.SH) : nullptr;
     a.QS = B->at<uint2>(L.QS);
     a.vid_sorted = B->at<uint32_t>(L.vid_cur);
     a.voxel_start = B->at<uint32_t>(L.start);
@@ -2233,7 +2242,8 @@ void enqueue_binning_inplace(MechBatch* B)
     const uint32_t* hdr = B->at<uint32_t>(L.hdr);
     hipLaunchKernelGGL(k_shadow, dim3(nbc), dim3(BLOCK), 0, B->stream, hdr, B->at<double>(L.X[0]),
                        B->at<double>(L.X[1]), B->at<double>(L.X[2]), B->at<double>(L.R[cur]),
-                       B->at<float4>(L.SH), B->at<uint2>(L.QS), B->at<uint32_t>(L.slot_of),
+                       is_fp32(B->prm) ? B->at<float4>(L.SH) : nullptr, B->at<uint2>(L.QS),
+                       B->at<uint32_t>(L.slot_of),
                        B->at<SlotDesc>(L.slots), B->phys.alpha);
     enqueue_keys(B);
     hipLaunchKernelGGL(k_rank_perm, dim3(nbc), dim3(BLOCK), 0, B->stream, hdr, B->at<uint32_t>(L.vid_cur),
