@@ -42,12 +42,13 @@ PEAK_FP64_VECTOR_TFLOPS = 78.6
 #   cell: Adams-Bashforth 3 x (2 mul + 1 sub + 1 fma) + walls          -> negligible
 FLOP_PER_CANDIDATE = 11
 FLOP_PER_INTERACTION = {"fp64": 18, "fp32": 18, "fp32k": 27}
-# algorithmic HBM bytes per cell of the force kernel: own f64 position (24) + own and
-# neighbour float shadow read once each (16 + 16; the prefilter in every precision) +
-# in FP64 the neighbour's f64 position and radius once (32) + v_prev in/out + voxel id
-# (4) + new f64 position (24)
-FORCE_BYTES_PER_CELL = {"fp64": 24 + 32 + 32 + 4 + 48 + 24, "fp32": 24 + 32 + 4 + 24 + 24,
-                        "fp32k": 24 + 32 + 4 + 24 + 24}
+# algorithmic HBM bytes per cell of the force kernel: own f64 position and radius
+# (24 + 8) + own and neighbour quantised shadow read once each (8 + 8; the prefilter in
+# every precision) + for the pair terms the own and neighbour float shadow once each
+# (16 + 16, FP32) or the neighbour's f64 position and radius once (32, FP64) + v_prev
+# in/out (24 FP32, 48 FP64) + voxel id (4) + new f64 position (24)
+FORCE_BYTES_PER_CELL = {"fp64": 24 + 8 + 16 + 32 + 48 + 4 + 24, "fp32": 24 + 8 + 16 + 32 + 24 + 4 + 24,
+                        "fp32k": 24 + 8 + 16 + 32 + 24 + 4 + 24}
 
 
 def tuning_str(t: dict) -> str:
