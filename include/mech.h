@@ -208,8 +208,7 @@ int population_set_division(MechPopulation* pop, double p_div, uint64_t seed);
  * as well as grows.  Survivors keep their order by id and are renumbered 0, 1, ...; the
  * cell arrays hold them in that order after the step.  The seed is the one the last
  * population_set_division call gave (0 if none).  p_death = 0 stops death.  Waits for
- * the stream.  MECH_E_INVALID if p_death is outside [0, 1] or the handle came from
- * batch_create. */
+ * the stream.  MECH_E_INVALID if p_death is outside [0, 1]. */
 int population_set_death(MechPopulation* pop, double p_death);
 
 /* Current number of cells (waits for the stream; a growing population's size is known
