@@ -1878,8 +1878,21 @@ int validate_physics(const MechParams* p)
     return MECH_OK;
 }
 
+// Units per um of the quantised shadow: the largest power of two S with h S <= 2^13.
+double quant_scale(double h) { return std::ldexp(1.0, (int)std::floor(std::log2(8192.0 / h))); }
+
 int validate_domain(const double lo[3], const double hi[3], double h, int32_t dims[3], uint64_t* V)
 {
+    // the quantised shadow rounds x S to an integer: it must stay exact in a double
+    // (and S finite in a float)
+    {
+        const double S = quant_scale(h);
+        double pm = 0.0;
+        for (int a = 0; a < 3; ++a) pm = std::max(pm, std::max(std::fabs(lo[a]), std::fabs(hi[a])));
+        if (!(S < 0x1p100)) return fail(MECH_E_INVALID, "voxel_size %.17g is too small", h);
+        if (!(pm * S < 0x1p52))
+            return fail(MECH_E_INVALID, "domain coordinates up to %.17g um are too large for voxel_size %.17g", pm, h);
+    }
     uint64_t v = 1;
     for (int a = 0; a < 3; ++a) {
         if (!(std::isfinite(lo[a]) && std::isfinite(hi[a]) && hi[a] >= lo[a]))
@@ -2671,7 +2684,7 @@ int admit_impl(MechBatch* B, const double lo[3], const double hi[3], int64_t n, 
     d.r_max_f = (float)rmax;
     // the largest power of two with h S <= 2^13, and the margin for float positions
     // (2^-20 P S units, P the largest coordinate magnitude of the domain)
-    d.q_scale = (float)std::ldexp(1.0, (int)std::floor(std::log2(8192.0 / B->prm.voxel_size)));
+    d.q_scale = (float)quant_scale(B->prm.voxel_size);
     {
         double pm = 0.0;
         for (int a = 0; a < 3; ++a) pm = std::max(pm, std::max(std::fabs(lo[a]), std::fabs(hi[a])));

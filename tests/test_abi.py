@@ -89,6 +89,9 @@ def _p(**kw):
     (lambda p: setattr(p, "n_types", 9), B.MECH_E_INVALID),
     (lambda p: setattr(p, "n_types", 0), B.MECH_E_INVALID),
     (lambda p: p.domain_hi.__setitem__(0, -200.0), B.MECH_E_INVALID),
+    # the quantised prefilter needs |x| S < 2^52 (S = 256 per um at a 30 um voxel)
+    (lambda p: p.domain_hi.__setitem__(1, 2.0 ** 45), B.MECH_E_INVALID),
+    (lambda p: setattr(p, "voxel_size", 1e-40), B.MECH_E_INVALID),
 ])
 def test_workspace_bytes_rejects_bad_params(mutate, code):
     p, pop = _p()
