@@ -76,7 +76,9 @@ def measured_counters(kernel: str, workload: str, precision: str, tuning: dict):
       valu_issue_frac  wave64 VALU instructions / issue slots (one per CU per cycle;
                        GRBM_GUI_ACTIVE sums the 8 XCDs' cycles)
       valu_lane_util   active lanes per VALU instruction / 64
-      td_busy_frac     texture-data (vector load return) busy cycles / cycles"""
+      td_busy_frac     texture-data (vector load return) busy cycles / cycles
+      mean_waves_per_cu  rocprofv3's MeanOccupancyPerCU (waves resident per CU, averaged
+                       over the kernel's run; 32 is the most a CU holds), when profiled"""
     import re
     from paper_2306_11544_amd import rocprof_summary as RS
     path = os.path.join(ROOT, "profiles", f"pmc_{kernel}_{workload}_{precision}.txt")
@@ -95,6 +97,7 @@ def measured_counters(kernel: str, workload: str, precision: str, tuning: dict):
     return {"valu_issue_frac": v["SQ_INSTS_VALU"] / (cus * cycles),
             "valu_lane_util": v["SQ_THREAD_CYCLES_VALU"] / (64.0 * v["SQ_ACTIVE_INST_VALU"]),
             "td_busy_frac": v["TD_TD_BUSY_sum"] / (cus * cycles),
+            "mean_waves_per_cu": v.get("MeanOccupancyPerCU"),
             "source": os.path.relpath(path, ROOT)}
 
 
@@ -110,6 +113,27 @@ def copy_calibration(mb: int, stream):
             torch.neg(src, out=dst)
     torch.cuda.synchronize()
     log(f"copy calibration: 3 x neg over {n * 4} bytes")
+
+
+def copy_bandwidth(stream, mb: int = 1024, reps: int = 5) -> float:
+    """Achieved HBM bandwidth of a plain streaming kernel on this GPU (GB/s): y = -x over
+    mb MiB of float32 (reads and writes mb MiB each), timed with HIP events on `stream`."""
+    import torch
+    n = (mb << 20) // 4
+    with torch.cuda.stream(stream):
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            torch.neg(src, out=dst)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            torch.neg(src, out=dst)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return 2.0 * n * 4 / (ms * 1e-3) / 1e9
 
 
 def log(*a):
@@ -434,6 +458,8 @@ def main():
     P.close()
     if args.calibrate_copy_mb:
         copy_calibration(args.calibrate_copy_mb, stream)
+    copy_gbs = copy_bandwidth(stream)
+    log(f"streaming copy: {copy_gbs:.0f} GB/s")
     traffic = measured_traffic(kname, pop.name, precision, tuning)
     counters = measured_counters(kname, pop.name, precision, tuning)
 
@@ -467,7 +493,12 @@ def main():
                      "force_ms_per_launch": force_ms,
                      "counters": counters,
                      "hbm_algorithmic_GBs": force_gbs,
-                     "hbm_frac": force_gbs / PEAK_HBM_GBS},
+                     "hbm_frac": force_gbs / PEAK_HBM_GBS,
+                     # the same rates against what a plain streaming copy reaches here
+                     "copy_GBs": copy_gbs,
+                     "hbm_frac_of_copy": force_gbs / copy_gbs,
+                     "traffic_frac_of_copy": None if traffic is None
+                     else traffic / (force_ms * 1e-3) / 1e9 / copy_gbs},
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
