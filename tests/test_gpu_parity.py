@@ -157,6 +157,29 @@ def test_tumour1m_first_step_sampled(orc):
     assert np.abs(got["vel"].sum(axis=0)).max() <= 1e-5 * np.abs(got["vel"]).sum()
 
 
+def test_tumour1m_full_200_steps(orc):
+    """The 1M-cell tumour at full size for its stated 200 steps: the FP64 path and the
+    FP32 + Kahan path against the FP64 oracle, run on the host's cores in chunks of 20
+    steps (each chunk resumes from the last positions and v_prev, as the method does)."""
+    require_gpu()
+    pop = workloads.config("tumour1m")
+    p = orc.params_of(pop)
+    pos, vprev, inter = pop.pos, None, 0
+    for k in range(10):
+        out = orc.run(p, pos, pop.radius, pop.type, vprev, steps=20)
+        pos, vprev, inter = out["pos"], out["vprev"], inter + out["interactions"]
+        say("tumour1m fp64 oracle", 20 * (k + 1), "of", pop.steps, "steps")
+    for precision, tol, label in ((B.MECH_FP64, FP64_TOL, "fp64"),
+                                  (B.MECH_FP32_KAHAN, FP32_TOL, "fp32k")):
+        got = run_gpu(pop, pop.steps, precision=precision)
+        err = pos_err(got["pos"], pos, pop.half_width)
+        record(f"{label} tumour1m {pop.steps} steps vs fp64 oracle", err,
+               interactions=got["interactions"], oracle_interactions=inter)
+        assert err <= tol, (label, err)
+        if precision == B.MECH_FP64:
+            assert abs(got["interactions"] - inter) <= 1e-9 * inter + 2
+
+
 def test_tumour1m_full_run_properties():
     """All 200 steps at full size: state finite, inside the walls, momentum balanced."""
     require_gpu()
