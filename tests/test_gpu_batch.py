@@ -64,6 +64,32 @@ def test_batch_matches_fp64_oracle(orc, prec, tol):
         assert err <= tol
 
 
+def test_batch256_full_500_steps_sampled(orc):
+    """The 256-simulation batch (6.1M cells, FP32) at full size for its 500 steps: the
+    smallest, the largest and four drawn simulations against the FP64 oracle."""
+    require_gpu()
+    pops = workloads.batch()
+    cells, vox = _capacity(pops)
+    say("batch256 fp32 500 steps", cells, "cells")
+    with B.Batch(_params(B.MECH_FP32), cells, vox, len(pops)) as bt:
+        slots = [bt.admit_pop(pp, n_steps=pp.steps) for pp in pops]
+        bt.step(max(pp.steps for pp in pops))
+        B.batch_sync(bt)
+        assert set(bt.poll()) == set(slots)
+        sizes = [pp.n for pp in pops]
+        rng = np.random.default_rng(41)
+        pick = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)),
+                       *(int(k) for k in rng.choice(len(pops), 4, replace=False))})
+        got = {k: bt.read(slots[k])[0] for k in pick}
+    for k in pick:
+        pp = pops[k]
+        say("batch256 oracle sim", k, pp.n, "cells")
+        want = orc.run_pop(pp)["pos"]
+        err = pos_err(got[k], want, pp.half_width)
+        record(f"batch256 fp32 sim{k} ({pp.n} cells) {pp.steps} steps vs fp64 oracle", err)
+        assert err <= 1e-4, (k, err)
+
+
 def test_continuous_admission_and_repack():
     """A running, B admitted while A runs, A retired, C admitted into A's space."""
     require_gpu()
