@@ -131,6 +131,35 @@ def test_fp32_first_step_decisions_exact(orc, precision):
     assert np.abs(got["vel"] - want["vprev"]).max() <= 2e-5 * scale
 
 
+def test_kahan_compensation_is_live(orc):
+    """The compensated sums are not compiled away: on a pile of cells with about 170
+    neighbours each, FP32 + Kahan differs from the plain FP32 sums, and both stay as
+    close to the FP64 oracle as the oracle's own float variants (the errors are
+    recorded; rounding the positions to float dominates them at this size)."""
+    require_gpu()
+    rng = np.random.default_rng(27)
+    # a dense pile: 4000 cells in a 60 um ball, deep in each other's repulsion range
+    n = 4000
+    d = rng.normal(size=(n, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    pos = d * (60.0 * rng.uniform(0, 1, (n, 1)) ** (1 / 3))
+    pop = workloads.Population(name="pile4k", pos=pos, radius=np.full(n, 8.4), type=np.zeros(n, np.int32),
+                               lo=(-200.0, -200.0, -200.0), hi=(200.0, 200.0, 200.0),
+                               c_adh=workloads.C_ADH_1, steps=1)
+    say("kahan pile")
+    plain = run_gpu(pop, 1, precision=B.MECH_FP32)["vel"]
+    comp = run_gpu(pop, 1, precision=B.MECH_FP32_KAHAN)["vel"]
+    exact = orc.run_pop(pop, steps=1)["vprev"]
+    o_plain = orc.run_pop(pop, steps=1, precision=orc.FP32)["vprev"]
+    o_comp = orc.run_pop(pop, steps=1, precision=orc.FP32_KAHAN)["vprev"]
+    assert not np.array_equal(plain, comp)
+    err = lambda v: float(np.abs(v - exact).max())
+    assert err(comp) <= 2 * err(o_comp) + 1e-6 * np.abs(exact).max()
+    assert err(plain) <= 2 * err(o_plain) + 1e-6 * np.abs(exact).max()
+    record("kahan pile4k step-1 velocity max error, fp32 / fp32k / oracle fp32 / oracle fp32k",
+           err(plain), fp32k=err(comp), oracle_fp32=err(o_plain), oracle_fp32k=err(o_comp))
+
+
 def test_tumour1m_first_step_sampled(orc):
     """The 1M-cell tumour in FP32 + Kahan at full size: first-step velocities of sampled
     cells (each computed alone by the oracle) and the exact interaction count."""
