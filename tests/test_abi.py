@@ -217,3 +217,15 @@ def test_plain_c_client(tmp_path):
     res = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
     assert res.returncode == 0, res.stdout + res.stderr
     assert "client ok" in res.stdout
+
+
+def test_no_device_is_reported_as_a_device_error():
+    """Without a GPU, creation fails with MECH_E_DEVICE and a message (no crash, no CPU
+    fallback)."""
+    if B.lib().mech_device_count() > 0:
+        pytest.skip("a GPU is present")
+    pop = workloads.plain(50, seed=4)
+    with pytest.raises(B.MechError) as e:
+        B.create_population(B.params_of(pop), pop.pos, pop.radius, pop.type)
+    assert e.value.code == B.MECH_E_DEVICE
+    assert "device" in B.mech_last_error().lower()
