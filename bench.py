@@ -340,6 +340,9 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sims", type=int, default=256, help="batch workload: simulations")
+    ap.add_argument("--cells", type=int, default=0,
+                    help="tumour workload with this many cells at the 1M-cell tumour's density "
+                         "(core and cube scaled by (cells / 1e6)^(1/3)); a scaling study")
     ap.add_argument("--force", default="cells",
                     help="force kernel when not tuned: cells | rows | voxel")
     ap.add_argument("--no-tune", dest="tune", action="store_false",
@@ -379,7 +382,11 @@ def main():
 
     precision = args.precision or {"tumour1m": "fp32k", "sph100k": "fp64",
                                    "plain1k": "fp64"}[args.workload]
-    pop = workloads.config(args.workload)
+    if args.cells and args.workload == "tumour1m":
+        f = (args.cells / 1e6) ** (1.0 / 3.0)
+        pop = workloads.tumour(args.cells, core_radius=600.0 * f, half=1000.0 * f)
+    else:
+        pop = workloads.config(args.workload)
     prm = B.params_of(pop, B.PRECISIONS[precision], flags=B.FORCE_KERNELS[args.force])
     log(f"workload {pop.name} n={pop.n} precision={precision} steps={args.steps} "
         f"warmup={args.warmup}")
