@@ -1026,6 +1026,30 @@ __device__ __forceinline__ void hold(const ForceArgs<VPT>& a, uint32_t i)
     for (int c = 0; c < 3; ++c) a.X[c][i] = a.XS[c][i];
 }
 
+// 1/sqrt(x) and 1/x in FP64 from the hardware estimates (about 24 correct bits) and two
+// Newton steps each: measured on gfx950 within 1.8 ulp (rsqrt), 2.2 ulp (x * rsqrt(x)
+// as sqrt) and 0.5 ulp (reciprocal) of the exact values over 2^-12 .. 2^12.  They
+// replace the correctly rounded square root and three divisions of the pair term; the
+// in-range decision is on d2 and is unchanged.
+__device__ __forceinline__ double rsqrt_nr(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+    y = y * fma(-h * y, y, 1.5);
+    y = y * fma(-h * y, y, 1.5);
+    return y;
+}
+
+__device__ __forceinline__ double rcp_nr(double x)
+{
+    double y = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    return y;
+}
+
 // FP64 pair term.  d2 and the in-range test are evaluated without contraction so the
 // decision is the exact IEEE result of d2 = dx*dx + dy*dy + dz*dz < (alpha (ri+rj))^2.
 __device__ __forceinline__ bool pair64(double xi, double yi, double zi, double ri, double xj,
@@ -1044,15 +1068,16 @@ __device__ __forceinline__ bool pair64(double xi, double yi, double zi, double r
         RA = alpha * R;
         if (!(d2 > 0.0 && d2 < RA * RA)) return false;
     }
-    double d = sqrt(d2);
+    const double inv_d = rsqrt_nr(d2);
+    const double d = d2 * inv_d;
     double w = 0.0;
     if (d < R) {
-        double u = 1.0 - d / R;
+        double u = 1.0 - d * rcp_nr(R);
         w = c_rep * u * u;
     }
-    double a = 1.0 - d / RA;
+    double a = 1.0 - d * rcp_nr(RA);
     w -= cadh * a * a;
-    double s = w / d;
+    double s = w * inv_d;
     ax += s * dx;
     ay += s * dy;
     az += s * dz;
