@@ -376,7 +376,8 @@ __global__ __launch_bounds__(BLOCK) void k_scan_down(uint32_t* __restrict__ coun
                                                      uint32_t* __restrict__ voxel_start,
                                                      uint32_t* __restrict__ occ)
 {
-    __shared__ uint32_t tile[SCAN_TILE];
+    static_assert(SCAN_PER_THREAD == 8, "a thread's bins are read and written as two uint4");
+    __shared__ __align__(16) uint32_t tile[SCAN_TILE];
     __shared__ uint64_t sh[BLOCK / WAVE];
     const uint32_t S = XSUB * hdr[H_VOXELS];
     const uint32_t nt = (S + SCAN_TILE - 1) / SCAN_TILE;
@@ -401,7 +402,13 @@ __global__ __launch_bounds__(BLOCK) void k_scan_down(uint32_t* __restrict__ coun
         }
         __syncthreads();
         // each thread holds whole voxels: bins t*SCAN_PER_THREAD + k
-        const uint32_t* mine = tile + threadIdx.x * SCAN_PER_THREAD;
+        uint32_t mine[SCAN_PER_THREAD];
+        {
+            const uint4 m0 = *reinterpret_cast<const uint4*>(tile + threadIdx.x * SCAN_PER_THREAD);
+            const uint4 m1 = *reinterpret_cast<const uint4*>(tile + threadIdx.x * SCAN_PER_THREAD + 4);
+            mine[0] = m0.x; mine[1] = m0.y; mine[2] = m0.z; mine[3] = m0.w;
+            mine[4] = m1.x; mine[5] = m1.y; mine[6] = m1.z; mine[7] = m1.w;
+        }
         uint64_t loc[SCAN_PER_THREAD];
         bool first_occ[SCAN_PER_THREAD];
         uint64_t sum = 0;
@@ -426,13 +433,28 @@ __global__ __launch_bounds__(BLOCK) void k_scan_down(uint32_t* __restrict__ coun
                 hdr[H_OCC] = (uint32_t)((off0 + tot) >> 32);
             }
         }
+        const uint32_t v0 = base + threadIdx.x * SCAN_PER_THREAD;
+        if (v0 + SCAN_PER_THREAD <= S) {
+            // whole: two 16-byte stores (v0 is a multiple of 8 and the array 256-byte aligned)
+            uint32_t ev[SCAN_PER_THREAD];
 #pragma unroll
-        for (int k = 0; k < SCAN_PER_THREAD; ++k) {
-            uint32_t v = base + threadIdx.x * SCAN_PER_THREAD + k;
-            if (v < S) {
-                uint64_t e = off + loc[k];
-                voxel_start[v] = (uint32_t)e;
-                if (first_occ[k]) occ[(uint32_t)(e >> 32)] = v / XSUB;
+            for (int k = 0; k < SCAN_PER_THREAD; ++k) {
+                const uint64_t e = off + loc[k];
+                ev[k] = (uint32_t)e;
+                if (first_occ[k]) occ[(uint32_t)(e >> 32)] = (v0 + k) / XSUB;
+            }
+            uint4* dst = reinterpret_cast<uint4*>(voxel_start + v0);
+            dst[0] = make_uint4(ev[0], ev[1], ev[2], ev[3]);
+            dst[1] = make_uint4(ev[4], ev[5], ev[6], ev[7]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < SCAN_PER_THREAD; ++k) {
+                uint32_t v = v0 + k;
+                if (v < S) {
+                    uint64_t e = off + loc[k];
+                    voxel_start[v] = (uint32_t)e;
+                    if (first_occ[k]) occ[(uint32_t)(e >> 32)] = v / XSUB;
+                }
             }
         }
         // the histogram of the next step starts from zero (empty bins already are: most
