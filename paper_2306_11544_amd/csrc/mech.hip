@@ -3,18 +3,19 @@
 // One step, all on the device, on the batch's stream:
 //   k_bin          a1+a2  storage bin of every cell (its voxel, cut into XSUB slabs along x;
 //                         FP64 key) and an integer-atomic histogram, one atomic per run of
-//                         equal bins in a wave
+//                         equal bins in a wave; its first workgroup also does the step's
+//                         per-simulation bookkeeping (step counters, Euler start)
 //   k_scan_reduce  a3     per-tile sums of (count, occupied voxels) packed in 64 bits
 //   k_scan_top            exclusive scan of the tile sums (one workgroup; on grids of at
 //                         most FUSED_SCAN_TILES tiles k_scan_down adds them up itself)
 //   k_scan_down           bin starts (exclusive prefix), occupied-voxel list, count reset
 //   k_scatter      a4     cells into their bin's segment (arbitrary order inside it)
 //   k_rank_gather  a4+a5  rank inside the bin by ascending id -> final slot; gather of the
-//                         cell state into that order (+ the float shadow)
+//                         cell state into that order (+ the float and quantised shadows)
 //   k_force_*      a6+a7  27-voxel neighbour forces -> velocity, Adams-Bashforth, walls
 //   k_div_*               growing populations only: division after the walls
 //   k_die_*               dying populations only: death after division
-//   k_step_end            per-simulation step counters
+//   k_step_end            the bookkeeping alone, for a step without cells
 // The paper measures the mechanics "update velocity" loop as the region that degrades
 // when cells sit in memory in creation order rather than next to their neighbours in
 // space (Section 5.4); here every step re-sorts cells by voxel, so the force kernel
@@ -104,6 +105,7 @@ static_assert(SCAN_PER_THREAD % XSUB == 0 && SCAN_TILE % XSUB == 0, "scan tiles 
 constexpr int H_CELLS = 0, H_VOXELS = 1, H_OCC = 2;
 constexpr int H_STEP = 3;    // steps taken since creation (division draws)
 constexpr int H_DIV = 4;     // cells that drew a division this step
+constexpr int H_STEP_NOW = 5;  // the running step's index (H_STEP before it began)
 constexpr int HDR_WORDS = 8;
 
 // ------------------------------------------------------------------------ kernel args
@@ -121,6 +123,9 @@ struct SlotDesc {
     uint32_t n_cells;          // 0 marks a retired slot during a repack
     int32_t steps_left;        // > 0 steps to run, < 0 no limit, 0 frozen
     int32_t euler;             // the next step takes v_prev = v
+    int32_t active_now;        // the running step advances the slot (steps_left was not 0)
+    int32_t euler_now;         // the running step takes v_prev = v
+    int32_t pad_[2];
     float q_scale;             // units per um of the quantised shadow: a power of two, h q_scale <= 2^13
     float q_pad;               // extra prefilter margin in units for float positions
 };
@@ -232,16 +237,40 @@ __device__ __forceinline__ void wave_sync()
 // take consecutive offsets from the value it gets back.  Which cell of a bin gets which
 // offset does not matter: a4 orders each bin's cells by id.  vid receives the global
 // bin (XSUB * voxel_off + bin_key).
+// The step's bookkeeping, done by the step's first kernel before any other reads it:
+// whether each slot advances in this step and with which start of Adams-Bashforth, then
+// its counters for the next step; and the step index.  (A step without cells runs
+// k_step_end instead.)  `threads` threads starting at thread 0 of one workgroup.
+__device__ __forceinline__ void begin_step(SlotDesc* slots, uint32_t n_slots, uint32_t* hdr, uint32_t tid,
+                                           uint32_t threads)
+{
+    for (uint32_t t = tid; t < n_slots; t += threads) {
+        SlotDesc& d = slots[t];
+        const int32_t left = d.steps_left;
+        d.active_now = left != 0 ? 1 : 0;
+        d.euler_now = d.euler;
+        if (left > 0) d.steps_left = left - 1;
+        d.euler = 0;
+    }
+    if (tid == 0) {
+        const uint32_t step = hdr[H_STEP];
+        hdr[H_STEP_NOW] = step;
+        hdr[H_STEP] = step + 1u;
+    }
+}
+
 __global__ __launch_bounds__(BLOCK) void k_bin(const double* __restrict__ px,
                                                const double* __restrict__ py,
                                                const double* __restrict__ pz,
                                                const uint32_t* __restrict__ slot_of,
-                                               const SlotDesc* __restrict__ slots,
-                                               const uint32_t* __restrict__ hdr,
+                                               SlotDesc* __restrict__ slots,
+                                               uint32_t* __restrict__ hdr,
                                                uint32_t* __restrict__ count,
                                                uint32_t* __restrict__ vid,
-                                               uint32_t* __restrict__ off)
+                                               uint32_t* __restrict__ off,
+                                               uint32_t n_slots, int step_start)
 {
+    if (step_start && blockIdx.x == 0) begin_step(slots, n_slots, hdr, threadIdx.x, BLOCK);
     const uint32_t n = hdr[H_CELLS];
     const uint32_t lane = threadIdx.x & (WAVE - 1);
     const uint64_t le = lane == WAVE - 1 ? ~0ull : (2ull << lane) - 1ull;  // lanes <= this one
@@ -554,13 +583,15 @@ static_assert(SMALL_BINS / SMALL_BLOCK == SMALL_PER_THREAD && SMALL_PER_THREAD %
 
 template <typename VPT>
 __global__ __launch_bounds__(SMALL_BLOCK) void k_bin_small(const uint32_t* __restrict__ slot_of,
-                                                     const SlotDesc* __restrict__ slots,
+                                                     SlotDesc* __restrict__ slots,
                                                      uint32_t* __restrict__ hdr,
                                                      const uint32_t* __restrict__ id_cur,
                                                      uint32_t* __restrict__ vid_cur,
                                                      uint32_t* __restrict__ bin_start,
-                                                     uint32_t* __restrict__ occ, GatherArgs<VPT> a)
+                                                     uint32_t* __restrict__ occ, GatherArgs<VPT> a,
+                                                     uint32_t n_slots, int step_start)
 {
+    if (step_start) begin_step(slots, n_slots, hdr, threadIdx.x, SMALL_BLOCK);
     __shared__ uint32_t s_start[SMALL_BINS + 1];   // counts, then bin starts
     __shared__ uint32_t s_key[SMALL_CELLS];
     __shared__ uint32_t s_src[SMALL_CELLS];
@@ -791,7 +822,7 @@ struct DivArgs {
 
 __global__ __launch_bounds__(BLOCK) void k_div_mark(DivArgs a)
 {
-    const uint32_t n = a.hdr[H_CELLS], t = a.hdr[H_STEP];
+    const uint32_t n = a.hdr[H_CELLS], t = a.hdr[H_STEP_NOW];
     for (uint32_t s = blockIdx.x * BLOCK + threadIdx.x; s < n; s += gridDim.x * BLOCK) {
         const uint32_t id = a.ID[s];
         a.flag[id] = division_draw(a.seed, id, t, 0) < a.p_div ? 1u : 0u;
@@ -867,7 +898,7 @@ __global__ __launch_bounds__(BLOCK) void k_div_scan_down(DivArgs a)
 // parent and daughter move by -/+ r/2 along the drawn direction, through the walls.
 __global__ __launch_bounds__(BLOCK) void k_div_apply(DivArgs a)
 {
-    const uint32_t n = a.hdr[H_CELLS], t = a.hdr[H_STEP];
+    const uint32_t n = a.hdr[H_CELLS], t = a.hdr[H_STEP_NOW];
     const uint32_t room = a.capacity - n;
     for (uint32_t s = blockIdx.x * BLOCK + threadIdx.x; s < n; s += gridDim.x * BLOCK) {
         const uint32_t id = a.ID[s];
@@ -935,7 +966,7 @@ __device__ __forceinline__ bool dies(const DivArgs& a, uint32_t id, uint32_t t)
 
 __global__ __launch_bounds__(BLOCK) void k_die_mark(DivArgs a)
 {
-    const uint32_t n = a.hdr[H_CELLS], t = a.hdr[H_STEP];
+    const uint32_t n = a.hdr[H_CELLS], t = a.hdr[H_STEP_NOW];
     for (uint32_t s = blockIdx.x * BLOCK + threadIdx.x; s < n; s += gridDim.x * BLOCK) {
         const uint32_t id = a.ID[s];
         a.flag[id] = dies(a, id, t) ? 0u : 1u;
@@ -944,7 +975,7 @@ __global__ __launch_bounds__(BLOCK) void k_die_mark(DivArgs a)
 
 __global__ __launch_bounds__(BLOCK) void k_die_move(DivArgs a)
 {
-    const uint32_t n = a.hdr[H_CELLS], t = a.hdr[H_STEP];
+    const uint32_t n = a.hdr[H_CELLS], t = a.hdr[H_STEP_NOW];
     for (uint32_t s = blockIdx.x * BLOCK + threadIdx.x; s < n; s += gridDim.x * BLOCK) {
         const uint32_t id = a.ID[s];
         if (dies(a, id, t)) continue;
@@ -1032,7 +1063,7 @@ __device__ __forceinline__ void integrate(const ForceArgs<VPT>& a, const PhysArg
 {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        const double vp = d.euler ? v[c] : (double)a.VP[c][i];
+        const double vp = d.euler_now ? v[c] : (double)a.VP[c][i];
         const double xn = a.XS[c][i] + P.dt * (1.5 * v[c] - 0.5 * vp);
         a.X[c][i] = reflect(xn, d.lo[c], d.hi[c]);
         a.VP[c][i] = (VPT)v[c];
@@ -1221,7 +1252,7 @@ __device__ __forceinline__ void force_rows_cell(const PhysArgs& P, const ForceAr
 {
     {
         const SlotDesc& d = a.slots[a.slot_of[i]];
-        if (d.steps_left == 0) {
+        if (!d.active_now) {
             hold(a, i);
         } else {
             const Cellgeo g = cell_geo(a.vid_sorted[i] / XSUB, d);
@@ -1320,7 +1351,7 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
     const bool in_pop = i < n;
     const uint32_t ii = in_pop ? i : n - 1;  // idle lanes mirror the last cell
     const SlotDesc& d = a.slots[a.slot_of[ii]];
-    const bool valid = in_pop && d.steps_left != 0;
+    const bool valid = in_pop && d.active_now != 0;
     const Cellgeo g = cell_geo(a.vid_sorted[ii] / XSUB, d);
     // The x slabs of each neighbour row that can hold a partner: every interacting j has
     // |x_j - x_i| < alpha (r_i + r_max).  The window is taken in FP64 from the exact
@@ -1615,7 +1646,7 @@ __global__ __launch_bounds__(FL_WAVES * WAVE) void k_force_lds(PhysArgs P, Force
         const uint32_t vox = __builtin_amdgcn_readfirstlane(occ[o]);
         const uint32_t vb = a.voxel_start[XSUB * vox], k = a.voxel_start[XSUB * vox + XSUB] - vb;
         const SlotDesc& d = a.slots[__builtin_amdgcn_readfirstlane(a.slot_of[vb])];
-        if (d.steps_left == 0) {
+        if (!d.active_now) {
             for (uint32_t t = lane; t < k; t += WAVE) hold(a, vb + t);
             continue;
         }
@@ -2022,6 +2053,7 @@ struct MechBatch {
     double p_div = 0.0;
     uint64_t div_seed = 0;
     double p_death = 0.0;                 // dying populations: death probability per step
+    bool step_start = false;              // the binning being enqueued starts a step
     bool growing = false;                 // the device may hold more cells than the host mirror
     int64_t reorder_phase = 0;            // steps since the mode was set
     bool last_gather = true;              // the last binning reordered the cells
@@ -2064,8 +2096,9 @@ void enqueue_keys(MechBatch* B)
     const uint32_t* hdr = B->at<uint32_t>(L.hdr);
     hipLaunchKernelGGL(k_bin, dim3(nbc), dim3(BLOCK), 0, B->stream, B->at<double>(L.X[0]),
                        B->at<double>(L.X[1]), B->at<double>(L.X[2]), B->at<uint32_t>(L.slot_of),
-                       B->at<SlotDesc>(L.slots), hdr, B->at<uint32_t>(L.count), B->at<uint32_t>(L.vid_cur),
-                       B->at<uint32_t>(L.off));
+                       B->at<SlotDesc>(L.slots), B->at<uint32_t>(L.hdr), B->at<uint32_t>(L.count),
+                       B->at<uint32_t>(L.vid_cur), B->at<uint32_t>(L.off), (uint32_t)B->cap_slots,
+                       B->step_start ? 1 : 0);
     hipLaunchKernelGGL(k_scan_reduce, dim3(nbt), dim3(BLOCK), 0, B->stream, B->at<uint32_t>(L.count), hdr,
                        B->at<uint64_t>(L.tsum));
     if (blocks_for((uint64_t)B->cap_voxels * XSUB, SCAN_TILE) <= FUSED_SCAN_TILES) {
@@ -2124,7 +2157,8 @@ void enqueue_binning(MechBatch* B)
     if (small_binning(B))
         hipLaunchKernelGGL(k_bin_small<VPT>, dim3(1), dim3(SMALL_BLOCK), 0, B->stream, B->at<uint32_t>(L.slot_of),
                            B->at<SlotDesc>(L.slots), B->at<uint32_t>(L.hdr), B->at<uint32_t>(L.ID[cur]),
-                           B->at<uint32_t>(L.vid_cur), B->at<uint32_t>(L.start), B->at<uint32_t>(L.occ), g);
+                           B->at<uint32_t>(L.vid_cur), B->at<uint32_t>(L.start), B->at<uint32_t>(L.occ), g,
+                           (uint32_t)B->cap_slots, B->step_start ? 1 : 0);
     else
         hipLaunchKernelGGL(k_rank_gather<VPT>, dim3(nbc), dim3(BLOCK), 0, B->stream, hdr, g);
 }
@@ -2408,16 +2442,18 @@ void enqueue_step(MechBatch* B, int parity, bool gather = true)
 {
     const int saved = B->parity;
     B->parity = parity;
+    B->step_start = true;   // the first binning kernel does the step's bookkeeping
     if (gather) {
         enqueue_binning_any(B);
+        B->step_start = false;
         enqueue_force_any(B, parity ^ 1);
     } else {
         enqueue_binning_inplace(B);
+        B->step_start = false;
         enqueue_force_inplace_any(B);
     }
     enqueue_division(B, gather ? parity ^ 1 : parity);
     enqueue_death(B, gather ? parity ^ 1 : parity);
-    enqueue_step_end(B);
     B->parity = saved;
 }
 
@@ -2954,10 +2990,12 @@ int profile_impl(MechBatch* B, int64_t n_steps, double* phase_ms)
         const int p = B->parity;
         const bool gather = gather_now(B);
         (void)hipEventRecord(ev[0], B->stream);
+        B->step_start = true;
         if (gather)
             enqueue_binning_any(B);
         else
             enqueue_binning_inplace(B);
+        B->step_start = false;
         (void)hipEventRecord(ev[1], B->stream);
         if (gather)
             enqueue_force_any(B, p ^ 1);
@@ -2966,7 +3004,6 @@ int profile_impl(MechBatch* B, int64_t n_steps, double* phase_ms)
         (void)hipEventRecord(ev[2], B->stream);
         enqueue_division(B, gather ? p ^ 1 : p);
         enqueue_death(B, gather ? p ^ 1 : p);
-        enqueue_step_end(B);
         rc = after_step(B, gather);
         if (rc == MECH_OK) rc = sync_check(B);
         float t0 = 0.f, t1 = 0.f;
