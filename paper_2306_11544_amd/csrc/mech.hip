@@ -134,7 +134,7 @@ static_assert(sizeof(SlotDesc) % 16 == 0, "SlotDesc alignment");
 // Physics shared by the slots of a batch.
 struct PhysArgs {
     double dt, c_rep, alpha, c_adh0;
-    float c_rep_f, alpha_f, c_adh0_f, pad_;
+    float c_rep_f, alpha_f, c_adh0_f, inv_alpha_f;   // inv_alpha_f = fl(1 / alpha_f)
     int32_t n_types, pad2_;
 };
 
@@ -311,20 +311,23 @@ __global__ __launch_bounds__(BLOCK) void k_scan_reduce(const uint32_t* __restric
                                                        const uint32_t* __restrict__ hdr,
                                                        uint64_t* __restrict__ tsum)
 {
+    static_assert(XSUB == 4, "a voxel's bins are read as one uint4");
     __shared__ uint64_t sh[BLOCK / WAVE];
-    const uint32_t S = XSUB * hdr[H_VOXELS];
+    const uint32_t V = hdr[H_VOXELS];
+    const uint32_t S = XSUB * V;
     const uint32_t nt = (S + SCAN_TILE - 1) / SCAN_TILE;
+    const uint4* count4 = reinterpret_cast<const uint4*>(count);   // one voxel per uint4
     for (uint32_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
-        const uint32_t base = tile * SCAN_TILE;
+        const uint32_t base = tile * (SCAN_TILE / XSUB);
         uint64_t acc = 0;
 #pragma unroll
-        for (int k = 0; k < SCAN_PER_THREAD; ++k) {
+        for (int k = 0; k < SCAN_PER_THREAD / XSUB; ++k) {
             const uint32_t v = base + k * BLOCK + threadIdx.x;
-            const uint32_t c = v < S ? count[v] : 0u;
-            // the XSUB bins of a voxel are read by XSUB adjacent lanes
-            uint32_t any = c;
-            for (uint32_t o = 1; o < XSUB; o <<= 1) any |= __shfl_xor(any, (int)o, WAVE);
-            acc += (uint64_t)c | ((uint64_t)((threadIdx.x % XSUB) == 0 && any != 0u) << 32);
+            if (v < V) {
+                const uint4 q = count4[v];
+                const uint32_t c = q.x + q.y + q.z + q.w;
+                acc += (uint64_t)c | ((uint64_t)((q.x | q.y | q.z | q.w) != 0u) << 32);
+            }
         }
         acc = wave_sum(acc);
         if ((threadIdx.x & (WAVE - 1)) == 0) sh[threadIdx.x / WAVE] = acc;
@@ -1138,11 +1141,13 @@ __device__ __forceinline__ bool pair64(double xi, double yi, double zi, double r
 }
 
 // FP32 pair term on the float shadow: same decision as the float oracle
-// (d2 by two fused multiply-adds, R and R_A rounded to float).
+// (d2 by two fused multiply-adds, R and R_A rounded to float).  1/d from the hardware
+// reciprocal square root, 1/R from the hardware reciprocal, and 1/R_A as
+// (1/R) fl(1/alpha): one transcendental fewer per pair than 1/R_A of its own.
 template <bool KAHAN>
 __device__ __forceinline__ bool pair32(float xi, float yi, float zi, float ri, float4 q,
                                        float alpha, float c_rep, float cadh, float* acc,
-                                       float* cmp)
+                                       float* cmp, float inv_alpha)
 {
     float dx, dy, dz, d2, R, RA;
     {
@@ -1157,12 +1162,13 @@ __device__ __forceinline__ bool pair32(float xi, float yi, float zi, float ri, f
     }
     float inv_d = __builtin_amdgcn_rsqf(d2);
     float d = d2 * inv_d;
+    const float inv_R = __builtin_amdgcn_rcpf(R);
     float w = 0.0f;
     if (d < R) {
-        float u = 1.0f - d * __builtin_amdgcn_rcpf(R);
+        float u = 1.0f - d * inv_R;
         w = c_rep * u * u;
     }
-    float a = 1.0f - d * __builtin_amdgcn_rcpf(RA);
+    float a = 1.0f - d * (inv_R * inv_alpha);
     w -= cadh * a * a;
     float s = w * inv_d;
     float t[3] = {s * dx, s * dy, s * dz};
@@ -1289,7 +1295,7 @@ __device__ __forceinline__ void force_rows_cell(const PhysArgs& P, const ForceAr
                     for (uint32_t j = b; j < e; ++j) {
                         const float c = MULTI ? a.cadh_f[ti * P.n_types + a.T[j]] : P.c_adh0_f;
                         inter += pair32<PREC == 2>(me.x, me.y, me.z, me.w, a.SH[j], P.alpha_f,
-                                                   P.c_rep_f, c, acc, cmp);
+                                                   P.c_rep_f, c, acc, cmp, P.inv_alpha_f);
                     }
                 }
 #pragma unroll
@@ -1470,7 +1476,7 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
         } else {
             const float cadh = MULTI ? a.cadh_f[ti * P.n_types + c.t] : P.c_adh0_f;
             inter += pair32<PREC == 2>(xi, yi, zi, ri, make_float4(c.x, c.y, c.z, c.r), P.alpha_f, P.c_rep_f,
-                                       cadh, acc, cmp);
+                                       cadh, acc, cmp, P.inv_alpha_f);
         }
     };
     // The ring evaluates in every lane the candidates of its oldest entries, one per pass
@@ -1695,7 +1701,8 @@ __global__ __launch_bounds__(FL_WAVES * WAVE) void k_force_lds(PhysArgs P, Force
                                    acc[0], acc[1], acc[2]);
                         } else {
                             const float cadh = MULTI ? a.cadh_f[ti * P.n_types + s_type[w][m]] : P.c_adh0_f;
-                            pair32<PREC == 2>(me.x, me.y, me.z, me.w, c, P.alpha_f, P.c_rep_f, cadh, acc, cmp);
+                            pair32<PREC == 2>(me.x, me.y, me.z, me.w, c, P.alpha_f, P.c_rep_f, cadh, acc, cmp,
+                                              P.inv_alpha_f);
                         }
                     }
                 }
@@ -2573,6 +2580,7 @@ int create_batch_impl(const MechParams* params, int64_t max_cells, int64_t max_v
     B->phys.c_adh0 = params->c_adh[0];
     B->phys.c_rep_f = (float)params->c_rep;
     B->phys.alpha_f = (float)params->rel_adh_distance;
+    B->phys.inv_alpha_f = 1.0f / B->phys.alpha_f;
     B->phys.c_adh0_f = (float)params->c_adh[0];
     B->phys.n_types = params->n_types;
     B->L = make_layout(*params, max_cells, (uint64_t)max_voxels, max_slots);
