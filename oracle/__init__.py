@@ -14,8 +14,11 @@ Parity status of each function (what pins it is listed in tests/test_oracle_*.py
   velocity_voxel     pinned: equals all-pairs (pair set exactly, sums to 1e-13)
   run / integrate    pinned: two-cell closed-form trajectories, exact AB2 recurrence
                      in 50-digit arithmetic, reflecting-wall special cases
-  FP32 variants      pinned: decisions equal FP64 on well-separated pairs; Kahan sum
-                     within the textbook compensated-summation bound of math.fsum
+  FP32 variants      pinned: the float in-range decision equals numpy's per-operation
+                     float32 evaluation of the written expression on pairs within a
+                     few ulps of their cutoff; decisions equal FP64 on well-separated
+                     pairs; the Kahan sum within the textbook compensated-summation
+                     bound of math.fsum
   velocity_sampled   pinned: equals velocity_voxel on the sampled cells
   splitmix64         pinned: the generator's published reference outputs (tests/golden)
   uniform / divide / pinned: uniformity, selection by the draws, ranks and ids, parent and

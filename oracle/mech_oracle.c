@@ -10,16 +10,13 @@
  *      Voxels are numbered x fastest: vid = kx + nx*(ky + ny*kz).  The paper's
  *      voxel-parallel update walks a linear container of mechanics voxels (Section 5.4,
  *      the voxel-based update-velocity listing); the x-fastest numbering is our reading.
- *   2. Binning: k_a = clamp(floor((x_a - lo_a) * (1/h)), 0, n_a - 1); cells are listed
- *      voxel by voxel, ascending voxel id.  Inside a voxel they are listed by x slab,
- *      s = clamp(floor((x - lo_x) * (1/h) * 4), 0, 4 n_x - 1) - 4 k_x (the voxel cut in
- *      four along x), then by ascending cell id.  The paper leaves the order inside a
- *      voxel open; this one keeps the cells within reach of each other along x
- *      contiguous.  Only occupied voxels are listed in `occ` (the paper's non-empty
- *      voxel list, Section 5.4).
+ *   2. Binning: k_a = clamp(floor((x_a - lo_a) * (1/h)), 0, n_a - 1); a counting sort
+ *      by voxel id, stable in cell id, lists the cells voxel by voxel (ascending voxel
+ *      id) and inside a voxel by ascending cell id.  Only occupied voxels are listed in
+ *      `occ` (the paper's non-empty voxel list, Section 5.4).
  *   3. Velocity (overdamped: velocity = sum of pair forces, unit mobility), gathered
  *      over the 27 voxels around the cell's own voxel, dz outermost, then dy, then dx,
- *      each voxel's cells in their binned order (slab, then id):
+ *      each voxel's cells by ascending id:
  *        delta = x_i - x_j, d2 = |delta|^2, R = r_i + r_j, R_A = alpha * R
  *        a pair interacts when 0 < d2 < R_A*R_A
  *        w = c_rep (1 - d/R)^2 [d < R]  -  C[t_i][t_j] (1 - d/R_A)^2
@@ -38,15 +35,15 @@
  * lessons: compute cells voxel by voxel in mesh order and skip empty voxels (Section
  * 5.4) -- which this oracle also follows, since it is the algorithm being checked.
  *
- * FP32 variant (an approximation; it fixes what the FP32 kernels compute): positions
- * and radii are rounded to float once per step, the pair arithmetic runs in float with
- * d2 = fma(dz, dz, fma(dy, dy, dx*dx)) (two fused multiply-adds, correctly rounded),
- * the force sum is plain float or Kahan-compensated per component (the compensated
- * result being sum - c, the running sum less its carried correction), and the update in
- * step 4 runs in double on the float velocity; v_prev holds the float velocity.
+ * FP32 variant (an approximation): positions and radii are rounded to float once per
+ * step and the pair arithmetic of step 3 runs in float, each operation of the written
+ * expressions rounded on its own (d2 = (dx*dx + dy*dy) + dz*dz, no fused forms); the
+ * force sum is plain float or Kahan-compensated per component (Kahan 1965; the result
+ * is the running sum, its correction term is not added back), and the update in step 4
+ * runs in double on the float velocity; v_prev holds the float velocity.
  *
- * Everything is compiled with -ffp-contract=off so that d2 and the in-range decision
- * are the exact IEEE results of the written expressions.
+ * Everything is compiled with -ffp-contract=off, so every result is the IEEE value of the
+ * expression as written.
  */
 #include <math.h>
 #include <stdint.h>
@@ -80,9 +77,8 @@ int32_t oracle_grid_dims(const OracleParams* p, int32_t dims[3])
     return 0;
 }
 
-/* Voxel id of a position; *slab receives its x slab inside the voxel (0..3). */
-static int64_t voxel_of(const OracleParams* p, const int32_t dims[3], double inv_h,
-                        const double* x, int* slab)
+/* Voxel id of a position. */
+static int64_t voxel_of(const OracleParams* p, const int32_t dims[3], double inv_h, const double* x)
 {
     int64_t k[3];
     for (int a = 0; a < 3; ++a) {
@@ -92,12 +88,6 @@ static int64_t voxel_of(const OracleParams* p, const int32_t dims[3], double inv
         if (ka > dims[a] - 1) ka = dims[a] - 1;
         k[a] = ka;
     }
-    double t = (x[0] - p->lo[0]) * inv_h;
-    double f4 = floor(t * 4.0);
-    int64_t s4 = (int64_t)f4;
-    if (f4 < 0.0) s4 = 0;
-    if (s4 > 4 * (int64_t)dims[0] - 1) s4 = 4 * (int64_t)dims[0] - 1;
-    *slab = (int)(s4 - 4 * k[0]);
     return k[0] + (int64_t)dims[0] * (k[1] + (int64_t)dims[1] * k[2]);
 }
 
@@ -110,24 +100,16 @@ int32_t oracle_bin(const OracleParams* p, int64_t n, const double* pos, uint32_t
     if (oracle_grid_dims(p, dims)) return -1;
     int64_t V = (int64_t)dims[0] * dims[1] * dims[2];
     double inv_h = 1.0 / p->h;
-    /* key = 4 * vid + slab orders by (voxel, slab) */
-    uint32_t* cursor = (uint32_t*)calloc(4 * (size_t)V + 1, sizeof(uint32_t));
-    uint32_t* key = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(n ? n : 1));
-    if (!cursor || !key) { free(cursor); free(key); return -2; }
-    for (int64_t i = 0; i < n; ++i) {
-        int slab;
-        vid[i] = (uint32_t)voxel_of(p, dims, inv_h, pos + 3 * i, &slab);
-        key[i] = 4u * vid[i] + (uint32_t)slab;
-    }
+    uint32_t* cursor = (uint32_t*)malloc(sizeof(uint32_t) * ((size_t)V + 1));
+    if (!cursor) return -2;
+    for (int64_t i = 0; i < n; ++i) vid[i] = (uint32_t)voxel_of(p, dims, inv_h, pos + 3 * i);
     /* counts per voxel, then exclusive prefix */
     memset(voxel_start, 0, sizeof(uint32_t) * ((size_t)V + 1));
     for (int64_t i = 0; i < n; ++i) voxel_start[vid[i] + 1] += 1;
     for (int64_t v = 0; v < V; ++v) voxel_start[v + 1] += voxel_start[v];
-    /* the same per key; a stable placement in ascending id order gives (key, id) order */
-    for (int64_t i = 0; i < n; ++i) cursor[key[i] + 1] += 1;
-    for (int64_t k = 0; k < 4 * V; ++k) cursor[k + 1] += cursor[k];
-    for (int64_t i = 0; i < n; ++i) sorted_ids[cursor[key[i]]++] = (uint32_t)i;
-    free(key);
+    /* placing the cells in ascending id order keeps each voxel's cells in id order */
+    memcpy(cursor, voxel_start, sizeof(uint32_t) * ((size_t)V + 1));
+    for (int64_t i = 0; i < n; ++i) sorted_ids[cursor[vid[i]]++] = (uint32_t)i;
     int64_t m = 0;
     for (int64_t v = 0; v < V; ++v)
         if (voxel_start[v + 1] > voxel_start[v]) occ[m++] = (uint32_t)v;
@@ -164,7 +146,8 @@ static int pair_f64(const OracleParams* p, const double* xi, double ri, int ti,
 
 typedef struct { float s[3], c[3]; } AccF;
 
-/* One step of a float sum: plain, or Kahan-compensated (c carries the lost low part). */
+/* One step of a float sum: plain, or Kahan-compensated (c carries the low part lost by
+ * the last addition, subtracted from the next term; the sum itself is the result). */
 static void accumulate_f32(float* sum, float* c, float term, int kahan)
 {
     if (kahan) {
@@ -182,7 +165,7 @@ static int pair_f32(const OracleParams* p, const float* xi, float ri, int ti,
                     const float* xj, float rj, int tj, AccF* acc, int kahan)
 {
     float dx = xi[0] - xj[0], dy = xi[1] - xj[1], dz = xi[2] - xj[2];
-    float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));   /* fused, as the float kernels */
+    float d2 = dx * dx + dy * dy + dz * dz;
     float R = ri + rj;
     float RA = (float)p->alpha * R;
     if (!(d2 > 0.0f && d2 < RA * RA)) return 0;
@@ -205,7 +188,7 @@ float oracle_sum_f32(const float* x, int64_t n, int32_t kahan)
 {
     float s = 0.0f, c = 0.0f;
     for (int64_t i = 0; i < n; ++i) accumulate_f32(&s, &c, x[i], kahan);
-    return s - c;
+    return s;
 }
 
 /* ------------------------------------------------------------------ velocities */
@@ -244,7 +227,7 @@ int32_t oracle_velocity_allpairs(const OracleParams* p, int64_t n, const double*
                 inter += pair_f32(p, pf + 3 * i, rf[i], ti, pf + 3 * j, rf[j],
                                   type ? type[j] : 0, &acc, precision == OR_FP32_KAHAN);
             }
-            for (int c = 0; c < 3; ++c) vel[3 * i + c] = (double)(acc.s[c] - acc.c[c]);
+            for (int c = 0; c < 3; ++c) vel[3 * i + c] = (double)acc.s[c];
         }
     }
     free(pf);
@@ -313,7 +296,7 @@ int32_t oracle_velocity_voxel(const OracleParams* p, int64_t n, const double* po
                     }
                 }
         for (int c = 0; c < 3; ++c)
-            vel[3 * i + c] = (precision == OR_FP64) ? acc[c] : (double)(accf.s[c] - accf.c[c]);
+            vel[3 * i + c] = (precision == OR_FP64) ? acc[c] : (double)accf.s[c];
     }
     if (interactions) *interactions = inter;
     if (candidates) *candidates = cand;
@@ -429,7 +412,7 @@ int32_t oracle_velocity_sampled(const OracleParams* p, int64_t n, const double* 
                     }
                 }
         for (int c = 0; c < 3; ++c)
-            vel[3 * k + c] = (precision == OR_FP64) ? acc[c] : (double)(accf.s[c] - accf.c[c]);
+            vel[3 * k + c] = (precision == OR_FP64) ? acc[c] : (double)accf.s[c];
     }
     if (interactions) *interactions = inter;
 done:

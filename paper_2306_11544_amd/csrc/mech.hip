@@ -1140,10 +1140,13 @@ __device__ __forceinline__ bool pair64(double xi, double yi, double zi, double r
     return true;
 }
 
-// FP32 pair term on the float shadow: same decision as the float oracle
-// (d2 by two fused multiply-adds, R and R_A rounded to float).  1/d from the hardware
-// reciprocal square root, 1/R from the hardware reciprocal, and 1/R_A as
-// (1/R) fl(1/alpha): one transcendental fewer per pair than 1/R_A of its own.
+// FP32 pair term on the float shadow.  The decision is the IEEE float result of the
+// written expressions, each operation rounded on its own (d2 = (dx*dx + dy*dy) + dz*dz,
+// R and R_A rounded to float; no fused forms).  1/d from the hardware reciprocal square
+// root, 1/R from the hardware reciprocal, and 1/R_A as (1/R) fl(1/alpha): one
+// transcendental fewer per pair than 1/R_A of its own.  With KAHAN the three sums are
+// Kahan-compensated (Kahan 1965): cmp carries the low part the last addition lost and is
+// taken off the next term; the running sum is the result.
 template <bool KAHAN>
 __device__ __forceinline__ bool pair32(float xi, float yi, float zi, float ri, float4 q,
                                        float alpha, float c_rep, float cadh, float* acc,
@@ -1155,7 +1158,7 @@ __device__ __forceinline__ bool pair32(float xi, float yi, float zi, float ri, f
         dx = xi - q.x;
         dy = yi - q.y;
         dz = zi - q.z;
-        d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
+        d2 = dx * dx + dy * dy + dz * dz;
         R = ri + q.w;
         RA = alpha * R;
         if (!(d2 > 0.0f && d2 < RA * RA)) return false;
@@ -1200,7 +1203,7 @@ __device__ __forceinline__ bool in_range32(const float4& me, const float4& c, fl
 {
 #pragma clang fp contract(off)
     const float dx = me.x - c.x, dy = me.y - c.y, dz = me.z - c.z;
-    const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
+    const float d2 = dx * dx + dy * dy + dz * dz;
     const float RA = alpha * (me.w + c.w);
     return d2 > 0.0f && d2 < RA * RA;
 }
@@ -1299,7 +1302,7 @@ __device__ __forceinline__ void force_rows_cell(const PhysArgs& P, const ForceAr
                     }
                 }
 #pragma unroll
-                for (int c = 0; c < 3; ++c) v[c] = (double)(acc[c] - cmp[c]);
+                for (int c = 0; c < 3; ++c) v[c] = (double)acc[c];
             }
             cand -= 1;  // the cell itself
             integrate(a, P, d, i, v);
@@ -1581,7 +1584,7 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
         cand -= 1;  // the cell itself
         double v[3];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) v[c] = (double)(acc[c] - cmp[c]);
+        for (int c = 0; c < 3; ++c) v[c] = (double)acc[c];
         integrate(a, P, d, i, v);
     } else if (in_pop) {
         hold(a, i);
@@ -1744,14 +1747,11 @@ __global__ __launch_bounds__(FL_WAVES * WAVE) void k_force_lds(PhysArgs P, Force
                 inter += cnt;
                 flush();
             }
-            // combine the slices of each target in slice order
+            // combine the slices' sums of each target in slice order
             wave_sync();
             Real* part = reinterpret_cast<Real*>(stage);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                part[lane * 6 + c] = acc[c];
-                part[lane * 6 + 3 + c] = cmp[c];
-            }
+            for (int c = 0; c < 3; ++c) part[lane * 3 + c] = acc[c];
             wave_sync();
             if (s == 0) {
                 Real tot[3] = {0, 0, 0}, tc[3] = {0, 0, 0};
@@ -1759,7 +1759,7 @@ __global__ __launch_bounds__(FL_WAVES * WAVE) void k_force_lds(PhysArgs P, Force
                     const uint32_t l = t + q * r;
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
-                        const Real term = part[l * 6 + c] - part[l * 6 + 3 + c];
+                        const Real term = part[l * 3 + c];
                         if (PREC == 2) {
                             const Real y = term - tc[c];
                             const Real tt = tot[c] + y;
@@ -1773,7 +1773,7 @@ __global__ __launch_bounds__(FL_WAVES * WAVE) void k_force_lds(PhysArgs P, Force
                 cand += C - 1;
                 double v[3];
 #pragma unroll
-                for (int c = 0; c < 3; ++c) v[c] = (double)(tot[c] - tc[c]);
+                for (int c = 0; c < 3; ++c) v[c] = (double)tot[c];
                 integrate(a, P, d, i, v);
             }
             wave_sync();

@@ -74,3 +74,35 @@ def pos_err(a, b, S):
     if a.size == 0:
         return 0.0
     return float(np.abs(a - b).max() / S)
+
+
+def storage_order(pos, lo, hi, h):
+    """The order the library stores cells in, computed with numpy: by voxel, then by x slab
+    (the voxel cut in four along x, slab floor((x - lo) * (1/h) * 4) - 4 kx, clamped like
+    the voxel index), then by id.  The voxel and the ids inside it are the method's; the
+    slab order is the library's own choice (it keeps a neighbour row's cells within reach
+    of a cell along x contiguous), so it is checked here and not by the oracle."""
+    pos = np.asarray(pos, dtype=np.float64).reshape(-1, 3)
+    lo = np.asarray(lo, float)
+    dims = np.maximum(1, np.ceil((np.asarray(hi, float) - lo) / h)).astype(np.int64)
+    k = np.clip(np.floor((pos - lo) * (1.0 / h)), 0, dims - 1).astype(np.int64)
+    vid = k[:, 0] + dims[0] * (k[:, 1] + dims[1] * k[:, 2])
+    s4 = np.clip(np.floor((pos[:, 0] - lo[0]) * (1.0 / h) * 4.0), 0, 4 * dims[0] - 1).astype(np.int64)
+    return np.lexsort((np.arange(len(pos)), s4 - 4 * k[:, 0], vid)).astype(np.uint32)
+
+
+def check_binning(got, want, pos, lo, hi, h):
+    """GPU binning (voxel_of_cell, voxel_start, sorted_ids, occ) against the oracle's:
+    voxel of every cell, voxel starts and the occupied list bit for bit; each voxel's
+    segment of the storage order holds exactly the oracle's cells of that voxel; and the
+    order inside it is the library's documented one (storage_order)."""
+    vid, start, ids, occ = got
+    wvid, wstart, wids, wocc = want
+    for name, g, w in (("voxel_of_cell", vid, wvid), ("voxel_start", start, wstart), ("occ", occ, wocc)):
+        assert g.dtype == np.uint32 and g.shape == w.shape, name
+        assert np.array_equal(g, w), name
+    assert ids.dtype == np.uint32 and ids.shape == wids.shape
+    V = len(start) - 1
+    assert np.array_equal(vid[ids], np.repeat(np.arange(V, dtype=np.uint32), np.diff(start.astype(np.int64))))
+    assert np.array_equal(ids[np.lexsort((ids, vid[ids]))], wids)
+    assert np.array_equal(ids, storage_order(pos, lo, hi, h))

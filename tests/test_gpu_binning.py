@@ -1,4 +1,6 @@
-"""Binning on the GPU (a1-a5) is bit-exact against the oracle.
+"""Binning on the GPU (a1-a5) is bit-exact against the oracle: voxel of every cell, voxel
+starts, occupied list, and the cells of each voxel; the order inside a voxel is checked
+against the library's documented storage order.
 
 Compared at creation, where both sides bin the same seeded positions: the three
 single-simulation workloads at full size (1k, 100k, 1M cells), positions the oracle
@@ -8,7 +10,7 @@ import numpy as np
 import pytest
 
 import workloads
-from gpu_helpers import require_gpu, say
+from gpu_helpers import check_binning, require_gpu, say
 from paper_2306_11544_amd import binding as B
 
 pytestmark = pytest.mark.gpu
@@ -19,10 +21,7 @@ def _compare(orc, pop, precision=B.MECH_FP64):
     want = orc.bin(orc.params_of(pop), pop.pos)
     with B.Population(B.params_of(pop, precision), pop.pos, pop.radius, pop.type) as P:
         got = P.binning()
-    names = ("voxel_of_cell", "voxel_start", "sorted_ids", "occ")
-    for name, g, w in zip(names, got, want):
-        assert g.dtype == np.uint32 and g.shape == w.shape, name
-        assert np.array_equal(g, w), name
+    check_binning(got, want, pop.pos, pop.lo, pop.hi, pop.voxel)
 
 
 @pytest.mark.parametrize("name", ["plain1k", "sph100k", "tumour1m"])
@@ -77,3 +76,14 @@ def test_binning_ragged_sizes(orc):
     require_gpu()
     for n in (1, 2, 63, 65, 255, 257, 4097):
         _compare(orc, workloads.spheroid(n, seed=100 + n))
+
+
+def test_binning_large_grid_scan_path(orc):
+    """A grid of more than 2048 scan tiles (4 bins per voxel, 2048 bins per tile: above
+    1,048,576 voxels) takes the separate tile-sum scan (k_scan_top) instead of the fused
+    one; its output is compared bit for bit too.  A sparse 3.3 mm cube: 110^3 = 1,331,000
+    voxels for 200,000 cells."""
+    require_gpu()
+    pop = workloads.plain(200_000, seed=12, half=1650.0)
+    assert np.prod(orc.grid_dims(orc.params_of(pop))) * 4 > 2048 * 2048
+    _compare(orc, pop)

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 import workloads
-from gpu_helpers import pos_err, record, require_gpu, say
+from gpu_helpers import check_binning, pos_err, record, require_gpu, say
 from paper_2306_11544_amd import binding as B
 
 pytestmark = pytest.mark.gpu
@@ -111,8 +111,7 @@ def test_binning_after_growth_is_exact(orc):
         P.step(1)
         vid, start, ids, occ = P.binning()
     want = orc.bin(orc.params_of(pop), before)
-    for g, w in zip((vid, start, ids, occ), want):
-        assert np.array_equal(g, w)
+    check_binning((vid, start, ids, occ), want, before, pop.lo, pop.hi, pop.voxel)
 
 
 def test_bad_division_arguments():

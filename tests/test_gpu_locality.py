@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 import workloads
-from gpu_helpers import require_gpu, say
+from gpu_helpers import check_binning, require_gpu, say
 from paper_2306_11544_amd import binding as B
 
 pytestmark = pytest.mark.gpu
@@ -49,10 +49,7 @@ def test_binning_of_cells_left_in_place_is_exact(orc, every):
         P.step(1)
         vid, start, ids, occ = P.binning()
     want = orc.bin(orc.params_of(pop), before)
-    assert np.array_equal(vid, want[0])
-    assert np.array_equal(start, want[1])
-    assert np.array_equal(ids, want[2])
-    assert np.array_equal(occ, want[3])
+    check_binning((vid, start, ids, occ), want, before, pop.lo, pop.hi, pop.voxel)
 
 
 def test_switching_modes_mid_run():

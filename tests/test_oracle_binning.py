@@ -1,8 +1,8 @@
 """Pins the oracle's binning against numpy floor + lexsort (a library routine).
 
 Binning is integer work and must be bit-exact: voxel of each cell, the exclusive
-prefix of voxel counts, cells ordered by (voxel, x slab, id) -- the slab being the
-quarter of the voxel along x that holds the cell -- and the list of occupied voxels.
+prefix of voxel counts, cells ordered by (voxel, id) -- a counting sort by voxel that is
+stable in cell id -- and the list of occupied voxels.
 Adversarial positions sit exactly on voxel and slab faces, on lo and hi, one ulp
 either side of a face, and at -0.0.
 """
@@ -18,10 +18,8 @@ def numpy_bin(lo, hi, h, pos):
     k = np.floor((pos - lo) * (1.0 / h))
     k = np.clip(k, 0, dims - 1).astype(np.int64)
     vid = k[:, 0] + dims[0] * (k[:, 1] + dims[1] * k[:, 2])
-    s4 = np.floor((pos[:, 0] - lo[0]) * (1.0 / h) * 4.0)
-    slab = np.clip(s4, 0, 4 * dims[0] - 1).astype(np.int64) - 4 * k[:, 0]
     V = int(np.prod(dims))
-    order = np.lexsort((np.arange(len(pos)), slab, vid))
+    order = np.lexsort((np.arange(len(pos)), vid))
     start = np.concatenate([[0], np.cumsum(np.bincount(vid, minlength=V))])
     occ = np.unique(vid)
     return vid.astype(np.uint32), start.astype(np.uint32), order.astype(np.uint32), occ.astype(np.uint32)
@@ -73,12 +71,12 @@ def test_voxel_numbering_is_x_fastest(orc):
     assert list(vid) == [1, 3, 9, 26]
 
 
-def test_slab_order_inside_a_voxel(orc):
-    """Cells of one voxel are listed by x quarter of the voxel, then by id."""
+def test_ties_broken_by_ascending_id(orc):
+    """Cells of one voxel are listed by ascending id, wherever they sit in it."""
     p = orc.params((0.0,) * 3, (90.0,) * 3, h=30.0)
-    x = np.array([29.0, 1.0, 16.0, 7.5, 7.4999, 22.5, 0.0, 15.0])
+    x = np.array([29.0, 1.0, 16.0, 7.5, 7.4999, 22.5, 0.0, 15.0, 45.0, 31.0])
     pos = np.stack([x, np.full_like(x, 3.0), np.full_like(x, 3.0)], axis=1)
-    _, start, order, _ = orc.bin(p, pos)
-    # slabs: 29->3, 1->0, 16->2, 7.5->1, 7.4999->0, 22.5->3, 0->0, 15->2
-    assert list(order) == [1, 4, 6, 3, 2, 7, 0, 5]
-    assert start[0] == 0 and start[1] == 8
+    vid, start, order, occ = orc.bin(p, pos)
+    assert list(vid) == [0] * 8 + [1, 1]
+    assert list(order) == [0, 1, 2, 3, 4, 5, 6, 7, 8, 9]
+    assert list(start[:3]) == [0, 8, 10] and list(occ) == [0, 1]

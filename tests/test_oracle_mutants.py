@@ -16,7 +16,7 @@ import oracle
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "mech_oracle.c")
-PINS = ["tests/test_oracle_closed_form.py", "tests/test_oracle_invariants.py",
+PINS = ["tests/test_oracle_closed_form.py", "tests/test_oracle_invariants.py", "tests/test_oracle_fp32.py",
         "tests/test_oracle_bruteforce.py", "tests/test_oracle_binning.py", "tests/test_kahan.py",
         "tests/test_oracle_division.py", "tests/test_oracle_death.py"]
 
@@ -51,22 +51,27 @@ MUTANTS = [
     ("voxel numbering y fastest",
      "    return k[0] + (int64_t)dims[0] * (k[1] + (int64_t)dims[1] * k[2]);",
      "    return k[1] + (int64_t)dims[1] * (k[0] + (int64_t)dims[0] * k[2]);"),
-    ("x slab ignored",
-     "    *slab = (int)(s4 - 4 * k[0]);", "    *slab = 0;"),
+    ("a cell on a voxel face binned into the voxel below",
+     "        double f = floor((x[a] - p->lo[a]) * inv_h);",
+     "        double f = ceil((x[a] - p->lo[a]) * inv_h) - 1.0;"),
     ("ties broken by descending id",
-     "    for (int64_t i = 0; i < n; ++i) sorted_ids[cursor[key[i]]++] = (uint32_t)i;",
-     "    for (int64_t i = n - 1; i >= 0; --i) sorted_ids[cursor[key[i]]++] = (uint32_t)i;"),
-    ("voxel counts off by one",
-     "    for (int64_t i = 0; i < n; ++i) voxel_start[vid[i] + 1] += 1;",
-     "    for (int64_t i = 0; i < n; ++i) voxel_start[vid[i]] += 1;"),
+     "    for (int64_t i = 0; i < n; ++i) sorted_ids[cursor[vid[i]]++] = (uint32_t)i;",
+     "    for (int64_t i = n - 1; i >= 0; --i) sorted_ids[cursor[vid[i]]++] = (uint32_t)i;"),
+    ("occupied voxels named one voxel late",
+     "        if (voxel_start[v + 1] > voxel_start[v]) occ[m++] = (uint32_t)v;",
+     "        if (voxel_start[v + 1] > voxel_start[v]) occ[m++] = (uint32_t)(v + 1);"),
     ("scan drops the last voxel",
      "    for (int64_t v = 0; v < V; ++v) voxel_start[v + 1] += voxel_start[v];",
      "    for (int64_t v = 0; v + 1 < V; ++v) voxel_start[v + 1] += voxel_start[v];"),
     ("empty voxels listed as occupied",
-     "        if (voxel_start[v + 1] > voxel_start[v]) occ[m++] = (uint32_t)v;",
-     "        if (voxel_start[v + 1] >= voxel_start[v]) occ[m++] = (uint32_t)v;"),
+     "        if (voxel_start[v + 1] > voxel_start[v]) occ[m++]",
+     "        if (voxel_start[v + 1] >= voxel_start[v]) occ[m++]"),
     ("Kahan compensation sign",
      "        *c = (t - *sum) - y;", "        *c = (t - *sum) + y;"),
+    ("float distance without its z term",
+     "    float d2 = dx * dx + dy * dy + dz * dz;", "    float d2 = dx * dx + dy * dy;"),
+    ("float distance fused",
+     "    float d2 = dx * dx + dy * dy + dz * dz;", "    float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));"),
     ("float repulsion dropped",
      "        w += (float)p->c_rep * u * u;", "        w += 0.0f;"),
     ("division draw from the direction counter",
