@@ -105,7 +105,7 @@ typedef struct MechTuning {
                                    4 per compute unit for the voxel kernel              */
     int32_t list_len;           /* in-range candidates a lane of the list kernel holds
                                    before the wave evaluates them: 16, 32, 64, or 0
-                                   (default: 16)                                        */
+                                   (default: 16); 64 needs block_waves <= 4             */
 } MechTuning;
 
 typedef struct MechPopulation MechPopulation;
@@ -272,6 +272,37 @@ int create_batch(const MechParams* params, int64_t max_cells, int64_t max_voxels
 int create_batch_in(const MechParams* params, int64_t max_cells, int64_t max_voxels,
                     int32_t max_slots, void* hip_stream, void* workspace,
                     int64_t workspace_bytes, MechBatch** out);
+
+/* Cells and voxels of the largest batch arena within hbm_budget_bytes of device memory,
+ * for workloads that need about voxels_per_cell voxels per cell (max_voxels =
+ * ceil(voxels_per_cell * max_cells), at least 1) and max_slots slots: the admission
+ * capacity a server gets from an HBM budget.  MECH_E_BUDGET if not even one cell fits;
+ * MECH_E_INVALID for bad parameters (voxels_per_cell must lie in (0, 1e6]).  Defined by
+ * the library's arena layout, not by the paper. */
+int batch_budget_capacity(const MechParams* params, int64_t hbm_budget_bytes, double voxels_per_cell,
+                          int32_t max_slots, int64_t* max_cells, int64_t* max_voxels);
+
+/* create_batch with the capacity batch_budget_capacity gives for the budget: one device
+ * allocation of at most hbm_budget_bytes, made here and owned by the batch.  Admission
+ * then fails with MECH_E_BUDGET whenever a request's cells or voxels do not fit what the
+ * running simulations leave free. */
+int create_batch_budget(const MechParams* params, int64_t hbm_budget_bytes, double voxels_per_cell,
+                        int32_t max_slots, void* hip_stream, MechBatch** out);
+
+/* Capacity of a batch: cells, voxels and slots it was created for, and its arena bytes
+ * (each pointer may be NULL). */
+int batch_capacity(MechBatch* batch, int64_t* max_cells, int64_t* max_voxels, int32_t* max_slots,
+                   int64_t* arena_bytes);
+
+/* Record a reference point on the batch's stream and wait until the device reaches it:
+ * the zero of batch_slot_done_ms.  A serving loop calls it once when its clock starts. */
+int batch_mark_clock(MechBatch* batch);
+
+/* Device time in ms from the last batch_mark_clock to the completion of a slot's last
+ * step (its completion event, recorded right after that step), for a slot that
+ * batch_poll has reported finished.  MECH_E_INVALID if the clock was never marked, the
+ * slot holds no simulation or has not finished on the device. */
+int batch_slot_done_ms(MechBatch* batch, int32_t slot, double* ms);
 
 /* Admit one simulation (arrays as in create_population, domain given here).  It runs
  * n_steps steps of the following batch_step calls and then stays frozen until read and

@@ -39,6 +39,8 @@ def search_space():
         for u in (2, 4, 8):
             for g in (0, 16):
                 for ln in (0, 32, 64):
+                    if w == 8 and ln == 64:
+                        continue    # more LDS than a compute unit has
                     space.append(B.tuning("cells", w, u, g, ln))
     for w in (2, 4, 8):
         space.append(B.tuning("rows", w, 4, 0))

@@ -39,7 +39,9 @@ EXPORTS = ("mech_last_error", "mech_abi_version", "mech_device_count",
            "batch_workspace_bytes", "batch_request_voxels", "create_batch", "create_batch_in",
            "batch_admit", "batch_step", "batch_poll", "batch_read", "batch_retire",
            "batch_slot_info", "batch_info", "batch_stats", "batch_profile", "batch_set_flags",
-           "batch_get_tuning", "batch_set_tuning", "batch_sync", "batch_stream", "destroy_batch")
+           "batch_get_tuning", "batch_set_tuning", "batch_sync", "batch_stream", "destroy_batch",
+           "batch_budget_capacity", "create_batch_budget", "batch_capacity", "batch_mark_clock",
+           "batch_slot_done_ms")
 
 
 class MechError(RuntimeError):
@@ -134,6 +136,11 @@ def lib():
             "batch_sync": (C.c_int, [vp]),
             "batch_stream": (C.c_void_p, [vp]),
             "destroy_batch": (C.c_int, [vp]),
+            "batch_budget_capacity": (C.c_int, [P(MechParams), C.c_int64, C.c_double, C.c_int32, lp, lp]),
+            "create_batch_budget": (C.c_int, [P(MechParams), C.c_int64, C.c_double, C.c_int32, vp, P(vp)]),
+            "batch_capacity": (C.c_int, [vp, lp, lp, ip, lp]),
+            "batch_mark_clock": (C.c_int, [vp]),
+            "batch_slot_done_ms": (C.c_int, [vp, C.c_int32, dp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -396,6 +403,16 @@ def batch_request_voxels(params: MechParams, lo, hi) -> int:
     return r
 
 
+def batch_budget_capacity(params: MechParams, budget_bytes: int, voxels_per_cell: float,
+                          max_slots: int):
+    """(max_cells, max_voxels) of the largest arena within the budget (computed by the
+    library on the host; no device needed)."""
+    c, v = C.c_int64(), C.c_int64()
+    _ck(lib().batch_budget_capacity(C.byref(params), int(budget_bytes), float(voxels_per_cell),
+                                    int(max_slots), C.byref(c), C.byref(v)))
+    return int(c.value), int(v.value)
+
+
 def batch_sync(batch) -> None:
     """Wait until every step enqueued on the batch has completed."""
     _ck(lib().batch_sync(batch.h))
@@ -404,12 +421,18 @@ def batch_sync(batch) -> None:
 class Batch:
     """Many independent simulations advanced together (see include/mech.h)."""
 
-    def __init__(self, params: MechParams, max_cells: int, max_voxels: int, max_slots: int,
-                 stream=None, workspace=None):
+    def __init__(self, params: MechParams, max_cells: int = 0, max_voxels: int = 1,
+                 max_slots: int = 1, stream=None, workspace=None, budget_bytes=None,
+                 voxels_per_cell: float = 1.6):
+        """Capacity given as max_cells/max_voxels/max_slots, or (budget_bytes set) sized
+        by the library from an HBM byte budget for max_slots slots."""
         self.params = params
         self._ws = workspace
         h = C.c_void_p()
-        if workspace is not None:
+        if budget_bytes is not None:
+            _ck(lib().create_batch_budget(C.byref(params), int(budget_bytes), float(voxels_per_cell),
+                                          int(max_slots), stream, C.byref(h)))
+        elif workspace is not None:
             _ck(lib().create_batch_in(C.byref(params), int(max_cells), int(max_voxels),
                                       int(max_slots), stream, C.c_void_p(int(workspace.data_ptr())),
                                       int(workspace.numel() * workspace.element_size()),
@@ -439,6 +462,26 @@ class Batch:
     def step(self, n_steps=1):
         _ck(lib().batch_step(self.h, int(n_steps)))
         return self
+
+    def sync(self):
+        """Wait until every step enqueued on the batch has completed."""
+        _ck(lib().batch_sync(self.h))
+
+    def capacity(self):
+        c, v, b = C.c_int64(), C.c_int64(), C.c_int64()
+        s = C.c_int32()
+        _ck(lib().batch_capacity(self.h, C.byref(c), C.byref(v), C.byref(s), C.byref(b)))
+        return dict(max_cells=c.value, max_voxels=v.value, max_slots=s.value, arena_bytes=b.value)
+
+    def mark_clock(self):
+        """Zero of done_ms: recorded on the stream and waited for."""
+        _ck(lib().batch_mark_clock(self.h))
+
+    def done_ms(self, slot) -> float:
+        """Device ms from mark_clock to the completion of the slot's last step."""
+        ms = C.c_double()
+        _ck(lib().batch_slot_done_ms(self.h, int(slot), C.byref(ms)))
+        return float(ms.value)
 
     def poll(self):
         out = np.zeros(self.max_slots, np.int32)

@@ -142,6 +142,8 @@ typedef unsigned short ushort2v __attribute__((ext_vector_type(2)));
 typedef short short2v __attribute__((ext_vector_type(2)));
 // margin of the prefilter's reach in units of the quantised shadow (3 > sqrt(3) + 1)
 constexpr uint32_t Q_MARGIN = 3;
+// entries of the quantised shadow past the last cell that the force kernel's trips may read
+constexpr size_t QS_PAD = 16;
 
 // The quantised shadow of a cell, the prefilter's input: each coordinate as
 // round(x S) mod 2^16 (S = q_scale, a power of two, so x S is exact) and the reach
@@ -1353,8 +1355,8 @@ __global__ __launch_bounds__(WPB * WAVE) void k_force_rows(PhysArgs P, ForceArgs
 // are those of the reordered path, so the results are bitwise the same.
 template <int PREC, bool MULTI, typename VPT, int FC_UNROLL, int LIST, bool IND = false>
 __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceArgs<VPT>& a, uint32_t i,
-                                                 uint32_t n, uint32_t* const list0, uint32_t& inter,
-                                                 uint32_t& cand)
+                                                 uint32_t n, uint32_t* const list0, uint2* const rng0,
+                                                 uint32_t& inter, uint32_t& cand)
 {
     using Real = typename std::conditional<PREC == 0, double, float>::type;
     const bool in_pop = i < n;
@@ -1362,22 +1364,54 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
     const SlotDesc& d = a.slots[a.slot_of[ii]];
     const bool valid = in_pop && d.active_now != 0;
     const Cellgeo g = cell_geo(a.vid_sorted[ii] / XSUB, d);
-    // The x slabs of each neighbour row that can hold a partner: every interacting j has
-    // |x_j - x_i| < alpha (r_i + r_max).  The window is taken in FP64 from the exact
-    // position and widened by a margin that covers the float rounding of the FP32
-    // decision (a few ulp of |x|) and of R_A, so it never drops a pair either
-    // precision counts.  w0, w1: the window's first and one-past-last slab, counted from
-    // the first slab of the row's voxels and clipped to them.
-    uint32_t w0, w1;
-    {
-        const double xg = a.XS[0][ii];
+    // The candidates of each neighbour row that can hold a partner, the paper's test of
+    // whether a neighbour voxel can hold interacting cells (Section 4.2) done per cell and
+    // row: every interacting j has d_ij < reach = alpha (r_i + r_max), so with rho the
+    // distance in y-z from the cell to the row's voxels, a row with rho >= reach holds no
+    // partner and is skipped, and in the others |x_j - x_i| < sqrt(reach^2 - rho^2): the
+    // row's x slabs in that window are one contiguous run of the sorted arrays.  The reach
+    // is taken in FP64 from the exact position and widened by a margin that covers the
+    // float rounding of the FP32 decision (a few ulp of |x|) and of R_A; the window
+    // arithmetic then runs in float on coordinates in voxel units relative to the cell's
+    // own voxel (exact to about 1e-7 of a voxel), under a further relative pad of 1e-5.
+    // So a window never drops a pair that either precision counts.  The non-empty runs,
+    // in row order (dz, then dy), go to the lane's LDS slots rng0[k * WAVE], k < nr.
+    uint32_t nr = 0;
+    if (valid) {
+        const double xg = a.XS[0][ii], yg = a.XS[1][ii], zg = a.XS[2][ii];
         const double reach = P.alpha * (a.R[ii] + d.r_max);
-        const double m = reach * (1.0 + 1e-6) + 1e-3 + 5e-7 * (fabs(xg) + reach);
-        const double xs = (double)XSUB * d.inv_h;
-        const double lo_s = floor((xg - d.lo[0] - m) * xs), hi_s = floor((xg - d.lo[0] + m) * xs);
-        const double s_min = (double)(XSUB * (uint32_t)g.x0), s_max = (double)(XSUB * (uint32_t)g.x1 + XSUB - 1);
-        w0 = (uint32_t)(fmax(lo_s, s_min) - s_min);            // first slab, from the row's start
-        w1 = (uint32_t)(fmin(hi_s, s_max) - s_min) + 1u;       // one past the last slab
+        const double pm = fmax(fabs(xg), fmax(fabs(yg), fabs(zg)));
+        const double m = reach * (1.0 + 1e-6) + 1e-3 + 5e-7 * (pm + reach);
+        const float rh = (float)(m * d.inv_h) * (1.0f + 1e-5f);           // voxel units
+        const float rh2 = rh * rh;
+        const float uy = (float)((yg - d.lo[1]) * d.inv_h - (double)g.ky);  // in [0, 1]
+        const float uz = (float)((zg - d.lo[2]) * d.inv_h - (double)g.kz);
+        // x in slabs from the first slab of the row's voxels, and the row's last slab
+        const float sx = (float)(((xg - d.lo[0]) * d.inv_h - (double)g.x0) * (double)XSUB);
+        const float s_last = (float)(XSUB * (uint32_t)(g.x1 - g.x0 + 1) - 1u);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            const int dz = q / 3 - 1, dy = q % 3 - 1;
+            // distance from the cell to the row's voxels along y and z, in voxel units
+            const float ey = fmaxf(dy < 0 ? uy : dy > 0 ? 1.0f - uy : 0.0f, 0.0f);
+            const float ez = fmaxf(dz < 0 ? uz : dz > 0 ? 1.0f - uz : 0.0f, 0.0f);
+            const float t = rh2 - (ey * ey + ez * ez);
+            const int64_t r0 = row_first(g, d, q);
+            if (r0 >= 0 && t > 0.0f) {
+                const float hw = __builtin_sqrtf(t) * (float)XSUB;
+                const uint32_t w0 = (uint32_t)fmaxf(floorf(sx - hw), 0.0f);
+                const uint32_t w1 = (uint32_t)fminf(floorf(sx + hw), s_last) + 1u;
+                if (w1 > w0) {
+                    const uint32_t jb = a.voxel_start[XSUB * r0 + w0];
+                    const uint32_t je = a.voxel_start[XSUB * r0 + w1];
+                    if (je > jb) {
+                        rng0[nr * WAVE] = make_uint2(jb, je);
+                        ++nr;
+                        cand += je - jb;
+                    }
+                }
+            }
+        }
     }
     Real xi, yi, zi, ri;
     if constexpr (PREC == 0) {
@@ -1528,56 +1562,59 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
         }
     };
 
-    // the candidate range [j, e) of neighbour row q (empty outside the grid); the next
-    // row's range is read while the current row is walked
-    auto range = [&](int q, uint32_t& j, uint32_t& e) {
-        const int64_t r0 = valid ? row_first(g, d, q) : -1;
-        j = r0 < 0 ? 0u : a.voxel_start[XSUB * r0 + w0];
-        e = r0 < 0 ? 0u : a.voxel_start[XSUB * r0 + w1];
-    };
-    uint32_t j_next, e_next;
-    range(0, j_next, e_next);
-    for (int q = 0; q < 9; ++q) {
-        uint32_t j = j_next;
-        const uint32_t e = e_next;
-        if (q < 8) range(q + 1, j_next, e_next);
-        cand += e - j;
+    // The walk: each lane takes its own runs one after the other, FC_UNROLL candidates
+    // per trip, so a trip of the wave serves every lane that still has candidates,
+    // whichever row it is in (lanes of one wave sit in two or three voxels and at
+    // different depths of them, so their runs differ in number and length).  A trip reads
+    // FC_UNROLL consecutive entries of the quantised shadow from j; those at or past the
+    // run's end e are not listed (the array is padded, so the reads stay inside it, and a
+    // lane that has finished re-reads from its last e).  When j passes e the lane moves
+    // to its next run.  Candidates are listed in run order, so each sum is still taken in
+    // the fixed neighbour order.
+    uint32_t k = 0;
+    uint2 run = nr > 0 ? rng0[0] : make_uint2(0u, 0u);
+    uint32_t j = run.x, e = run.y;
+#pragma unroll 1
+    while (__any(k < nr)) {
+        const uint32_t lim = k < nr ? min(e - j, (uint32_t)FC_UNROLL) : 0u;
         if constexpr (IND) {
             // gathers through the sorted order: no locality between consecutive lanes
-            for (; j < e; ++j) {
-                const uint32_t jj = a.perm[j];
-                push(jj, near(a.QS[jj]));
-                if (full()) flush(KEEP);
+#pragma unroll
+            for (int u = 0; u < FC_UNROLL; ++u) {
+                uint32_t jj = ii;
+                bool in = false;
+                if ((uint32_t)u < lim) {
+                    jj = a.perm[j + u];
+                    in = near(a.QS[jj]);
+                }
+                push(jj, in);
             }
-            continue;
-        }
-        const uint2* sp = a.QS + j;
-        for (; j + FC_UNROLL <= e; j += FC_UNROLL, sp += FC_UNROLL) {
+        } else {
             uint2 c[FC_UNROLL];
 #pragma unroll
-            for (int u = 0; u < FC_UNROLL; ++u) c[u] = sp[u];
+            for (int u = 0; u < FC_UNROLL; ++u) c[u] = a.QS[j + u];
             if constexpr (PACK) {
 #pragma unroll
                 for (int g4 = 0; g4 < FC_UNROLL; g4 += 4) {
-                    uint32_t m = 0;
+                    uint32_t mk = 0;
 #pragma unroll
-                    for (int u = g4; u < FC_UNROLL && u < g4 + 4; ++u) m |= (near(c[u]) ? 1u : 0u) << (u - g4);
-                    push(((j + g4) << 4) | m, m != 0u);
+                    for (int u = g4; u < FC_UNROLL && u < g4 + 4; ++u)
+                        mk |= ((uint32_t)u < lim && near(c[u]) ? 1u : 0u) << (u - g4);
+                    push(((j + g4) << 4) | mk, mk != 0u);
                 }
             } else {
 #pragma unroll
-                for (int u = 0; u < FC_UNROLL; ++u) push(j + u, near(c[u]));
+                for (int u = 0; u < FC_UNROLL; ++u) push(j + u, (uint32_t)u < lim && near(c[u]));
             }
-            if (full()) flush(KEEP);
         }
-        for (; j < e; ++j, ++sp) {
-            const bool in = near(*sp);
-            if constexpr (PACK)
-                push((j << 4) | 1u, in);
-            else
-                push(j, in);
-            if (full()) flush(KEEP);
+        j += FC_UNROLL;
+        if (k < nr && j >= e) {
+            ++k;
+            run = k < nr ? rng0[k * WAVE] : make_uint2(e, e);
+            j = run.x;
+            e = run.y;
         }
+        if (full()) flush(KEEP);
     }
     flush(0);
     if (valid) {
@@ -1597,16 +1634,18 @@ __global__ __launch_bounds__(WPB * WAVE) void k_force_cells(PhysArgs P, ForceArg
     static_assert(2 * UNROLL <= LIST, "a trip must fit the list above the flush mark");
     constexpr uint32_t TB = WPB * WAVE;
     __shared__ uint32_t s_list[WPB][LIST][WAVE];
+    __shared__ uint2 s_rng[WPB][9][WAVE];
     const uint32_t n = a.hdr[H_CELLS];
     const uint32_t nb = (n + TB - 1) / TB;
     uint32_t* const list0 = &s_list[threadIdx.x / WAVE][0][threadIdx.x & (WAVE - 1)];
+    uint2* const rng0 = &s_rng[threadIdx.x / WAVE][0][threadIdx.x & (WAVE - 1)];
     uint32_t inter = 0, cand = 0;
     // rounds of gridDim.x blocks, renumbered per round as in k_force_rows
     for (uint32_t lb0 = 0; lb0 < nb; lb0 += gridDim.x) {
         const uint32_t active = min(gridDim.x, nb - lb0);
         if (blockIdx.x >= active) break;
         const uint32_t i = (lb0 + xcd_block(blockIdx.x, active)) * TB + threadIdx.x;
-        force_cells_cell<PREC, MULTI, VPT, UNROLL, LIST, IND>(P, a, i, n, list0, inter, cand);
+        force_cells_cell<PREC, MULTI, VPT, UNROLL, LIST, IND>(P, a, i, n, list0, rng0, inter, cand);
     }
     add_stats(a.stats, inter, cand);
 }
@@ -1908,7 +1947,7 @@ Layout make_layout(const MechParams& p, int64_t ncap, uint64_t vcap, int32_t sca
         for (int c = 0; c < 3; ++c) L.VP[k][c] = take(nn * vpb);
     }
     L.SH = take(is_fp32(p) ? nn * 16 : 0);   // read by the FP32 kernels only
-    L.QS = take(nn * 8);
+    L.QS = take((nn + QS_PAD) * 8);        // a trip of the force kernel may read past the last cell
     L.slot_of = take(nn * 4);
     L.vid_cur = take(nn * 4);
     L.off = take(nn * 4);
@@ -1968,15 +2007,19 @@ double quant_scale(double h) { return std::ldexp(1.0, (int)std::floor(std::log2(
 
 int validate_domain(const double lo[3], const double hi[3], double h, int32_t dims[3], uint64_t* V)
 {
-    // the quantised shadow rounds x S to an integer: it must stay exact in a double
-    // (and S finite in a float)
+    // The quantised shadow rounds x S to an integer: it must stay exact in a double (and
+    // S finite in a float).  The prefilter squares its threshold t = (reach_i + reach_j
+    // + Q_MARGIN + q_pad) units in 32 bits, so t must stay below 2^16: each reach is at
+    // most alpha r_max S <= h S / 2 <= 2^12 units (the voxel holds 2 alpha r_max), and
+    // q_pad = ceil(2^-20 P S) grows with the largest coordinate P.
     {
         const double S = quant_scale(h);
         double pm = 0.0;
         for (int a = 0; a < 3; ++a) pm = std::max(pm, std::max(std::fabs(lo[a]), std::fabs(hi[a])));
         if (!(S < 0x1p100)) return fail(MECH_E_INVALID, "voxel_size %.17g is too small", h);
-        if (!(pm * S < 0x1p52))
-            return fail(MECH_E_INVALID, "domain coordinates up to %.17g um are too large for voxel_size %.17g", pm, h);
+        if (!(pm * S < 0x1p52) || !(std::ceil(pm * S * 0x1p-20) + 2.0 * 4096.0 + (double)Q_MARGIN < 65536.0))
+            return fail(MECH_E_INVALID, "domain coordinates up to %.17g um are too large for voxel_size %.17g "
+                        "(the prefilter's margin would overflow)", pm, h);
     }
     uint64_t v = 1;
     for (int a = 0; a < 3; ++a) {
@@ -2042,6 +2085,8 @@ struct MechBatch {
     hipStream_t stream = nullptr, copy_stream = nullptr;
     bool own_stream = false;
     hipEvent_t copy_done = nullptr;
+    hipEvent_t clock = nullptr;           // batch_mark_clock's reference point
+    bool clock_marked = false;
     char* arena = nullptr;
     bool own_arena = false;
     Layout L{};
@@ -2201,7 +2246,11 @@ void launch_cells_w(MechBatch* B, const ForceArgs<VPT>& a)
                         ? 32 : B->tune.list_len;
     switch (len) {
     case 32: launch_cells_l<PREC, MULTI, VPT, WPB, 32>(B, a); break;
-    case 64: launch_cells_l<PREC, MULTI, VPT, WPB, 64>(B, a); break;
+    case 64:
+        // 8 waves with 64-entry lists would take more LDS than a CU has (set_tuning
+        // rejects the pair)
+        if constexpr (WPB <= 4) launch_cells_l<PREC, MULTI, VPT, WPB, 64>(B, a);
+        break;
     default: launch_cells_l<PREC, MULTI, VPT, WPB, 16>(B, a); break;
     }
 }
@@ -2539,6 +2588,7 @@ void release(MechBatch* B)
     for (auto& s : B->slots)
         if (s.done) (void)hipEventDestroy(s.done);
     if (B->copy_done) (void)hipEventDestroy(B->copy_done);
+    if (B->clock) (void)hipEventDestroy(B->clock);
     if (B->own_arena && B->arena) (void)hipFree(B->arena);
     if (B->copy_stream) (void)hipStreamDestroy(B->copy_stream);
     if (B->own_stream && B->stream) (void)hipStreamDestroy(B->stream);
@@ -2605,9 +2655,10 @@ int create_batch_impl(const MechParams* params, int64_t max_cells, int64_t max_v
     if (hipStreamCreateWithFlags(&B->copy_stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&B->copy_done, hipEventDisableTiming) != hipSuccess)
         return bail(fail(MECH_E_DEVICE, "stream or event creation failed"));
+    // completion events keep timing: batch_slot_done_ms measures them against the clock mark
     for (auto& s : B->slots)
-        if (hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess)
-            return bail(fail(MECH_E_DEVICE, "hipEventCreate failed"));
+        if (hipEventCreate(&s.done) != hipSuccess) return bail(fail(MECH_E_DEVICE, "hipEventCreate failed"));
+    if (hipEventCreate(&B->clock) != hipSuccess) return bail(fail(MECH_E_DEVICE, "hipEventCreate failed"));
     if (workspace) {
         if (ws_bytes < (int64_t)B->L.total)
             return bail(fail(MECH_E_NOMEM, "workspace of %lld bytes < %zu needed", (long long)ws_bytes, B->L.total));
@@ -3028,6 +3079,33 @@ int profile_impl(MechBatch* B, int64_t n_steps, double* phase_ms)
     return MECH_OK;
 }
 
+// The largest arena within a byte budget: cells and voxels = ceil(voxels_per_cell * cells)
+// (at least one), found by bisection over the layout's exact size.
+int budget_capacity(const MechParams* params, int64_t budget, double vpc, int32_t max_slots, int64_t* cells_out,
+                    int64_t* voxels_out)
+{
+    int rc = validate_physics(params);
+    if (rc) return rc;
+    if (!(std::isfinite(vpc) && vpc > 0.0 && vpc <= 1e6))
+        return fail(MECH_E_INVALID, "voxels_per_cell must be in (0, 1e6]");
+    if (max_slots < 1 || max_slots > 65536) return fail(MECH_E_INVALID, "max_slots out of range");
+    const int64_t vmax = (int64_t(1) << 30) - 1;
+    auto voxels_for = [&](int64_t c) { return std::min<int64_t>(vmax, std::max<int64_t>(1, (int64_t)std::ceil(vpc * (double)c))); };
+    auto bytes = [&](int64_t c) { return (int64_t)make_layout(*params, c, (uint64_t)voxels_for(c), max_slots).total; };
+    if (budget < bytes(1)) return fail(MECH_E_BUDGET, "a budget of %lld bytes holds no cell (%lld needed for one)",
+                                       (long long)budget, (long long)bytes(1));
+    int64_t lo = 1, hi = std::min<int64_t>((int64_t(1) << 31) - 1, (int64_t)((double)vmax / vpc));
+    hi = std::max<int64_t>(hi, 1);
+    if (bytes(hi) <= budget) lo = hi;
+    while (lo < hi) {   // bytes(lo) <= budget < bytes(hi + 1) after the loop
+        const int64_t mid = lo + (hi - lo + 1) / 2;
+        if (bytes(mid) <= budget) lo = mid; else hi = mid - 1;
+    }
+    *cells_out = lo;
+    *voxels_out = voxels_for(lo);
+    return MECH_OK;
+}
+
 int64_t batch_bytes(const MechParams* params, int64_t max_cells, int64_t max_voxels, int32_t max_slots)
 {
     int rc = validate_physics(params);
@@ -3409,6 +3487,62 @@ int create_batch_in(const MechParams* params, int64_t max_cells, int64_t max_vox
     return create_batch_impl(params, max_cells, max_voxels, max_slots, hip_stream, workspace, workspace_bytes, out);
 }
 
+int batch_budget_capacity(const MechParams* params, int64_t hbm_budget_bytes, double voxels_per_cell,
+                          int32_t max_slots, int64_t* max_cells, int64_t* max_voxels)
+{
+    if (!max_cells || !max_voxels) return fail(MECH_E_INVALID, "max_cells or max_voxels is NULL");
+    return budget_capacity(params, hbm_budget_bytes, voxels_per_cell, max_slots, max_cells, max_voxels);
+}
+
+int create_batch_budget(const MechParams* params, int64_t hbm_budget_bytes, double voxels_per_cell,
+                        int32_t max_slots, void* hip_stream, MechBatch** out)
+{
+    if (out) *out = nullptr;
+    int64_t cells = 0, voxels = 0;
+    int rc = budget_capacity(params, hbm_budget_bytes, voxels_per_cell, max_slots, &cells, &voxels);
+    if (rc) return rc;
+    return create_batch_impl(params, cells, voxels, max_slots, hip_stream, nullptr, 0, out);
+}
+
+int batch_capacity(MechBatch* B, int64_t* max_cells, int64_t* max_voxels, int32_t* max_slots,
+                   int64_t* arena_bytes)
+{
+    if (!B) return fail(MECH_E_INVALID, "batch is NULL");
+    if (max_cells) *max_cells = B->cap_cells;
+    if (max_voxels) *max_voxels = B->cap_voxels;
+    if (max_slots) *max_slots = B->cap_slots;
+    if (arena_bytes) *arena_bytes = (int64_t)B->L.total;
+    return MECH_OK;
+}
+
+int batch_mark_clock(MechBatch* B)
+{
+    if (!B) return fail(MECH_E_INVALID, "batch is NULL");
+    HIP_TRY(hipSetDevice(B->device));
+    HIP_TRY(hipEventRecord(B->clock, B->stream));
+    HIP_TRY(hipEventSynchronize(B->clock));
+    B->clock_marked = true;
+    return MECH_OK;
+}
+
+int batch_slot_done_ms(MechBatch* B, int32_t slot, double* ms)
+{
+    if (!B || !ms) return fail(MECH_E_INVALID, "batch or ms is NULL");
+    if (slot < 0 || slot >= B->cap_slots || !B->slots[(size_t)slot].used)
+        return fail(MECH_E_INVALID, "slot %d holds no simulation", slot);
+    const HostSlot& s = B->slots[(size_t)slot];
+    if (!B->clock_marked) return fail(MECH_E_INVALID, "batch_mark_clock was not called");
+    if (!s.done_recorded) return fail(MECH_E_INVALID, "slot %d has not finished its steps", slot);
+    HIP_TRY(hipSetDevice(B->device));
+    const hipError_t q = hipEventQuery(s.done);
+    if (q == hipErrorNotReady) return fail(MECH_E_INVALID, "slot %d has not finished on the device yet", slot);
+    if (q != hipSuccess) return fail(MECH_E_DEVICE, "hipEventQuery failed: %s", hipGetErrorString(q));
+    float t = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&t, B->clock, s.done));
+    *ms = (double)t;
+    return MECH_OK;
+}
+
 int batch_admit(MechBatch* B, const double domain_lo[3], const double domain_hi[3], int64_t n_cells,
                 const double* pos, const double* radius, const int32_t* type, const double* prev_velocity,
                 int64_t n_steps, int32_t* slot_out)
@@ -3541,6 +3675,8 @@ int batch_set_tuning(MechBatch* B, const MechTuning* t)
         return fail(MECH_E_INVALID, "blocks_per_cu %d not in [0, 64]", t->blocks_per_cu);
     if (t->list_len != 0 && t->list_len != 16 && t->list_len != 32 && t->list_len != 64)
         return fail(MECH_E_INVALID, "list_len %d not in {0, 16, 32, 64}", t->list_len);
+    if (t->block_waves == 8 && t->list_len == 64)
+        return fail(MECH_E_INVALID, "8 waves per workgroup with 64-entry lists exceed a compute unit's LDS");
     HIP_TRY(hipSetDevice(B->device));
     HIP_TRY(hipStreamSynchronize(B->stream));
     drop_graphs(B);

@@ -14,8 +14,11 @@ The loop enqueues a chunk of steps, admits arrivals while that chunk runs (admis
 copies go on a second stream), waits for the chunk and reads the finished requests.
 Each request stops at its own step count inside a chunk (its slot freezes on the
 device), so chunks keep a fixed length whatever the requests still need.
-Latency is completion minus arrival, with completion taken when the step that finished
-the request is seen complete.
+Latency is completion minus arrival.  Completion is the device time of the request's
+last step (its slot's completion event, measured against a clock mark taken when the
+loop starts), not the end of the chunk it finished in, so a request that ends early in
+a chunk is not charged the rest of it.  A request larger than the whole arena can never
+be admitted: it is rejected (recorded in `rejected`) instead of waiting forever.
 
   python -m paper_2306_11544_amd.serve --requests 400 --rate 50 --budget-gb 200
 """
@@ -51,18 +54,9 @@ class Done:
 
 def capacity_for_budget(params: B.MechParams, budget_bytes: int, voxels_per_cell: float,
                         max_slots: int):
-    """Largest (cells, voxels) arena, voxels = voxels_per_cell * cells, within the budget."""
-    base = B.batch_workspace_bytes(params, 0, 1, max_slots)
-    per = (B.batch_workspace_bytes(params, 1 << 20, int((1 << 20) * voxels_per_cell) + 1,
-                                   max_slots) - base) / float(1 << 20)
-    cells = int(max(0, budget_bytes - base - (1 << 20)) / per)
-    max_voxels = (1 << 30) - 1          # the library's limit on voxels per arena
-    cells = min(cells, (1 << 31) - 1, int(max_voxels / voxels_per_cell))
-    voxels = min(int(cells * voxels_per_cell) + 1, max_voxels)
-    while cells > 0 and B.batch_workspace_bytes(params, cells, voxels, max_slots) > budget_bytes:
-        cells = int(cells * 0.99)
-        voxels = min(int(cells * voxels_per_cell) + 1, max_voxels)
-    return cells, voxels
+    """Largest (cells, voxels) arena, voxels = voxels_per_cell * cells, within the budget
+    (the library's batch_budget_capacity)."""
+    return B.batch_budget_capacity(params, budget_bytes, voxels_per_cell, max_slots)
 
 
 @dataclass
@@ -80,13 +74,16 @@ class Server:
     stats: dict = field(default_factory=dict)
 
     def __post_init__(self):
-        self.cap_cells, self.cap_voxels = capacity_for_budget(
-            self.params, self.budget_bytes, self.voxels_per_cell, self.max_slots)
-        if self.cap_cells < 1:
-            raise ValueError("HBM budget too small for any request")
-        self.batch = B.Batch(self.params, self.cap_cells, self.cap_voxels, self.max_slots)
-        self.arena_bytes = B.batch_workspace_bytes(self.params, self.cap_cells, self.cap_voxels,
-                                                   self.max_slots)
+        self.batch = self.make_batch()
+        cap = self.batch.capacity()
+        self.cap_cells, self.cap_voxels = cap["max_cells"], cap["max_voxels"]
+        self.arena_bytes = cap["arena_bytes"]
+        self.rejected = []
+
+    def make_batch(self):
+        """The batch whose arena the library sizes from the HBM budget."""
+        return B.Batch(self.params, max_slots=self.max_slots, budget_bytes=self.budget_bytes,
+                       voxels_per_cell=self.voxels_per_cell)
 
     def close(self):
         self.batch.close()
@@ -106,7 +103,8 @@ class Server:
         max_live = 0
         max_queue = 0
         busy_chunks = 0
-        t0 = time.perf_counter()
+        bt.mark_clock()
+        t0 = time.perf_counter()   # the device reached the clock mark just before this
 
         def now():
             return time.perf_counter() - t0
@@ -131,18 +129,25 @@ class Server:
                 try:
                     slot = bt.admit_pop(pop, n_steps=r.steps)
                 except B.MechError as e:
-                    if e.code in (B.MECH_E_BUDGET, B.MECH_E_FULL):
-                        break
-                    raise
+                    if e.code not in (B.MECH_E_BUDGET, B.MECH_E_FULL):
+                        raise
+                    if running:
+                        break           # waits for running requests to free space
+                    # nothing runs and it still does not fit: it never will
+                    queue.popleft()
+                    self.rejected.append((r.rid, pop.n, str(e)))
+                    if log:
+                        log(f"rejected rid={r.rid} n={pop.n}: {e}")
+                    continue
                 queue.popleft()
                 running[slot] = (r, pop.n, now())
                 live_cells += pop.n
             max_live = max(max_live, len(running))
-            B.batch_sync(bt)
+            bt.sync()
             for slot in bt.poll():
                 r, n, t_admit = running.pop(slot)
                 live_cells -= n
-                t_done = now()
+                t_done = bt.done_ms(slot) * 1e-3
                 pos = vel = None
                 if keep_results:
                     pos, vel = bt.read(slot)
@@ -157,6 +162,7 @@ class Server:
         lat = np.array([d.latency_s for d in done]) if done else np.zeros(1)
         self.stats = {
             "requests": len(done),
+            "rejected": len(self.rejected),
             "makespan_s": makespan,
             "cell_steps": cell_steps,
             "cell_steps_per_s": cell_steps / makespan if makespan > 0 else 0.0,

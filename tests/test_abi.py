@@ -91,6 +91,10 @@ def _p(**kw):
     (lambda p: p.domain_hi.__setitem__(0, -200.0), B.MECH_E_INVALID),
     # the quantised prefilter needs |x| S < 2^52 (S = 256 per um at a 30 um voxel)
     (lambda p: p.domain_hi.__setitem__(1, 2.0 ** 45), B.MECH_E_INVALID),
+    # ... and its squared threshold below 2^32: ceil(2^-20 |x| S) + 2 * 2^12 + 3 < 2^16,
+    # which fails from |x| ~ 2.35e8 um at S = 256 (t^2 would wrap and drop pairs)
+    (lambda p: p.domain_lo.__setitem__(2, -2.4e8), B.MECH_E_INVALID),
+    (lambda p: p.domain_hi.__setitem__(0, 3.0e8), B.MECH_E_INVALID),
     (lambda p: setattr(p, "voxel_size", 1e-40), B.MECH_E_INVALID),
 ])
 def test_workspace_bytes_rejects_bad_params(mutate, code):
@@ -138,6 +142,14 @@ def test_create_rejects_bad_cells_before_any_device_call(case, code):
     with pytest.raises(B.MechError) as e:
         B.create_population(p, pos, rad, typ, vp)
     assert e.value.code == code, B.mech_last_error()
+
+
+def test_prefilter_bound_accepts_large_valid_domains():
+    """Just inside the threshold bound a domain is accepted (S = 256 per um at 30 um:
+    ceil(2^-20 * 2.3e8 * 256) = 56,153 units, + 8192 + 3 < 65,536)."""
+    p, _ = _p()
+    p.domain_lo[2] = -2.3e8
+    assert B.population_workspace_bytes(p, 10) > 0
 
 
 def test_workspace_bytes_scales_with_cells():

@@ -87,7 +87,8 @@ def test_bad_configurations_are_rejected():
     with B.Batch(p, pops[0].n, B.batch_request_voxels(p, pops[0].lo, pops[0].hi), 1) as bt:
         for bad in (B.tuning(6, 4, 4, 0), B.tuning(0, 3, 4, 0), B.tuning(0, 16, 4, 0),
                     B.tuning(0, 4, 16, 0), B.tuning(0, 4, 1, 0), B.tuning(0, 4, 4, 65),
-                    B.tuning(0, 4, 4, -1), B.tuning(0, 4, 4, 0, 20), B.tuning(0, 4, 4, 0, 48)):
+                    B.tuning(0, 4, 4, -1), B.tuning(0, 4, 4, 0, 20), B.tuning(0, 4, 4, 0, 48),
+                    B.tuning(0, 8, 4, 0, 64)):
             with pytest.raises(B.MechError) as e:
                 bt.set_tuning(bad)
             assert e.value.code == B.MECH_E_INVALID
