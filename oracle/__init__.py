@@ -55,7 +55,10 @@ class OracleParams(C.Structure):
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (OpenMP over cells; no fast-math, no contraction)."""
+    """Compile the oracle with gcc (OpenMP over cells; no fast-math, no contraction),
+    and the microenvironment oracle (oracle.diffusion) beside it."""
+    from . import diffusion
+    diffusion.build(force)
     if os.environ.get("MECH_ORACLE_LIB"):
         return _LIB
     if force or not os.path.exists(_LIB):

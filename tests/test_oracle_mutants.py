@@ -1,9 +1,10 @@
 """The oracle's pins catch plausible mistakes.
 
-Each mutant is a copy of oracle/mech_oracle.c with one mistake planted: a dropped term,
-a wrong sign, a wrong index, an off-by-one, a wrong tie-break.  The copy is compiled on
-the CPU and the oracle's pin tests are run against it in a child process (through
-MECH_ORACLE_LIB); at least one pin must fail.  The mutants never leave the CPU.
+Each mutant is a copy of oracle/mech_oracle.c (or oracle/diffusion_oracle.c) with one
+mistake planted: a dropped term, a wrong sign, a wrong index, an off-by-one, a wrong
+tie-break, a wrong boundary row.  The copy is compiled on the CPU and the oracle's pin
+tests are run against it in a child process (through MECH_ORACLE_LIB or
+DIFF_ORACLE_LIB); at least one pin must fail.  The mutants never leave the CPU.
 """
 import os
 import subprocess
@@ -13,6 +14,7 @@ from concurrent.futures import ThreadPoolExecutor
 import pytest
 
 import oracle
+from oracle import diffusion as OD
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "mech_oracle.c")
@@ -95,20 +97,60 @@ MUTANTS = [
 ]
 
 
-def _run_pins(name, text, repl, workdir):
-    src = open(SRC).read()
-    assert src.count(text) == 1, f"mutant '{name}': its text is not unique in mech_oracle.c"
+DIFF_SRC = os.path.join(ROOT, "oracle", "diffusion_oracle.c")
+DIFF_PINS = ["tests/test_oracle_diffusion.py"]
+
+# (name, text in diffusion_oracle.c, replacement); each text occurs exactly once
+DIFF_MUTANTS = [
+    ("first face row without the no-flux correction",
+     "    double diag = b + r;\n    cp[0]", "    double diag = b + 2.0 * r;\n    cp[0]"),
+    ("last face row without the no-flux correction",
+     "        diag = (i == n - 1) ? b + r : b + 2.0 * r;", "        diag = b + 2.0 * r;"),
+    ("decay not split over the three sweeps",
+     "        const double b = 1.0 + p->decay[s] * p->dt / 3.0;",
+     "        const double b = 1.0 + p->decay[s] * p->dt;"),
+    ("diffusion number over dx instead of dx^2",
+     "p->diffusion[s] * p->dt / (p->dx * p->dx);", "p->diffusion[s] * p->dt / p->dx;"),
+    ("back substitution sign",
+     "        u[i * stride] = u[i * stride] - cp[i] * u[(i + 1) * stride];",
+     "        u[i * stride] = u[i * stride] + cp[i] * u[(i + 1) * stride];"),
+    ("first substrate's coefficients for all",
+     "        const double r = p->diffusion[s] *", "        const double r = p->diffusion[0] *"),
+    ("sweeps in reverse order",
+     "        sweep(p, rho, 0);\n        sweep(p, rho, 1);\n        sweep(p, rho, 2);",
+     "        sweep(p, rho, 2);\n        sweep(p, rho, 1);\n        sweep(p, rho, 0);"),
+    ("central difference over dx",
+     "else val = (u[v + st] - u[v - st]) / (2.0 * p->dx);", "else val = (u[v + st] - u[v - st]) / p->dx;"),
+    ("first-face gradient halved",
+     "else if (c == 0) val = (u[v + st] - u[v]) / p->dx;",
+     "else if (c == 0) val = (u[v + st] - u[v]) / (2.0 * p->dx);"),
+    ("gradient y stride from the wrong axis",
+     "    const int64_t stride[3] = {1, nx, (int64_t)nx * ny};",
+     "    const int64_t stride[3] = {1, ny, (int64_t)nx * ny};"),
+]
+
+
+def _run_pins(name, text, repl, workdir, src_path=SRC, pins=PINS, var="MECH_ORACLE_LIB",
+              compile_to=oracle.compile_to):
+    src = open(src_path).read()
+    assert src.count(text) == 1, f"mutant '{name}': its text is not unique in {src_path}"
     tag = "".join(ch if ch.isalnum() else "_" for ch in name)
     c_path = os.path.join(workdir, f"mutant_{tag}.c")
     so_path = os.path.join(workdir, f"mutant_{tag}.so")
     with open(c_path, "w") as f:
         f.write(src.replace(text, repl))
-    oracle.compile_to(c_path, so_path)
-    env = dict(os.environ, MECH_ORACLE_LIB=so_path, OMP_NUM_THREADS="2")
-    res = subprocess.run([sys.executable, "-m", "pytest", *PINS, "-x", "-q", "-m", "not gpu",
+    compile_to(c_path, so_path)
+    env = dict(os.environ, OMP_NUM_THREADS="2")
+    env[var] = so_path
+    res = subprocess.run([sys.executable, "-m", "pytest", *pins, "-x", "-q", "-m", "not gpu",
                           "-p", "no:cacheprovider"], cwd=ROOT, env=env, capture_output=True,
                          text=True, timeout=600)
     return res.returncode, res.stdout[-600:]
+
+
+def _run_diff_pins(name, text, repl, workdir):
+    return _run_pins(name, text, repl, workdir, DIFF_SRC, DIFF_PINS, "DIFF_ORACLE_LIB",
+                     OD.compile_to)
 
 
 def test_every_mutant_fails_a_pin(tmp_path):
@@ -131,3 +173,24 @@ def test_unmutated_copy_passes_the_pins(tmp_path):
 @pytest.mark.parametrize("name,text,repl", MUTANTS, ids=[m[0] for m in MUTANTS])
 def test_mutant_text_is_present(name, text, repl):
     assert open(SRC).read().count(text) == 1
+
+
+def test_every_diffusion_mutant_fails_a_pin(tmp_path):
+    with ThreadPoolExecutor(max_workers=4) as ex:
+        futs = {name: ex.submit(_run_diff_pins, name, text, repl, str(tmp_path))
+                for name, text, repl in DIFF_MUTANTS}
+        results = {name: f.result() for name, f in futs.items()}
+    survivors = [name for name, (rc, _) in results.items() if rc == 0]
+    assert not survivors, f"mutants no pin caught: {survivors}"
+    crashed = {name: out for name, (rc, out) in results.items() if rc not in (0, 1)}
+    assert not crashed, crashed
+
+
+def test_unmutated_diffusion_copy_passes_the_pins(tmp_path):
+    rc, out = _run_diff_pins("identity", "#include <math.h>", "#include <math.h>", str(tmp_path))
+    assert rc == 0, out
+
+
+@pytest.mark.parametrize("name,text,repl", DIFF_MUTANTS, ids=[m[0] for m in DIFF_MUTANTS])
+def test_diffusion_mutant_text_is_present(name, text, repl):
+    assert open(DIFF_SRC).read().count(text) == 1
