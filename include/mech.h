@@ -69,7 +69,12 @@ enum {
        prefiltered four at a time, in-range lists evaluated in batches. */
     MECH_FLAG_SIMPLE_FORCE = 2,   /* one thread per cell, every candidate evaluated inline */
     MECH_FLAG_VOXEL_FORCE = 4,    /* one wave per occupied voxel, neighbourhood in LDS     */
-    MECH_FORCE_KERNEL_MASK = 6
+    MECH_FLAG_PRUNED_FORCE = 8,   /* the default kernel with each cell's neighbour rows
+                                     pruned by its distance to them (the paper's
+                                     neighbour-voxel test, Section 4.2) and x windows
+                                     trimmed to its reach sphere; each lane walks its own
+                                     runs                                                */
+    MECH_FORCE_KERNEL_MASK = 14
 };
 
 typedef struct MechParams {
@@ -93,8 +98,9 @@ typedef struct MechParams {
  * computes the same results up to the summation order of the force sums (bitwise the
  * same for one configuration); it only sets how the work is dealt to the GPU. */
 typedef struct MechTuning {
-    int32_t force_kernel;       /* 0 (list kernel), MECH_FLAG_SIMPLE_FORCE or
-                                   MECH_FLAG_VOXEL_FORCE (the force bits of flags)      */
+    int32_t force_kernel;       /* 0 (list kernel), MECH_FLAG_SIMPLE_FORCE,
+                                   MECH_FLAG_VOXEL_FORCE or MECH_FLAG_PRUNED_FORCE (the
+                                   force bits of flags)                                 */
     int32_t block_waves;        /* wave64s per workgroup of the per-cell kernels:
                                    1, 2, 4 (default) or 8                               */
     int32_t unroll;             /* candidates the list kernel tests per loop trip:
@@ -123,7 +129,9 @@ int32_t mech_device_count(void);
  * what create_population_in requires), or a negative MECH_E_* code. */
 int64_t population_workspace_bytes(const MechParams* params, int64_t n_cells);
 
-/* Create a population on the current HIP device.
+/* Create a population on the current HIP device.  Defined by the method (not the
+ * paper): the cells, their radii and types and the physics of MechParams.  The initial
+ * binning is the paper's voxel container and non-empty voxel list (Section 5.4).
  *   pos            n_cells x 3 doubles, row major, id order; each inside the domain
  *   radius         n_cells doubles > 0
  *   type           n_cells int32 in [0, n_types), or NULL for all type 0
@@ -151,18 +159,26 @@ int create_population_in(const MechParams* params, int64_t n_cells, const double
                          const double* prev_velocity, void* hip_stream, void* workspace,
                          int64_t workspace_bytes, MechPopulation** out);
 
-/* Enqueue n_steps steps (a1-a7 each) on the population's stream and return.  After the
+/* Enqueue n_steps steps (a1-a7 each) on the population's stream and return.  The step is
+ * the paper's "update velocity" region (Sections 4.1 and 5.4) with the force law,
+ * overdamped velocity, Adams-Bashforth update and walls of the method's definition
+ * (file header); the reorder by voxel every step is the layout of Sections 5.4 and 6.
+ * After the
  * first call, each step is one launch of a captured HIP graph.  Makes no allocation. */
 int step_mechanics(MechPopulation* pop, int64_t n_steps);
 
-/* Wait for the stream and copy the state out in id order:
+/* Wait for the stream and copy the state out in id order (defined by this library: the
+ * state the method's steps produce, un-permuted from the voxel order back to ids):
  *   pos  n_cells x 3 (required)
  *   vel  n_cells x 3 or NULL: the velocity of the last step, which is also the v_prev of
  *        the next one (zeros, or the given prev_velocity, before any step)
  * n_cells must equal the population size.  MECH_E_NONFINITE if any value is NaN/Inf. */
 int read_state(MechPopulation* pop, double* pos, double* vel, int64_t n_cells);
 
-/* Wait and copy the binning of the last step (or of creation, before any step):
+/* Wait and copy the binning of the last step (or of creation, before any step); the
+ * voxel of every cell, the voxel starts and the occupied list are the method's (the
+ * paper's voxel container and non-empty voxel list, Section 5.4), the order inside a
+ * voxel the library's:
  *   voxel_of_cell  n_cells uint32, id order (may be NULL)
  *   voxel_start    n_voxels + 1 uint32: exclusive prefix of voxel counts (may be NULL)
  *   sorted_ids     n_cells uint32: ids in storage order (voxel, x slab, id), the x slab
@@ -173,7 +189,8 @@ int read_state(MechPopulation* pop, double* pos, double* vel, int64_t n_cells);
 int read_binning(MechPopulation* pop, uint32_t* voxel_of_cell, uint32_t* voxel_start,
                  uint32_t* sorted_ids, uint32_t* occ, int64_t* n_occ, int64_t* n_voxels);
 
-/* Wait and return the running totals: steps taken, interacting ordered pairs
+/* Defined by this library (measurement): wait and return the running totals: steps
+ * taken, interacting ordered pairs
  * (0 < d^2 < R_A^2), and candidate pairs the force kernel tested: the cells of the 27
  * voxels around each cell, narrowed by the default kernel to the x slabs within reach of
  * the cell (the other kernels test all of them). */

@@ -33,7 +33,8 @@ NOISE = 0.02   # relative timing difference below which the default configuratio
 
 def search_space():
     """Candidate configurations: the list kernel over workgroup size x tile x grid x list
-    length, the inline kernel over workgroup size, the LDS kernel over grid size."""
+    length, its pruned walk over workgroup size x list length, the inline kernel over
+    workgroup size, the LDS kernel over grid size."""
     space = []
     for w in (1, 2, 4, 8):
         for u in (2, 4, 8):
@@ -42,6 +43,9 @@ def search_space():
                     if w == 8 and ln == 64:
                         continue    # more LDS than a compute unit has
                     space.append(B.tuning("cells", w, u, g, ln))
+    for w in (1, 2, 4):
+        for ln in (0, 32):
+            space.append(B.tuning("pruned", w, 4, 0, ln))
     for w in (2, 4, 8):
         space.append(B.tuning("rows", w, 4, 0))
     for g in (2, 4, 8):
@@ -103,6 +107,12 @@ def tune(params: B.MechParams, pops, steps: int = 3, repeats: int = 2, space=Non
     return space[best], rows
 
 
+def chosen_ms(rows, best: B.MechTuning) -> float:
+    """The force-kernel time the tuner measured for the configuration it chose."""
+    want = best.as_dict()
+    return next(r["force_ms"] for r in rows if all(r[k] == v for k, v in want.items()))
+
+
 def tuned(params: B.MechParams, pops, cache: bool = True, log=None, **kw):
     """The cached choice for this workload's shape class, else tune() and cache it."""
     key = shape_class(params, pops)
@@ -120,7 +130,7 @@ def tuned(params: B.MechParams, pops, cache: bool = True, log=None, **kw):
     best, rows = tune(params, pops, log=log, **kw)
     if cache:
         data[key] = {"tuning": best.as_dict(),
-                     "force_ms": min(r["force_ms"] for r in rows),
+                     "force_ms": chosen_ms(rows, best),
                      "seconds": time.perf_counter() - t0}
         os.makedirs(os.path.dirname(path), exist_ok=True)
         tmp = path + ".tmp"

@@ -22,8 +22,10 @@ MECH_AB2_ZERO_HISTORY, MECH_AB2_EULER_START = 0, 1
 MECH_FLAG_NO_GRAPH = 1
 MECH_FLAG_SIMPLE_FORCE = 2
 MECH_FLAG_VOXEL_FORCE = 4
-MECH_FORCE_KERNEL_MASK = 6
-FORCE_KERNELS = {"cells": 0, "rows": MECH_FLAG_SIMPLE_FORCE, "voxel": MECH_FLAG_VOXEL_FORCE}
+MECH_FLAG_PRUNED_FORCE = 8
+MECH_FORCE_KERNEL_MASK = 14
+FORCE_KERNELS = {"cells": 0, "rows": MECH_FLAG_SIMPLE_FORCE, "voxel": MECH_FLAG_VOXEL_FORCE,
+                 "pruned": MECH_FLAG_PRUNED_FORCE}
 MECH_ABI_VERSION = 2
 
 PRECISIONS = {"fp64": MECH_FP64, "fp32": MECH_FP32, "fp32k": MECH_FP32_KAHAN}
@@ -42,6 +44,12 @@ EXPORTS = ("mech_last_error", "mech_abi_version", "mech_device_count",
            "batch_get_tuning", "batch_set_tuning", "batch_sync", "batch_stream", "destroy_batch",
            "batch_budget_capacity", "create_batch_budget", "batch_capacity", "batch_mark_clock",
            "batch_slot_done_ms")
+# every symbol include/microenv.h declares
+MICROENV_EXPORTS = ("create_microenvironment", "microenvironment_step", "microenvironment_gradients",
+                    "read_density", "read_gradients", "write_density", "microenvironment_profile",
+                    "microenvironment_device_arrays", "microenvironment_stream",
+                    "destroy_microenvironment")
+MECH_MAX_SUBSTRATES = 16
 
 
 class MechError(RuntimeError):
@@ -56,6 +64,13 @@ class MechParams(C.Structure):
                 ("voxel_size", C.c_double), ("dt", C.c_double), ("c_rep", C.c_double),
                 ("rel_adh_distance", C.c_double), ("n_types", C.c_int32), ("reserved", C.c_int32),
                 ("c_adh", C.c_double * 64)]
+
+
+class MechMicroenvParams(C.Structure):
+    _fields_ = [("abi_version", C.c_int32), ("n_substrates", C.c_int32), ("dims", C.c_int32 * 3),
+                ("reserved", C.c_int32), ("voxel_size", C.c_double), ("dt", C.c_double),
+                ("diffusion", C.c_double * MECH_MAX_SUBSTRATES),
+                ("decay", C.c_double * MECH_MAX_SUBSTRATES)]
 
 
 class MechTuning(C.Structure):
@@ -141,6 +156,16 @@ def lib():
             "batch_capacity": (C.c_int, [vp, lp, lp, ip, lp]),
             "batch_mark_clock": (C.c_int, [vp]),
             "batch_slot_done_ms": (C.c_int, [vp, C.c_int32, dp]),
+            "create_microenvironment": (C.c_int, [P(MechMicroenvParams), dp, vp, P(vp)]),
+            "microenvironment_step": (C.c_int, [vp, C.c_int64]),
+            "microenvironment_gradients": (C.c_int, [vp]),
+            "read_density": (C.c_int, [vp, dp, C.c_int64]),
+            "read_gradients": (C.c_int, [vp, dp, C.c_int64]),
+            "write_density": (C.c_int, [vp, dp, C.c_int64]),
+            "microenvironment_profile": (C.c_int, [vp, C.c_int64, dp]),
+            "microenvironment_device_arrays": (C.c_int, [vp, P(vp), P(vp)]),
+            "microenvironment_stream": (C.c_void_p, [vp]),
+            "destroy_microenvironment": (C.c_int, [vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -544,6 +569,101 @@ class Batch:
         if getattr(self, "h", None):
             _ck(lib().destroy_batch(self.h))
             self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------- microenvironment
+
+def microenv_params(dims, voxel_size=20.0, dt=0.01, diffusion=(1e5,), decay=(0.1,)) -> MechMicroenvParams:
+    p = MechMicroenvParams()
+    p.abi_version = MECH_ABI_VERSION
+    D = np.atleast_1d(np.asarray(diffusion, dtype=np.float64))
+    lam = np.atleast_1d(np.asarray(decay, dtype=np.float64))
+    if D.shape != lam.shape:
+        raise ValueError("diffusion and decay need one value per substrate")
+    p.n_substrates = int(D.size)
+    for a in range(3):
+        p.dims[a] = int(dims[a])
+    p.voxel_size, p.dt = float(voxel_size), float(dt)
+    for k in range(min(D.size, MECH_MAX_SUBSTRATES)):
+        p.diffusion[k] = float(D[k])
+        p.decay[k] = float(lam[k])
+    return p
+
+
+def microenv_params_of(env) -> MechMicroenvParams:
+    """From a workloads.Microenv description."""
+    return microenv_params(env.dims, env.dx, env.dt, env.diffusion, env.decay)
+
+
+class Microenv:
+    """A substrate mesh on the device (create_microenvironment ... destroy)."""
+
+    def __init__(self, params: MechMicroenvParams, density=None, stream=None):
+        self.params = params
+        nx, ny, nz = (int(params.dims[a]) for a in range(3))
+        self.shape = (int(params.n_substrates), nz, ny, nx)
+        self.n_values = int(np.prod(self.shape))
+        rho = None
+        if density is not None:
+            rho = np.ascontiguousarray(density, dtype=np.float64).reshape(-1)
+            if rho.size != self.n_values:
+                raise ValueError(f"density holds {rho.size} values, the mesh {self.n_values}")
+        h = C.c_void_p()
+        _ck(lib().create_microenvironment(C.byref(params), _d(rho), stream, C.byref(h)))
+        self.h = h
+
+    def step(self, n_steps=1):
+        _ck(lib().microenvironment_step(self.h, int(n_steps)))
+
+    def compute_gradients(self):
+        _ck(lib().microenvironment_gradients(self.h))
+
+    def density(self):
+        out = np.empty(self.n_values, np.float64)
+        _ck(lib().read_density(self.h, _d(out), out.size))
+        return out.reshape(self.shape)
+
+    def gradients(self):
+        out = np.empty(3 * self.n_values, np.float64)
+        _ck(lib().read_gradients(self.h, _d(out), out.size))
+        s, nz, ny, nx = self.shape
+        return out.reshape(s, 3, nz, ny, nx)
+
+    def set_density(self, density):
+        rho = np.ascontiguousarray(density, dtype=np.float64).reshape(-1)
+        _ck(lib().write_density(self.h, _d(rho), rho.size))
+
+    def profile(self, n_steps=1):
+        """Mean ms per launch of the x, y and z solves and of the gradient kernel."""
+        ms = np.zeros(4, np.float64)
+        _ck(lib().microenvironment_profile(self.h, int(n_steps), _d(ms)))
+        return tuple(float(x) for x in ms)
+
+    def device_arrays(self):
+        d, g = C.c_void_p(), C.c_void_p()
+        _ck(lib().microenvironment_device_arrays(self.h, C.byref(d), C.byref(g)))
+        return d.value, g.value
+
+    @property
+    def stream(self) -> int:
+        return int(lib().microenvironment_stream(self.h) or 0)
+
+    def close(self):
+        if getattr(self, "h", None):
+            h, self.h = self.h, None
+            _ck(lib().destroy_microenvironment(h))
 
     def __enter__(self):
         return self

@@ -1,4 +1,5 @@
-"""Builds libmech.so (the HIP kernels and C ABI) in-tree for gfx950 with hipcc."""
+"""Builds libmech.so (the HIP kernels and C ABI: the mechanics step and the
+microenvironment solver) in-tree for gfx950 with hipcc."""
 from __future__ import annotations
 
 import os
@@ -9,6 +10,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc", "mech.hip")
+SOURCES = [SRC, os.path.join(HERE, "csrc", "microenv.hip")]
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libmech.so")
 
@@ -28,15 +30,15 @@ def hipcc() -> str:
 
 
 def build(verbose: bool = False, extra=()) -> str:
-    """Compile csrc/mech.hip into paper_2306_11544_amd/libmech.so (always recompiles)."""
+    """Compile csrc/*.hip into paper_2306_11544_amd/libmech.so (always recompiles)."""
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIP_FLAGS, *extra, "-I", INCLUDE, SRC, "-o", tmp]
+    cmd = [hipcc(), *HIP_FLAGS, *extra, "-I", INCLUDE, *SOURCES, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError(f"hipcc failed building {SRC}")
+        raise RuntimeError(f"hipcc failed building {' '.join(SOURCES)}")
     os.replace(tmp, LIB)
     return LIB
 

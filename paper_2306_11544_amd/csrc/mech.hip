@@ -1353,7 +1353,8 @@ __global__ __launch_bounds__(WPB * WAVE) void k_force_rows(PhysArgs P, ForceArgs
 // IND: the cells are left in storage order; candidate slot j of the sorted order is read
 // through perm[j] (the locality study).  The candidates, their order and the arithmetic
 // are those of the reordered path, so the results are bitwise the same.
-template <int PREC, bool MULTI, typename VPT, int FC_UNROLL, int LIST, bool IND = false>
+// PRUNE: the per-cell pruned walk (below) instead of the slab window walk.
+template <int PREC, bool MULTI, typename VPT, int FC_UNROLL, int LIST, bool IND = false, bool PRUNE = false>
 __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceArgs<VPT>& a, uint32_t i,
                                                  uint32_t n, uint32_t* const list0, uint2* const rng0,
                                                  uint32_t& inter, uint32_t& cand)
@@ -1364,7 +1365,25 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
     const SlotDesc& d = a.slots[a.slot_of[ii]];
     const bool valid = in_pop && d.active_now != 0;
     const Cellgeo g = cell_geo(a.vid_sorted[ii] / XSUB, d);
-    // The candidates of each neighbour row that can hold a partner, the paper's test of
+    // Slab window (default walk): the x slabs of each neighbour row that can hold a
+    // partner: every interacting j has |x_j - x_i| < alpha (r_i + r_max).  The window is
+    // taken in FP64 from the exact position and widened by a margin that covers the
+    // float rounding of the FP32 decision (a few ulp of |x|) and of R_A, so it never drops
+    // a pair either precision counts.  w0, w1: the window's first and one-past-last slab,
+    // counted from the first slab of the row's voxels and clipped to them.
+    uint32_t w0 = 0, w1 = 0;
+    if constexpr (!PRUNE) {
+        const double xg = a.XS[0][ii];
+        const double reach = P.alpha * (a.R[ii] + d.r_max);
+        const double m = reach * (1.0 + 1e-6) + 1e-3 + 5e-7 * (fabs(xg) + reach);
+        const double xs = (double)XSUB * d.inv_h;
+        const double lo_s = floor((xg - d.lo[0] - m) * xs), hi_s = floor((xg - d.lo[0] + m) * xs);
+        const double s_min = (double)(XSUB * (uint32_t)g.x0), s_max = (double)(XSUB * (uint32_t)g.x1 + XSUB - 1);
+        w0 = (uint32_t)(fmax(lo_s, s_min) - s_min);            // first slab, from the row's start
+        w1 = (uint32_t)(fmin(hi_s, s_max) - s_min) + 1u;       // one past the last slab
+    }
+    // Pruned walk: the candidates of each neighbour row that can hold a partner, the
+    // paper's test of
     // whether a neighbour voxel can hold interacting cells (Section 4.2) done per cell and
     // row: every interacting j has d_ij < reach = alpha (r_i + r_max), so with rho the
     // distance in y-z from the cell to the row's voxels, a row with rho >= reach holds no
@@ -1377,7 +1396,7 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
     // So a window never drops a pair that either precision counts.  The non-empty runs,
     // in row order (dz, then dy), go to the lane's LDS slots rng0[k * WAVE], k < nr.
     uint32_t nr = 0;
-    if (valid) {
+    if (PRUNE && valid) {
         const double xg = a.XS[0][ii], yg = a.XS[1][ii], zg = a.XS[2][ii];
         const double reach = P.alpha * (a.R[ii] + d.r_max);
         const double pm = fmax(fabs(xg), fmax(fabs(yg), fabs(zg)));
@@ -1562,59 +1581,116 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
         }
     };
 
-    // The walk: each lane takes its own runs one after the other, FC_UNROLL candidates
-    // per trip, so a trip of the wave serves every lane that still has candidates,
-    // whichever row it is in (lanes of one wave sit in two or three voxels and at
-    // different depths of them, so their runs differ in number and length).  A trip reads
-    // FC_UNROLL consecutive entries of the quantised shadow from j; those at or past the
-    // run's end e are not listed (the array is padded, so the reads stay inside it, and a
-    // lane that has finished re-reads from its last e).  When j passes e the lane moves
-    // to its next run.  Candidates are listed in run order, so each sum is still taken in
-    // the fixed neighbour order.
-    uint32_t k = 0;
-    uint2 run = nr > 0 ? rng0[0] : make_uint2(0u, 0u);
-    uint32_t j = run.x, e = run.y;
-#pragma unroll 1
-    while (__any(k < nr)) {
-        const uint32_t lim = k < nr ? min(e - j, (uint32_t)FC_UNROLL) : 0u;
-        if constexpr (IND) {
-            // gathers through the sorted order: no locality between consecutive lanes
-#pragma unroll
-            for (int u = 0; u < FC_UNROLL; ++u) {
-                uint32_t jj = ii;
-                bool in = false;
-                if ((uint32_t)u < lim) {
-                    jj = a.perm[j + u];
-                    in = near(a.QS[jj]);
+    if constexpr (!PRUNE) {
+        // The slab walk: the lanes take the 9 rows together; in each, a lane reads its
+        // window's candidates FC_UNROLL per trip (lanes of one slab read the same
+        // candidate at the same time, one cache line).  The candidate range [j, e) of
+        // neighbour row q (empty outside the grid); the next row's range is read while
+        // the current row is walked.
+        auto range = [&](int q, uint32_t& j, uint32_t& e) {
+            const int64_t r0 = valid ? row_first(g, d, q) : -1;
+            j = r0 < 0 ? 0u : a.voxel_start[XSUB * r0 + w0];
+            e = r0 < 0 ? 0u : a.voxel_start[XSUB * r0 + w1];
+        };
+        uint32_t j_next, e_next;
+        range(0, j_next, e_next);
+        for (int q = 0; q < 9; ++q) {
+            uint32_t j = j_next;
+            const uint32_t e = e_next;
+            if (q < 8) range(q + 1, j_next, e_next);
+            cand += e - j;
+            if constexpr (IND) {
+                // gathers through the sorted order: no locality between consecutive lanes
+                for (; j < e; ++j) {
+                    const uint32_t jj = a.perm[j];
+                    push(jj, near(a.QS[jj]));
+                    if (full()) flush(KEEP);
                 }
-                push(jj, in);
+                continue;
             }
-        } else {
-            uint2 c[FC_UNROLL];
+            const uint2* sp = a.QS + j;
+            for (; j + FC_UNROLL <= e; j += FC_UNROLL, sp += FC_UNROLL) {
+                uint2 c[FC_UNROLL];
 #pragma unroll
-            for (int u = 0; u < FC_UNROLL; ++u) c[u] = a.QS[j + u];
-            if constexpr (PACK) {
+                for (int u = 0; u < FC_UNROLL; ++u) c[u] = sp[u];
+                if constexpr (PACK) {
 #pragma unroll
-                for (int g4 = 0; g4 < FC_UNROLL; g4 += 4) {
-                    uint32_t mk = 0;
+                    for (int g4 = 0; g4 < FC_UNROLL; g4 += 4) {
+                        uint32_t m = 0;
 #pragma unroll
-                    for (int u = g4; u < FC_UNROLL && u < g4 + 4; ++u)
-                        mk |= ((uint32_t)u < lim && near(c[u]) ? 1u : 0u) << (u - g4);
-                    push(((j + g4) << 4) | mk, mk != 0u);
+                        for (int u = g4; u < FC_UNROLL && u < g4 + 4; ++u) m |= (near(c[u]) ? 1u : 0u) << (u - g4);
+                        push(((j + g4) << 4) | m, m != 0u);
+                    }
+                } else {
+#pragma unroll
+                    for (int u = 0; u < FC_UNROLL; ++u) push(j + u, near(c[u]));
+                }
+                if (full()) flush(KEEP);
+            }
+            for (; j < e; ++j, ++sp) {
+                const bool in = near(*sp);
+                if constexpr (PACK)
+                    push((j << 4) | 1u, in);
+                else
+                    push(j, in);
+                if (full()) flush(KEEP);
+            }
+        }
+    } else {
+        // The walk: each lane takes its own runs one after the other, FC_UNROLL candidates
+        // per trip, so a trip of the wave serves every lane that still has candidates,
+        // whichever row it is in (lanes of one wave sit in two or three voxels and at
+        // different depths of them, so their runs differ in number and length).  A trip reads
+        // FC_UNROLL consecutive entries of the quantised shadow from j; those at or past the
+        // run's end e are not listed (the array is padded, so the reads stay inside it, and a
+        // lane that has finished re-reads from its last e).  When j passes e the lane moves
+        // to its next run.  Candidates are listed in run order, so each sum is still taken in
+        // the fixed neighbour order.
+        uint32_t k = 0;
+        uint2 run = nr > 0 ? rng0[0] : make_uint2(0u, 0u);
+        uint32_t j = run.x, e = run.y;
+    #pragma unroll 1
+        while (__any(k < nr)) {
+            const uint32_t lim = k < nr ? min(e - j, (uint32_t)FC_UNROLL) : 0u;
+            if constexpr (IND) {
+                // gathers through the sorted order: no locality between consecutive lanes
+    #pragma unroll
+                for (int u = 0; u < FC_UNROLL; ++u) {
+                    uint32_t jj = ii;
+                    bool in = false;
+                    if ((uint32_t)u < lim) {
+                        jj = a.perm[j + u];
+                        in = near(a.QS[jj]);
+                    }
+                    push(jj, in);
                 }
             } else {
-#pragma unroll
-                for (int u = 0; u < FC_UNROLL; ++u) push(j + u, (uint32_t)u < lim && near(c[u]));
+                uint2 c[FC_UNROLL];
+    #pragma unroll
+                for (int u = 0; u < FC_UNROLL; ++u) c[u] = a.QS[j + u];
+                if constexpr (PACK) {
+    #pragma unroll
+                    for (int g4 = 0; g4 < FC_UNROLL; g4 += 4) {
+                        uint32_t mk = 0;
+    #pragma unroll
+                        for (int u = g4; u < FC_UNROLL && u < g4 + 4; ++u)
+                            mk |= ((uint32_t)u < lim && near(c[u]) ? 1u : 0u) << (u - g4);
+                        push(((j + g4) << 4) | mk, mk != 0u);
+                    }
+                } else {
+    #pragma unroll
+                    for (int u = 0; u < FC_UNROLL; ++u) push(j + u, (uint32_t)u < lim && near(c[u]));
+                }
             }
+            j += FC_UNROLL;
+            if (k < nr && j >= e) {
+                ++k;
+                run = k < nr ? rng0[k * WAVE] : make_uint2(e, e);
+                j = run.x;
+                e = run.y;
+            }
+            if (full()) flush(KEEP);
         }
-        j += FC_UNROLL;
-        if (k < nr && j >= e) {
-            ++k;
-            run = k < nr ? rng0[k * WAVE] : make_uint2(e, e);
-            j = run.x;
-            e = run.y;
-        }
-        if (full()) flush(KEEP);
     }
     flush(0);
     if (valid) {
@@ -1628,24 +1704,28 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
     }
 }
 
-template <int PREC, bool MULTI, typename VPT, int WPB, int UNROLL, int LIST, bool IND = false>
+template <int PREC, bool MULTI, typename VPT, int WPB, int UNROLL, int LIST, bool IND = false, bool PRUNE = false>
 __global__ __launch_bounds__(WPB * WAVE) void k_force_cells(PhysArgs P, ForceArgs<VPT> a)
 {
     static_assert(2 * UNROLL <= LIST, "a trip must fit the list above the flush mark");
     constexpr uint32_t TB = WPB * WAVE;
     __shared__ uint32_t s_list[WPB][LIST][WAVE];
-    __shared__ uint2 s_rng[WPB][9][WAVE];
     const uint32_t n = a.hdr[H_CELLS];
     const uint32_t nb = (n + TB - 1) / TB;
     uint32_t* const list0 = &s_list[threadIdx.x / WAVE][0][threadIdx.x & (WAVE - 1)];
-    uint2* const rng0 = &s_rng[threadIdx.x / WAVE][0][threadIdx.x & (WAVE - 1)];
+    uint2* rng0 = nullptr;
+    if constexpr (PRUNE) {
+        // the pruned walk's runs; the slab walk takes no LDS beyond its lists
+        __shared__ uint2 s_rng[WPB][9][WAVE];
+        rng0 = &s_rng[threadIdx.x / WAVE][0][threadIdx.x & (WAVE - 1)];
+    }
     uint32_t inter = 0, cand = 0;
     // rounds of gridDim.x blocks, renumbered per round as in k_force_rows
     for (uint32_t lb0 = 0; lb0 < nb; lb0 += gridDim.x) {
         const uint32_t active = min(gridDim.x, nb - lb0);
         if (blockIdx.x >= active) break;
         const uint32_t i = (lb0 + xcd_block(blockIdx.x, active)) * TB + threadIdx.x;
-        force_cells_cell<PREC, MULTI, VPT, UNROLL, LIST, IND>(P, a, i, n, list0, rng0, inter, cand);
+        force_cells_cell<PREC, MULTI, VPT, UNROLL, LIST, IND, PRUNE>(P, a, i, n, list0, rng0, inter, cand);
     }
     add_stats(a.stats, inter, cand);
 }
@@ -2226,15 +2306,33 @@ uint32_t force_cell_grid(const MechBatch* B, int wpb)
     return std::min(tiles, cap);
 }
 
-template <int PREC, bool MULTI, typename VPT, int WPB, int LIST>
-void launch_cells_l(MechBatch* B, const ForceArgs<VPT>& a)
+template <int PREC, bool MULTI, typename VPT, int WPB, int LIST, bool PRUNE>
+void launch_cells_p(MechBatch* B, const ForceArgs<VPT>& a)
 {
     const dim3 grid(force_cell_grid(B, WPB)), block(WPB * WAVE);
     switch (B->tune.unroll) {
-    case 2: hipLaunchKernelGGL((k_force_cells<PREC, MULTI, VPT, WPB, 2, LIST>), grid, block, 0, B->stream, B->phys, a); break;
-    case 8: hipLaunchKernelGGL((k_force_cells<PREC, MULTI, VPT, WPB, 8, LIST>), grid, block, 0, B->stream, B->phys, a); break;
-    default: hipLaunchKernelGGL((k_force_cells<PREC, MULTI, VPT, WPB, 4, LIST>), grid, block, 0, B->stream, B->phys, a); break;
+    case 2:
+        hipLaunchKernelGGL((k_force_cells<PREC, MULTI, VPT, WPB, 2, LIST, false, PRUNE>), grid, block, 0, B->stream,
+                           B->phys, a);
+        break;
+    case 8:
+        hipLaunchKernelGGL((k_force_cells<PREC, MULTI, VPT, WPB, 8, LIST, false, PRUNE>), grid, block, 0, B->stream,
+                           B->phys, a);
+        break;
+    default:
+        hipLaunchKernelGGL((k_force_cells<PREC, MULTI, VPT, WPB, 4, LIST, false, PRUNE>), grid, block, 0, B->stream,
+                           B->phys, a);
+        break;
     }
+}
+
+template <int PREC, bool MULTI, typename VPT, int WPB, int LIST>
+void launch_cells_l(MechBatch* B, const ForceArgs<VPT>& a)
+{
+    if (B->prm.flags & MECH_FLAG_PRUNED_FORCE)
+        launch_cells_p<PREC, MULTI, VPT, WPB, LIST, true>(B, a);
+    else
+        launch_cells_p<PREC, MULTI, VPT, WPB, LIST, false>(B, a);
 }
 
 template <int PREC, bool MULTI, typename VPT, int WPB>
@@ -2607,6 +2705,55 @@ void push_slot(MechBatch* B, int32_t id)
                        B->slots[id].d);
 }
 
+// The physics constants the kernels take, in both precisions.
+PhysArgs phys_args(const MechParams& p)
+{
+    PhysArgs a{};
+    a.dt = p.dt;
+    a.c_rep = p.c_rep;
+    a.alpha = p.rel_adh_distance;
+    a.c_adh0 = p.c_adh[0];
+    a.c_rep_f = (float)p.c_rep;
+    a.alpha_f = (float)p.rel_adh_distance;
+    a.inv_alpha_f = 1.0f / a.alpha_f;
+    a.c_adh0_f = (float)p.c_adh[0];
+    a.n_types = p.n_types;
+    return a;
+}
+
+// The descriptor of a simulation of n cells (largest radius rmax) on a grid of dims
+// voxels over [lo, hi], placed at the given cell and voxel offsets of the arena.
+SlotDesc slot_desc(const MechParams& prm, const double lo[3], const double hi[3], const int32_t dims[3],
+                   double rmax, int64_t n, int64_t n_steps, bool has_vprev, uint32_t cell_off, uint32_t voxel_off)
+{
+    SlotDesc d{};
+    for (int a = 0; a < 3; ++a) {
+        d.lo[a] = lo[a];
+        d.hi[a] = hi[a];
+    }
+    d.inv_h = 1.0 / prm.voxel_size;
+    d.r_max = rmax;
+    d.r_max_f = (float)rmax;
+    // the largest power of two with h S <= 2^13, and the margin for float positions
+    // (2^-20 P S units, P the largest coordinate magnitude of the domain)
+    d.q_scale = (float)quant_scale(prm.voxel_size);
+    {
+        double pm = 0.0;
+        for (int a = 0; a < 3; ++a) pm = std::max(pm, std::max(std::fabs(lo[a]), std::fabs(hi[a])));
+        d.q_pad = (float)std::ceil(pm * (double)d.q_scale * 0x1p-20);
+    }
+    d.nx = dims[0];
+    d.ny = dims[1];
+    d.nz = dims[2];
+    d.voxel_off = voxel_off;
+    d.cell_off = cell_off;
+    d.prev_cell_off = d.cell_off;
+    d.n_cells = (uint32_t)n;
+    d.steps_left = n_steps < 0 ? -1 : (int32_t)std::min<int64_t>(n_steps, INT32_MAX);
+    d.euler = (prm.ab2_start == MECH_AB2_EULER_START && !has_vprev) ? 1 : 0;
+    return d;
+}
+
 int create_batch_impl(const MechParams* params, int64_t max_cells, int64_t max_voxels, int32_t max_slots,
                       void* stream, void* workspace, int64_t ws_bytes, MechBatch** out)
 {
@@ -2624,15 +2771,7 @@ int create_batch_impl(const MechParams* params, int64_t max_cells, int64_t max_v
     B->cap_voxels = max_voxels;
     B->cap_slots = max_slots;
     B->slots.resize((size_t)max_slots);
-    B->phys.dt = params->dt;
-    B->phys.c_rep = params->c_rep;
-    B->phys.alpha = params->rel_adh_distance;
-    B->phys.c_adh0 = params->c_adh[0];
-    B->phys.c_rep_f = (float)params->c_rep;
-    B->phys.alpha_f = (float)params->rel_adh_distance;
-    B->phys.inv_alpha_f = 1.0f / B->phys.alpha_f;
-    B->phys.c_adh0_f = (float)params->c_adh[0];
-    B->phys.n_types = params->n_types;
+    B->phys = phys_args(*params);
     B->L = make_layout(*params, max_cells, (uint64_t)max_voxels, max_slots);
     auto bail = [&](int code) {
         release(B);
@@ -2816,31 +2955,7 @@ int admit_impl(MechBatch* B, const double lo[3], const double hi[3], int64_t n, 
     if (id < 0) return fail(MECH_E_FULL, "all %d slots are in use", B->cap_slots);
     HostSlot& s = B->slots[id];
     SlotDesc& d = s.d;
-    d = SlotDesc{};
-    for (int a = 0; a < 3; ++a) {
-        d.lo[a] = lo[a];
-        d.hi[a] = hi[a];
-    }
-    d.inv_h = 1.0 / B->prm.voxel_size;
-    d.r_max = rmax;
-    d.r_max_f = (float)rmax;
-    // the largest power of two with h S <= 2^13, and the margin for float positions
-    // (2^-20 P S units, P the largest coordinate magnitude of the domain)
-    d.q_scale = (float)quant_scale(B->prm.voxel_size);
-    {
-        double pm = 0.0;
-        for (int a = 0; a < 3; ++a) pm = std::max(pm, std::max(std::fabs(lo[a]), std::fabs(hi[a])));
-        d.q_pad = (float)std::ceil(pm * (double)d.q_scale * 0x1p-20);
-    }
-    d.nx = dims[0];
-    d.ny = dims[1];
-    d.nz = dims[2];
-    d.voxel_off = B->n_voxels;
-    d.cell_off = B->n_cells;
-    d.prev_cell_off = d.cell_off;
-    d.n_cells = (uint32_t)n;
-    d.steps_left = n_steps < 0 ? -1 : (int32_t)std::min<int64_t>(n_steps, INT32_MAX);
-    d.euler = (B->prm.ab2_start == MECH_AB2_EULER_START && vprev == nullptr) ? 1 : 0;
+    d = slot_desc(B->prm, lo, hi, dims, rmax, n, n_steps, vprev != nullptr, B->n_cells, B->n_voxels);
     s.used = true;
     s.retired = false;
     s.reported = false;
@@ -3119,6 +3234,14 @@ int64_t batch_bytes(const MechParams* params, int64_t max_cells, int64_t max_vox
 }  // namespace
 
 // ------------------------------------------------------------------------ C ABI
+
+// The library's other source files (the microenvironment solver) report their errors
+// through the same thread-local text; not exported.
+__attribute__((visibility("hidden"))) int mech_report_error(int code, const char* text)
+{
+    g_err = text;
+    return code;
+}
 
 extern "C" {
 
@@ -3665,7 +3788,8 @@ int batch_get_tuning(MechBatch* B, MechTuning* out)
 int batch_set_tuning(MechBatch* B, const MechTuning* t)
 {
     if (!B || !t) return fail(MECH_E_INVALID, "batch or tuning is NULL");
-    if (t->force_kernel != 0 && t->force_kernel != MECH_FLAG_SIMPLE_FORCE && t->force_kernel != MECH_FLAG_VOXEL_FORCE)
+    if (t->force_kernel != 0 && t->force_kernel != MECH_FLAG_SIMPLE_FORCE && t->force_kernel != MECH_FLAG_VOXEL_FORCE &&
+        t->force_kernel != MECH_FLAG_PRUNED_FORCE)
         return fail(MECH_E_INVALID, "force_kernel %d unknown", t->force_kernel);
     if (t->block_waves != 1 && t->block_waves != 2 && t->block_waves != 4 && t->block_waves != 8)
         return fail(MECH_E_INVALID, "block_waves %d not in {1, 2, 4, 8}", t->block_waves);

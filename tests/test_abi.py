@@ -14,8 +14,8 @@ from paper_2306_11544_amd import binding as B
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def declared_functions():
-    text = open(os.path.join(ROOT, "include", "mech.h")).read()
+def declared_functions(header="mech.h"):
+    text = open(os.path.join(ROOT, "include", header)).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b([a-z_][a-z0-9_]*)\s*\(", text)) -
                   {"sizeof", "defined", "if", "return"})
@@ -36,6 +36,54 @@ def test_library_exports_every_declared_symbol():
         assert name in syms, name
 
 
+def test_microenv_header_declares_what_binding_exports_and_library_exports_it():
+    assert declared_functions("microenv.h") == sorted(B.MICROENV_EXPORTS)
+    lib = B.lib()
+    out = subprocess.run(["nm", "-D", "--defined-only", B.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    syms = {line.split()[-1] for line in out.splitlines() if line.strip()}
+    for name in B.MICROENV_EXPORTS:
+        assert hasattr(lib, name) and name in syms, name
+    # the library's internal error hook is not exported
+    assert not any("report_error" in x for x in syms)
+
+
+def test_microenv_params_struct_matches_header_layout():
+    # 6 int32 + 2 double + 2 x 16 double
+    assert C.sizeof(B.MechMicroenvParams) == 24 + 16 + 256
+    assert B.MechMicroenvParams.voxel_size.offset == 24
+    assert B.MechMicroenvParams.decay.offset == 24 + 16 + 128
+
+
+@pytest.mark.parametrize("change", [
+    {"n_substrates": 0}, {"n_substrates": 17}, {"dims": (0, 4, 4)}, {"dims": (4097, 1, 1)},
+    {"dims": (2048, 2048, 1024)}, {"voxel_size": 0.0}, {"dt": -1.0}, {"reserved": 1},
+    {"abi_version": 1}, {"diffusion": -1.0}, {"decay": float("nan")}])
+def test_microenv_rejects_bad_parameters_on_the_host(change):
+    p = B.microenv_params((8, 6, 4), diffusion=(1e3,), decay=(0.1,))
+    for k, v in change.items():
+        if k == "dims":
+            for a in range(3):
+                p.dims[a] = v[a]
+        elif k in ("diffusion", "decay"):
+            getattr(p, k)[0] = v
+        else:
+            setattr(p, k, v)
+    h = C.c_void_p()
+    rc = B.lib().create_microenvironment(C.byref(p), None, None, C.byref(h))
+    assert rc == B.MECH_E_INVALID, B.mech_last_error()
+    assert not h.value
+
+
+def test_microenv_rejects_a_nonfinite_density_on_the_host():
+    p = B.microenv_params((3, 2, 2), diffusion=(1e3,), decay=(0.1,))
+    rho = np.zeros(12)
+    rho[7] = np.inf
+    h = C.c_void_p()
+    rc = B.lib().create_microenvironment(C.byref(p), B._d(rho), None, C.byref(h))
+    assert rc == B.MECH_E_INVALID and "density[7]" in B.mech_last_error()
+
+
 def test_params_struct_matches_header_layout():
     # 4 int32 + 6 double + 4 double + 2 int32 + 64 double
     assert C.sizeof(B.MechParams) == 16 + 48 + 32 + 8 + 512
@@ -54,7 +102,7 @@ def test_tuning_search_space_is_valid():
     space = A.search_space()
     assert len({tuple(t.as_dict().values()) for t in space}) == len(space)
     for t in space:
-        assert t.force_kernel in (0, B.MECH_FLAG_SIMPLE_FORCE, B.MECH_FLAG_VOXEL_FORCE)
+        assert t.force_kernel in (0, B.MECH_FLAG_SIMPLE_FORCE, B.MECH_FLAG_VOXEL_FORCE, B.MECH_FLAG_PRUNED_FORCE)
         assert t.block_waves in (1, 2, 4, 8) and t.unroll in (2, 4, 8)
         assert 0 <= t.blocks_per_cu <= 64
         assert t.list_len in (0, 16, 32, 64) and 2 * t.unroll <= (t.list_len or 16)

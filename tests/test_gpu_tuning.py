@@ -53,14 +53,16 @@ def test_every_configuration_agrees_with_default():
 
 @pytest.mark.parametrize("prec", [B.MECH_FP64, B.MECH_FP32, B.MECH_FP32_KAHAN])
 def test_list_kernel_equals_inline_kernel_bitwise(prec):
-    """The list kernel's prefilter and slab window drop no interacting pair and its lists
-    keep the neighbour order: at every list length and tile its trajectories are bitwise
-    those of the inline kernel, which evaluates every pair of the 27 voxels in order."""
+    """The list kernel's prefilter and slab window (or, pruned, its row test and trimmed
+    windows) drop no interacting pair and its lists keep the neighbour order: at every
+    list length and tile its trajectories are bitwise those of the inline kernel, which
+    evaluates every pair of the 27 voxels in order."""
     require_gpu()
     pops = _sims(3, 3000, 8000, seed=4650)
     ref, inter_ref = _run(pops, B.tuning("rows", 4, 4, 0), 15, prec)
     for cfg in [("cells", 4, 4, 0, 16), ("cells", 4, 4, 0, 32), ("cells", 4, 4, 0, 64),
-                ("cells", 1, 8, 0, 64), ("cells", 8, 2, 16, 32), ("cells", 2, 8, 0, 16)]:
+                ("cells", 1, 8, 0, 64), ("cells", 8, 2, 16, 32), ("cells", 2, 8, 0, 16),
+                ("pruned", 4, 4, 0, 16), ("pruned", 1, 8, 0, 32), ("pruned", 2, 2, 0, 64)]:
         say("list kernel", prec, cfg)
         got, inter = _run(pops, B.tuning(*cfg), 15, prec)
         assert inter == inter_ref
@@ -85,7 +87,7 @@ def test_bad_configurations_are_rejected():
     pops = _sims(1, 1000, 1000, seed=4800)
     p = _params()
     with B.Batch(p, pops[0].n, B.batch_request_voxels(p, pops[0].lo, pops[0].hi), 1) as bt:
-        for bad in (B.tuning(6, 4, 4, 0), B.tuning(0, 3, 4, 0), B.tuning(0, 16, 4, 0),
+        for bad in (B.tuning(6, 4, 4, 0), B.tuning(10, 4, 4, 0), B.tuning(0, 3, 4, 0), B.tuning(0, 16, 4, 0),
                     B.tuning(0, 4, 16, 0), B.tuning(0, 4, 1, 0), B.tuning(0, 4, 4, 65),
                     B.tuning(0, 4, 4, -1), B.tuning(0, 4, 4, 0, 20), B.tuning(0, 4, 4, 0, 48),
                     B.tuning(0, 8, 4, 0, 64)):

@@ -16,6 +16,11 @@ workloads the mechanics step is benchmarked on:
             radii as sph100k, one type, 200 steps
   batch256  256 independent sph100k-like spheroids, sizes log-uniform in [1k, 100k]
   serve     Poisson request stream, sizes log-uniform in [1k, 500k], steps U{10..1000}
+  env75     substrate mesh of the microenvironment solver: 75 x 75 x 75 voxels of 20 um
+            (the paper's 75^3 mesh over the 1500 um box of its sample project), an
+            oxygen-like substrate (D = 1e5 um^2/min, decay 0.1 /min), dt = 0.01 min;
+            further substrates draw D and decay log-uniformly; densities are a seeded
+            smooth field plus white noise
 
 Draw order for every population: radii, then types, then positions.  Ball positions
 are drawn by rejection from the bounding cube.  Generator: numpy PCG64.
@@ -190,3 +195,53 @@ def config(name: str) -> Population:
     if name == "tumour1m":
         return tumour()
     raise KeyError(name)
+
+
+@dataclass
+class Microenv:
+    """A substrate mesh's inputs: dims (nx, ny, nz), voxel edge dx (um), time step dt
+    (min), per-substrate diffusion (um^2/min) and decay (1/min), densities
+    (n_substrates, nz, ny, nx) f64, and the step count of the workload."""
+    name: str
+    dims: tuple
+    dx: float
+    dt: float
+    diffusion: tuple
+    decay: tuple
+    density: np.ndarray
+    steps: int
+
+    @property
+    def n_substrates(self) -> int:
+        return len(self.diffusion)
+
+    @property
+    def voxels(self) -> int:
+        return int(np.prod(self.dims))
+
+
+def microenv(dims=(75, 75, 75), n_substrates: int = 1, seed: int = 6, steps: int = 100,
+             dx: float = 20.0, dt: float = 0.01) -> Microenv:
+    """Substrate 0 is oxygen-like (D = 1e5 um^2/min, decay 0.1 /min); substrate k >= 1 has
+    D = 10^U(2, 5) and decay 10^U(-3, 0).  Each density is 38 (0.6 + 0.4 u), u a sum of
+    eight random cosine modes of wavenumber 0..4 per axis rescaled to [0, 1], plus 5%
+    uniform noise (so the field holds every spatial frequency of the mesh)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    D = [1e5] + [float(10.0 ** rng.uniform(2.0, 5.0)) for _ in range(n_substrates - 1)]
+    lam = [0.1] + [float(10.0 ** rng.uniform(-3.0, 0.0)) for _ in range(n_substrates - 1)]
+    nx, ny, nz = dims
+    ax = [(np.arange(n) + 0.5) / n for n in (nz, ny, nx)]
+    rho = np.empty((n_substrates, nz, ny, nx), np.float64)
+    for s in range(n_substrates):
+        f = np.zeros((nz, ny, nx))
+        for _ in range(8):
+            k = rng.integers(0, 5, 3)
+            ph = rng.uniform(0, 2 * np.pi, 3)
+            f += (np.cos(np.pi * k[0] * ax[0] + ph[0])[:, None, None]
+                  * np.cos(np.pi * k[1] * ax[1] + ph[1])[None, :, None]
+                  * np.cos(np.pi * k[2] * ax[2] + ph[2])[None, None, :])
+        f = (f - f.min()) / max(f.max() - f.min(), 1e-300)
+        u = 0.95 * f + 0.05 * rng.random((nz, ny, nx))
+        rho[s] = 38.0 * (0.6 + 0.4 * u)
+    return Microenv(f"env{nx}x{ny}x{nz}s{n_substrates}", tuple(dims), dx, dt, tuple(D), tuple(lam),
+                    rho, steps)
