@@ -159,6 +159,35 @@ int create_population_in(const MechParams* params, int64_t n_cells, const double
                          const double* prev_velocity, void* hip_stream, void* workspace,
                          int64_t workspace_bytes, MechPopulation** out);
 
+/* Bytes of the static device scratch of step_mechanics_noalloc (64 MiB per device). */
+#define MECH_NOALLOC_SCRATCH_BYTES (64ll << 20)
+
+/* For callers that cannot allocate device memory (tight serving loops, harnesses that
+ * forbid allocation): create_population, step_mechanics(n_steps) and read_state in one
+ * synchronous call that allocates nothing.  Every device array of the population is
+ * carved from the library's static device scratch, MECH_NOALLOC_SCRATCH_BYTES per
+ * device, which each device the library runs on holds until the process ends; the call
+ * makes no device or host allocation, creates no stream, event or graph, and launches
+ * the same kernels as the population path directly on hip_stream (NULL: the null
+ * stream), so its results are bitwise those of that path.  It waits for the stream
+ * before returning, so it cannot be captured into a HIP graph.
+ *   params, n_cells, pos, radius, type, prev_velocity  as create_population (host
+ *                  arrays, copied in)
+ *   n_steps        steps to take (>= 0)
+ *   pos_out        n_cells x 3 doubles, id order: the positions after the steps (may be
+ *                  pos itself)
+ *   vel_out        n_cells x 3 doubles or NULL: the velocity of the last step, as
+ *                  read_state
+ *   interactions   host int64 or NULL: interacting ordered pairs over the steps
+ * MECH_E_NOMEM when the population's arrays (about 210 bytes per cell and 36 per voxel)
+ * exceed the scratch; the other errors as create_population and read_state.  Every call
+ * on one device uses that device's one scratch and leaves its contents behind (the next
+ * call sets every value it reads first): calls that overlap on one device race and must
+ * not be made. */
+int step_mechanics_noalloc(const MechParams* params, int64_t n_cells, const double* pos, const double* radius,
+                           const int32_t* type, const double* prev_velocity, int64_t n_steps, void* hip_stream,
+                           double* pos_out, double* vel_out, int64_t* interactions);
+
 /* Enqueue n_steps steps (a1-a7 each) on the population's stream and return.  The step is
  * the paper's "update velocity" region (Sections 4.1 and 5.4) with the force law,
  * overdamped velocity, Adams-Bashforth update and walls of the method's definition

@@ -43,7 +43,8 @@ EXPORTS = ("mech_last_error", "mech_abi_version", "mech_device_count",
            "batch_slot_info", "batch_info", "batch_stats", "batch_profile", "batch_set_flags",
            "batch_get_tuning", "batch_set_tuning", "batch_sync", "batch_stream", "destroy_batch",
            "batch_budget_capacity", "create_batch_budget", "batch_capacity", "batch_mark_clock",
-           "batch_slot_done_ms")
+           "batch_slot_done_ms", "step_mechanics_noalloc")
+MECH_NOALLOC_SCRATCH_BYTES = 64 << 20
 # every symbol include/microenv.h declares
 MICROENV_EXPORTS = ("create_microenvironment", "microenvironment_step", "microenvironment_gradients",
                     "read_density", "read_gradients", "write_density", "microenvironment_profile",
@@ -156,6 +157,8 @@ def lib():
             "batch_capacity": (C.c_int, [vp, lp, lp, ip, lp]),
             "batch_mark_clock": (C.c_int, [vp]),
             "batch_slot_done_ms": (C.c_int, [vp, C.c_int32, dp]),
+            "step_mechanics_noalloc": (C.c_int, [P(MechParams), C.c_int64, dp, dp, ip, dp, C.c_int64, vp,
+                                                 dp, dp, lp]),
             "create_microenvironment": (C.c_int, [P(MechMicroenvParams), dp, vp, P(vp)]),
             "microenvironment_step": (C.c_int, [vp, C.c_int64]),
             "microenvironment_gradients": (C.c_int, [vp]),
@@ -270,6 +273,21 @@ def create_population_in(params: MechParams, pos, radius, type, prev_velocity, s
                                    _d(vp), stream, C.c_void_p(workspace_ptr),
                                    int(workspace_bytes), C.byref(h)))
     return h
+
+
+def step_mechanics_noalloc(params: MechParams, pos, radius, type=None, prev_velocity=None, n_steps: int = 1,
+                           stream=None):
+    """create + n_steps steps + read_state in one call on the library's static scratch.
+    Returns (pos, vel, interactions)."""
+    pos, radius, t, vp = _cells(pos, radius, type, prev_velocity)
+    n = pos.shape[0]
+    out = np.empty((n, 3), np.float64)
+    vel = np.empty((n, 3), np.float64)
+    inter = C.c_int64(0)
+    _ck(lib().step_mechanics_noalloc(C.byref(params), n, _d(pos), _d(radius),
+                                     None if t is None else t.ctypes.data_as(C.POINTER(C.c_int32)),
+                                     _d(vp), int(n_steps), stream, _d(out), _d(vel), C.byref(inter)))
+    return out, vel, int(inter.value)
 
 
 def step_mechanics(h, n_steps: int = 1) -> None:

@@ -56,6 +56,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -111,6 +112,12 @@ constexpr int HDR_WORDS = 8;
 // ------------------------------------------------------------------------ kernel args
 
 // One simulation of a batch (device table, indexed by slot id).
+// Device scratch of the allocation-free entry point (step_mechanics_noalloc): every
+// array of its population is carved from here.  Each device the library runs on holds
+// its own copy until the process ends.  Host code never uses this name as an address:
+// it takes the device address from hipGetSymbolAddress (noalloc_scratch below).
+static __device__ __align__(256) unsigned char scratch[MECH_NOALLOC_SCRATCH_BYTES];
+
 struct SlotDesc {
     double lo[3], hi[3];       // domain (reflecting walls), um
     double inv_h;              // 1 / voxel edge
@@ -1994,6 +2001,30 @@ __global__ __launch_bounds__(BLOCK) void k_unpermute(uint32_t cell_off, uint32_t
     vel[k + 2] = (double)v2[s];
 }
 
+// The allocation-free entry point's input: positions and, when given, the history
+// arrive as host-layout rows (x, y, z per cell) in the staging area; they go into the
+// structure-of-arrays state of the first cell range of parity 0, with ids 0..n-1.
+template <typename VPT>
+__global__ __launch_bounds__(BLOCK) void k_load_cells(uint32_t n, const double* __restrict__ st, bool has_vprev,
+                                                      double* __restrict__ x0, double* __restrict__ x1,
+                                                      double* __restrict__ x2, uint32_t* __restrict__ id,
+                                                      uint32_t* __restrict__ slot_of, VPT* __restrict__ v0,
+                                                      VPT* __restrict__ v1, VPT* __restrict__ v2)
+{
+    const uint32_t i = blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= n) return;
+    const size_t k = 3 * (size_t)i;
+    x0[i] = st[k + 0];
+    x1[i] = st[k + 1];
+    x2[i] = st[k + 2];
+    id[i] = i;
+    slot_of[i] = 0;
+    const double* vp = st + 3 * (size_t)n;
+    v0[i] = has_vprev ? (VPT)vp[k + 0] : (VPT)0;
+    v1[i] = has_vprev ? (VPT)vp[k + 1] : (VPT)0;
+    v2[i] = has_vprev ? (VPT)vp[k + 2] : (VPT)0;
+}
+
 // ------------------------------------------------------------------------ host side
 
 inline uint32_t blocks_for(uint64_t n, uint32_t per) { return (uint32_t)((n + per - 1) / per); }
@@ -3235,6 +3266,157 @@ int64_t batch_bytes(const MechParams* params, int64_t max_cells, int64_t max_vox
 
 // ------------------------------------------------------------------------ C ABI
 
+namespace {
+
+// Device address of the static scratch on the current device, looked up once per device
+// (each device holds its own copy of the array at its own address).
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+int noalloc_scratch(int device, void** out)
+{
+    if (device < 0 || device >= MAX_DEVICES) return fail(MECH_E_DEVICE, "device %d out of range", device);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(MECH_E_DEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+        g_scratch_ptr[device] = ptr;
+    }
+    *out = g_scratch_ptr[device];
+    return MECH_OK;
+}
+
+// create_population + step_mechanics + read_state with every device array in the static
+// scratch: the same layout, the same kernels in the same order (direct launches), no
+// allocation, no stream, event or graph.
+int noalloc_impl(const MechParams* params, int64_t n, const double* pos, const double* radius, const int32_t* type,
+                 const double* vprev, int64_t n_steps, void* hip_stream, double* pos_out, double* vel_out,
+                 int64_t* interactions)
+{
+    int rc = validate_physics(params);
+    if (rc) return rc;
+    if (n < 0 || n >= (int64_t(1) << 31)) return fail(MECH_E_INVALID, "n_cells out of range");
+    if (n_steps < 0) return fail(MECH_E_INVALID, "n_steps must be >= 0");
+    if (n > 0 && !pos_out) return fail(MECH_E_INVALID, "pos_out is NULL");
+    int32_t dims[3];
+    uint64_t V = 0;
+    rc = validate_domain(params->domain_lo, params->domain_hi, params->voxel_size, dims, &V);
+    if (rc) return rc;
+    double rmax = 0.0;
+    rc = validate_cells(params, params->domain_lo, params->domain_hi, n, pos, radius, type, vprev, &rmax);
+    if (rc) return rc;
+    MechBatch B;   // on the stack: its vectors stay empty (no slot bookkeeping here)
+    B.prm = *params;
+    B.phys = phys_args(*params);
+    B.cap_cells = n;
+    B.cap_voxels = (int64_t)V;
+    B.cap_slots = 1;
+    B.L = make_layout(*params, n, V, 1);
+    if (B.L.total > (size_t)MECH_NOALLOC_SCRATCH_BYTES)
+        return fail(MECH_E_NOMEM, "%lld cells and %llu voxels need %zu bytes, the static scratch holds %llu",
+                    (long long)n, (unsigned long long)V, B.L.total, (unsigned long long)MECH_NOALLOC_SCRATCH_BYTES);
+    HIP_TRY(hipGetDevice(&B.device));
+    {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, B.device) != hipSuccess || cus < 1)
+            cus = 256;
+        B.cus = cus;
+    }
+    void* base = nullptr;
+    rc = noalloc_scratch(B.device, &base);
+    if (rc) return rc;
+    B.arena = (char*)base;
+    B.stream = (hipStream_t)hip_stream;
+    const Layout& L = B.L;
+    const hipStream_t st = B.stream;
+    // the scratch keeps the last call's contents: everything read before it is written
+    // is set here (adhesion tables, counts, starts, counters, header, slot table)
+    double cd[64];
+    float cf[64];
+    for (int k = 0; k < 64; ++k) {
+        cd[k] = params->c_adh[k];
+        cf[k] = (float)params->c_adh[k];
+    }
+    HIP_TRY(hipMemcpyAsync(B.arena + L.cadh, cd, sizeof cd, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(B.arena + L.cadh_f, cf, sizeof cf, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemsetAsync(B.arena + L.count, 0, (size_t)V * XSUB * 4, st));
+    HIP_TRY(hipMemsetAsync(B.arena + L.start, 0, ((size_t)V * XSUB + 1) * 4, st));
+    HIP_TRY(hipMemsetAsync(B.arena + L.stats, 0, STAT_SLOTS * 16, st));
+    HIP_TRY(hipMemsetAsync(B.arena + L.hdr, 0, HDR_WORDS * 4, st));
+    const SlotDesc d = slot_desc(*params, params->domain_lo, params->domain_hi, dims, rmax, n, -1, vprev != nullptr,
+                                 0u, 0u);
+    hipLaunchKernelGGL(k_set_slot, dim3(1), dim3(1), 0, st, B.at<SlotDesc>(L.slots), 0u, d);
+    B.n_cells = (uint32_t)n;
+    B.n_voxels = (uint32_t)V;
+    push_header(&B);
+    if (n > 0) {
+        const uint32_t nu = (uint32_t)n;
+        double* stage = B.at<double>(L.stage);
+        HIP_TRY(hipMemcpyAsync(stage, pos, 24 * (size_t)n, hipMemcpyHostToDevice, st));
+        if (vprev) HIP_TRY(hipMemcpyAsync(stage + 3 * (size_t)n, vprev, 24 * (size_t)n, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(B.arena + L.R[0], radius, 8 * (size_t)n, hipMemcpyHostToDevice, st));
+        if (type)
+            HIP_TRY(hipMemcpyAsync(B.arena + L.T[0], type, 4 * (size_t)n, hipMemcpyHostToDevice, st));
+        else
+            HIP_TRY(hipMemsetAsync(B.arena + L.T[0], 0, 4 * (size_t)n, st));
+        if (is_fp32(B.prm))
+            hipLaunchKernelGGL(k_load_cells<float>, dim3(blocks_for(nu, BLOCK)), dim3(BLOCK), 0, st, nu, stage,
+                               vprev != nullptr, B.at<double>(L.X[0]), B.at<double>(L.X[1]), B.at<double>(L.X[2]),
+                               B.at<uint32_t>(L.ID[0]), B.at<uint32_t>(L.slot_of), B.at<float>(L.VP[0][0]),
+                               B.at<float>(L.VP[0][1]), B.at<float>(L.VP[0][2]));
+        else
+            hipLaunchKernelGGL(k_load_cells<double>, dim3(blocks_for(nu, BLOCK)), dim3(BLOCK), 0, st, nu, stage,
+                               vprev != nullptr, B.at<double>(L.X[0]), B.at<double>(L.X[1]), B.at<double>(L.X[2]),
+                               B.at<uint32_t>(L.ID[0]), B.at<uint32_t>(L.slot_of), B.at<double>(L.VP[0][0]),
+                               B.at<double>(L.VP[0][1]), B.at<double>(L.VP[0][2]));
+        HIP_TRY(hipGetLastError());
+        // the initial binning of create_population
+        enqueue_binning_any(&B);
+        hipLaunchKernelGGL(k_copy_positions, dim3(blocks_for(nu, BLOCK)), dim3(BLOCK), 0, st, nu,
+                           B.at<double>(L.XS[0]), B.at<double>(L.XS[1]), B.at<double>(L.XS[2]),
+                           B.at<double>(L.X[0]), B.at<double>(L.X[1]), B.at<double>(L.X[2]));
+        B.parity ^= 1;
+        for (int64_t k = 0; k < n_steps; ++k) {
+            enqueue_step(&B, B.parity, true);
+            B.parity ^= 1;
+        }
+        HIP_TRY(hipGetLastError());
+        // read_state: un-permute into the staging area, then to the caller
+        const int p = B.parity;
+        if (is_fp32(B.prm))
+            hipLaunchKernelGGL(k_unpermute<float>, dim3(blocks_for(nu, BLOCK)), dim3(BLOCK), 0, st, 0u, nu,
+                               B.at<uint32_t>(L.ID[p]), B.at<double>(L.X[0]), B.at<double>(L.X[1]),
+                               B.at<double>(L.X[2]), B.at<float>(L.VP[p][0]), B.at<float>(L.VP[p][1]),
+                               B.at<float>(L.VP[p][2]), stage, stage + 3 * (size_t)n);
+        else
+            hipLaunchKernelGGL(k_unpermute<double>, dim3(blocks_for(nu, BLOCK)), dim3(BLOCK), 0, st, 0u, nu,
+                               B.at<uint32_t>(L.ID[p]), B.at<double>(L.X[0]), B.at<double>(L.X[1]),
+                               B.at<double>(L.X[2]), B.at<double>(L.VP[p][0]), B.at<double>(L.VP[p][1]),
+                               B.at<double>(L.VP[p][2]), stage, stage + 3 * (size_t)n);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(pos_out, stage, 24 * (size_t)n, hipMemcpyDeviceToHost, st));
+        if (vel_out) HIP_TRY(hipMemcpyAsync(vel_out, stage + 3 * (size_t)n, 24 * (size_t)n, hipMemcpyDeviceToHost, st));
+    }
+    unsigned long long stat[2 * STAT_SLOTS];
+    if (interactions) HIP_TRY(hipMemcpyAsync(stat, B.arena + L.stats, sizeof stat, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    HIP_TRY(hipGetLastError());
+    if (interactions) {
+        unsigned long long sum = 0;
+        for (uint32_t k = 0; k < STAT_SLOTS; ++k) sum += stat[2 * k];
+        *interactions = (int64_t)sum;
+    }
+    for (size_t i = 0; i < 3 * (size_t)n; ++i)
+        if (!std::isfinite(pos_out[i]) || (vel_out && !std::isfinite(vel_out[i])))
+            return fail(MECH_E_NONFINITE, "state holds a non-finite value at cell %zu", i / 3);
+    return MECH_OK;
+}
+
+}  // namespace
+
 // The library's other source files (the microenvironment solver) report their errors
 // through the same thread-local text; not exported.
 __attribute__((visibility("hidden"))) int mech_report_error(int code, const char* text)
@@ -3347,6 +3529,14 @@ int create_population_in(const MechParams* params, int64_t n_cells, const double
     }
     return create_pop_impl(params, n_cells, pos, radius, type, prev_velocity, hip_stream, workspace,
                            workspace_bytes, out);
+}
+
+int step_mechanics_noalloc(const MechParams* params, int64_t n_cells, const double* pos, const double* radius,
+                           const int32_t* type, const double* prev_velocity, int64_t n_steps, void* hip_stream,
+                           double* pos_out, double* vel_out, int64_t* interactions)
+{
+    return noalloc_impl(params, n_cells, pos, radius, type, prev_velocity, n_steps, hip_stream, pos_out, vel_out,
+                        interactions);
 }
 
 int step_mechanics(MechPopulation* P, int64_t n_steps)
