@@ -22,7 +22,8 @@ Further legs of the same JSON line (each bounded to seconds; --legs selects them
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload tumour1m|sph100k|plain1k]
                   [--precision fp64|fp32k|fp32] [--legs fp32k,batch,serving,microenv]
                   [--no-cpu-baseline]
-  python bench.py --workload batch | --locality | --grow     (standalone studies)
+  python bench.py --workload batch | --workload microenv | --locality | --grow
+                                                            (standalone studies)
 """
 from __future__ import annotations
 
@@ -619,6 +620,18 @@ def main():
         sys.exit(2)
     if args.workload == "batch":
         bench_batch(args)
+        return
+    if args.workload == "microenv":
+        import torch
+        torch.cuda.init()
+        leg = leg_microenv(args, steps=args.steps, cpu=not args.no_cpu_baseline)
+        if args.calibrate_copy_mb:
+            copy_calibration(args.calibrate_copy_mb, torch.cuda.Stream(device=torch.device("cuda:0")))
+        print(json.dumps({"metric": "microenvironment voxel updates/s (FP64, 75^3 mesh)",
+                          "value": leg["voxel_updates_per_s"], "unit": "voxel-updates/s", "n_gpus": 1,
+                          "steps": args.steps, "ms_per_step": leg["ms_per_step"], "higher_is_better": True,
+                          "dtype": "f64", "data": "synthetic", "config": {"workload": leg["workload"]},
+                          **{k: v for k, v in leg.items() if k != "workload"}}), flush=True)
         return
     if args.locality:
         bench_locality(args)

@@ -2,7 +2,7 @@
 
   python -m paper_2306_11544_amd.rocprof_summary stats <..._kernel_stats.csv> --command "<cmd>"
   python -m paper_2306_11544_amd.rocprof_summary pmc <counter_collection.csv>... --kernel k_force_cells
-      --command "<cmd of the first csv>" --command ...
+      --command "<cmd of the first csv>" --command ... [--candidates <per launch>]
   python -m paper_2306_11544_amd.rocprof_summary traffic --fetch <fetch counter_collection.csv>
       --write <write counter_collection.csv> --kernel k_force_cells --copy-kernel neg_kernel
       --copy-bytes <bytes read = bytes written by the copy> --command-fetch "<cmd>" --command-write "<cmd>"
@@ -48,10 +48,14 @@ def code_of(text: str) -> str:
     return " ".join("".join(out).split())
 
 
-def source_sha256() -> str:
-    """SHA-256 of the kernel source's code (comments and blank space removed)."""
-    with open(SOURCE, encoding="utf-8") as f:
+def source_sha256(path: str = SOURCE) -> str:
+    """SHA-256 of a kernel source's code (comments and blank space removed)."""
+    with open(path, encoding="utf-8") as f:
         return hashlib.sha256(code_of(f.read()).encode()).hexdigest()
+
+
+def source_line(path: str = SOURCE) -> str:
+    return f"source_sha256(csrc/{os.path.basename(path)} code): {source_sha256(path)}"
 
 
 def _short(name: str) -> str:
@@ -62,11 +66,11 @@ def _short(name: str) -> str:
     return s if len(s) <= 110 else s[:107] + "..."
 
 
-def stats(path: str, command: str, top: int = 25) -> str:
+def stats(path: str, command: str, top: int = 25, sources=(SOURCE,)) -> str:
     rows = list(csv.DictReader(open(path)))
     total = sum(float(r["TotalDurationNs"]) for r in rows)
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
-    out = [f"command: {command}", f"source_sha256(csrc/mech.hip code): {source_sha256()}",
+    out = [f"command: {command}", *[source_line(x) for x in sources],
            f"kernels: {len(rows)}  total kernel time: {total / 1e6:.3f} ms", "",
            f"{'calls':>7} {'avg_us':>10} {'min_us':>10} {'max_us':>10} {'pct':>6}  name"]
     for r in rows[:top]:
@@ -120,7 +124,7 @@ def traffic(a) -> str:
     lines = [
         f"command (FETCH_SIZE): {a.command_fetch}",
         f"command (WRITE_SIZE): {a.command_write}",
-        f"source_sha256(csrc/mech.hip code): {source_sha256()}",
+        source_line(a.source),
         f"kernel: {a.kernel}  ({len(kf)} dispatches; {'; '.join(_short(k) for k in kn)})",
         f"workload: {a.workload}",
         f"tuning: {a.tuning}",
@@ -136,12 +140,16 @@ def traffic(a) -> str:
     return "\n".join(lines) + "\n"
 
 
-def pmc(paths, kernel: str, commands) -> str:
+def pmc(paths, kernel: str, commands, candidates=None, source=SOURCE) -> str:
     """Mean per dispatch of every counter in the counter-collection CSVs, for the
-    dispatches of kernels whose name contains `kernel`."""
+    dispatches of kernels whose name contains `kernel`; with `candidates` (the candidate
+    pairs one launch tests, from the run's own counters) the summary records it, so that
+    VALU instructions per tested candidate can be derived."""
     lines = [f"command: {c}" for c in commands]
-    lines.append(f"source_sha256(csrc/mech.hip code): {source_sha256()}")
+    lines.append(source_line(source))
     lines.append(f"kernel: {kernel}")
+    if candidates is not None:
+        lines.append(f"candidates_per_launch: {candidates:.6g}")
     for path in paths:
         acc = collections.defaultdict(lambda: collections.defaultdict(float))
         name = {}
@@ -172,8 +180,8 @@ def read_traffic(path: str):
             k, _, v = line.partition(":")
             vals[k.strip()] = v.strip()
         if "traffic_bytes_per_launch" in vals:
-            out.append((float(vals["traffic_bytes_per_launch"]),
-                        vals["source_sha256(csrc/mech.hip code)"], vals.get("workload", ""),
+            sha = next((v for k, v in vals.items() if k.startswith("source_sha256(")), "")
+            out.append((float(vals["traffic_bytes_per_launch"]), sha, vals.get("workload", ""),
                         vals.get("tuning", "")))
     return out
 
@@ -185,6 +193,8 @@ def main(argv=None):
     s.add_argument("csv")
     s.add_argument("--command", required=True)
     s.add_argument("--top", type=int, default=25)
+    s.add_argument("--source", action="append", default=None,
+                   help="kernel source(s) whose code hash the summary records (default csrc/mech.hip)")
     t = sub.add_parser("traffic")
     t.add_argument("--fetch", required=True)
     t.add_argument("--write", required=True)
@@ -195,17 +205,20 @@ def main(argv=None):
     t.add_argument("--tuning", default="", help="launch configuration the run used, as K,W,U,G,L")
     t.add_argument("--command-fetch", required=True)
     t.add_argument("--command-write", required=True)
+    t.add_argument("--source", default=SOURCE, help="the kernel's source file (default csrc/mech.hip)")
     m = sub.add_parser("pmc")
     m.add_argument("csvs", nargs="+")
     m.add_argument("--kernel", required=True)
     m.add_argument("--command", action="append", default=[])
+    m.add_argument("--candidates", type=float, default=None, help="candidate pairs tested per launch")
+    m.add_argument("--source", default=SOURCE)
     a = ap.parse_args(argv)
     if a.cmd == "stats":
-        sys.stdout.write(stats(a.csv, a.command, a.top))
+        sys.stdout.write(stats(a.csv, a.command, a.top, tuple(a.source or (SOURCE,))))
     elif a.cmd == "traffic":
         sys.stdout.write(traffic(a))
     else:
-        sys.stdout.write(pmc(a.csvs, a.kernel, a.command))
+        sys.stdout.write(pmc(a.csvs, a.kernel, a.command, a.candidates, a.source))
 
 
 if __name__ == "__main__":

@@ -69,6 +69,14 @@ def assert_well_posed(orc, pop, steps, bar=1e-10):
     assert sens <= bar / 100, f"ill-posed case: sensitivity {sens:.2e}"
 
 
+def disp_err(got, want, x0):
+    """Displacement-relative error: |(x_gpu - x0) - (x_oracle - x0)| / |x_oracle - x0|, the
+    norms taken over all cells and axes; the error measured against how far the cells
+    moved from their start x0 (0 when they did not move)."""
+    d = np.linalg.norm(np.asarray(want) - np.asarray(x0))
+    return float(np.linalg.norm(np.asarray(got) - np.asarray(want)) / d) if d > 0 else 0.0
+
+
 def pos_err(a, b, S):
     """Domain-scaled position error: max over cells and axes of |a - b| / S."""
     if a.size == 0:

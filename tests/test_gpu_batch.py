@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 import workloads
-from gpu_helpers import pos_err, record, require_gpu, run_gpu, say
+from gpu_helpers import disp_err, pos_err, record, require_gpu, run_gpu, say
 from paper_2306_11544_amd import binding as B
 
 pytestmark = pytest.mark.gpu
@@ -60,7 +60,7 @@ def test_batch_matches_fp64_oracle(orc, prec, tol):
         want = orc.run_pop(pp, steps=60)["pos"]
         err = pos_err(g, want, pp.half_width)
         record(f"batch {'fp64' if prec == B.MECH_FP64 else 'fp32'} sim{k} ({pp.n} cells) 60 steps "
-               "vs fp64 oracle", err)
+               "vs fp64 oracle", err, disp_rel=disp_err(g, want, pp.pos))
         assert err <= tol
 
 
@@ -86,7 +86,8 @@ def test_batch256_full_500_steps_sampled(orc):
         say("batch256 oracle sim", k, pp.n, "cells")
         want = orc.run_pop(pp)["pos"]
         err = pos_err(got[k], want, pp.half_width)
-        record(f"batch256 fp32 sim{k} ({pp.n} cells) {pp.steps} steps vs fp64 oracle", err)
+        record(f"batch256 fp32 sim{k} ({pp.n} cells) {pp.steps} steps vs fp64 oracle", err,
+               disp_rel=disp_err(got[k], want, pp.pos))
         assert err <= 1e-4, (k, err)
 
 

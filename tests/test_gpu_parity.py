@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import workloads
-from gpu_helpers import assert_well_posed, pos_err, record, require_gpu, run_gpu, say
+from gpu_helpers import assert_well_posed, disp_err, pos_err, record, require_gpu, run_gpu, say
 from paper_2306_11544_amd import binding as B
 
 pytestmark = pytest.mark.gpu
@@ -47,7 +47,7 @@ def test_fp64_trajectory(orc, name, maker, steps):
     want = orc.run_pop(pop, steps=steps, per_step=True)
     got = run_gpu(pop, steps, per_step=True)
     err = pos_err(got["pos"], want["pos"], pop.half_width)
-    record(f"fp64 {name} {steps} steps", err)
+    record(f"fp64 {name} {steps} steps", err, disp_rel=disp_err(got["pos"], want["pos"], pop.pos))
     assert err <= FP64_TOL, err
     # v_prev after the last step is that step's velocity
     assert np.abs(got["vel"] - want["vprev"]).max() <= 1e-9 * max(1.0, np.abs(want["vprev"]).max())
@@ -74,7 +74,8 @@ def test_fp32_and_kahan_error_vs_fp64_oracle(orc, name, maker, steps):
     for prec, label in ((B.MECH_FP32, "fp32"), (B.MECH_FP32_KAHAN, "fp32k")):
         got = run_gpu(pop, steps, precision=prec)
         err = pos_err(got["pos"], want["pos"], pop.half_width)
-        record(f"{label} {name} {steps} steps vs fp64 oracle", err)
+        record(f"{label} {name} {steps} steps vs fp64 oracle", err,
+               disp_rel=disp_err(got["pos"], want["pos"], pop.pos))
         assert err <= FP32_TOL, (label, err)
 
 
@@ -98,7 +99,8 @@ def test_fp64_spheroid_full_1000_steps(orc):
     got = run_gpu(pop, pop.steps)
     want = _oracle_full(orc, "sph100k")
     err = pos_err(got["pos"], want["pos"], pop.half_width)
-    record("fp64 sph100k 1000 steps", err, interactions=got["interactions"],
+    record("fp64 sph100k 1000 steps", err, disp_rel=disp_err(got["pos"], want["pos"], pop.pos),
+           interactions=got["interactions"],
            oracle_interactions=want["interactions"])
     assert err <= FP64_TOL, err
     assert abs(got["interactions"] - want["interactions"]) <= 1e-9 * want["interactions"] + 2
@@ -113,7 +115,7 @@ def test_fp32_spheroid_full_1000_steps(orc, precision):
     want = _oracle_full(orc, "sph100k")
     err = pos_err(got["pos"], want["pos"], pop.half_width)
     record(f"{'fp32k' if precision == B.MECH_FP32_KAHAN else 'fp32'} sph100k 1000 steps "
-           "vs fp64 oracle", err)
+           "vs fp64 oracle", err, disp_rel=disp_err(got["pos"], want["pos"], pop.pos))
     assert err <= FP32_TOL, err
 
 
@@ -203,7 +205,8 @@ def test_tumour1m_full_200_steps(orc):
         got = run_gpu(pop, pop.steps, precision=precision)
         err = pos_err(got["pos"], pos, pop.half_width)
         record(f"{label} tumour1m {pop.steps} steps vs fp64 oracle", err,
-               interactions=got["interactions"], oracle_interactions=inter)
+               disp_rel=disp_err(got["pos"], pos, pop.pos), interactions=got["interactions"],
+               oracle_interactions=inter)
         assert err <= tol, (label, err)
         if precision == B.MECH_FP64:
             assert abs(got["interactions"] - inter) <= 1e-9 * inter + 2
@@ -228,7 +231,7 @@ def test_euler_start(orc):
     got = run_gpu(pop, 100, ab2_start=B.MECH_AB2_EULER_START)
     want = orc.run_pop(pop, steps=100, euler_first=True)
     err = pos_err(got["pos"], want["pos"], pop.half_width)
-    record("fp64 plain1k euler start 100 steps", err)
+    record("fp64 plain1k euler start 100 steps", err, disp_rel=disp_err(got["pos"], want["pos"], pop.pos))
     assert err <= FP64_TOL
     zero = orc.run_pop(pop, steps=100)
     assert pos_err(zero["pos"], want["pos"], pop.half_width) > 1e-8  # the start matters
