@@ -30,6 +30,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdint>
@@ -63,6 +64,10 @@ int fail(int code, const char* fmt, ...)
 
 constexpr int LINES = 64;          // mesh lines per block (one wave64)
 constexpr int LDS_MAX_N = 128;     // longest line staged in LDS (64 x 128 doubles = 64 KiB)
+constexpr int SEG_MAX = 8;         // segments per line in k_solve_seg
+constexpr int SEG_MIN_LEN = 10;    // shortest segment worth a thread of its own
+constexpr int SEG_MAX_N = 112;     // longest line of k_solve_seg: the tile and the maps in LDS
+constexpr int SEG_LEN_MAX = 16;    // longest segment: ceil(112 / 8) = 14 fits
 constexpr int GRAD_BLOCK = 256;
 constexpr int MAX_DIM = 4096;
 
@@ -219,6 +224,125 @@ __global__ __launch_bounds__(LINES) void k_solve_yz(SolveArgs a, int64_t lines)
     }
 }
 
+// Solve along any axis with every line cut into segments (n <= SEG_MAX_N).  A block takes
+// LB lines and nseg segments of each: thread t works on line t % LB and segment t / LB,
+// so a line's segments run in parallel.  Both recurrences are affine in their running
+// value (y_i = m_i r y_{i-1} + m_i rho_i forward, u_i = y_i - c_i u_{i+1} back), so each
+// thread first composes its segment's map, the maps of the segments before it give the
+// value its segment starts from (at most nseg - 1 compositions), and the segment is then
+// recomputed from that value with the recurrence as written.  The chain of dependent
+// operations per line shrinks from 2n to about 4n / nseg + 2 nseg.  A thread holds its
+// segment's values and factors in registers from one batch of loads.  The block's lines
+// sit in LDS as tile[i][l]; loads and stores run with consecutive threads on consecutive
+// addresses (whole contiguous rows along x; along y and z the LB lines of one index i).
+template <int AXIS, int LB>
+__global__ __launch_bounds__(SEG_MAX * LINES) void k_solve_seg(SolveArgs a, int64_t lines, int seg_len)
+{
+    extern __shared__ double sh[];
+    const int n = AXIS == 0 ? a.nx : AXIS == 1 ? a.ny : a.nz;
+    const int nseg = blockDim.x / LB;
+    constexpr int LS = LB + 1;               // row stride: odd, so a column walk spreads over banks
+    double* tile = sh;                       // [n][LS]
+    double* mp = sh + (size_t)n * LS;        // [nseg][LB] composed maps: y_out = P y_in + Q
+    double* mq = mp + (size_t)nseg * LB;
+    const int l = threadIdx.x % LB, w = threadIdx.x / LB;
+    const int64_t L0 = (int64_t)blockIdx.x * LB;
+    const int cnt = (int)min<int64_t>(LB, lines - L0);
+    const int64_t lines_per_sub = AXIS == 0 ? (int64_t)a.ny * a.nz
+                                            : AXIS == 1 ? (int64_t)a.nx * a.nz : (int64_t)a.nx * a.ny;
+    // first element and stride of line L0 + l (valid for l < cnt)
+    int64_t base = 0, stride = 1;
+    int s = 0;
+    {
+        const int64_t L = L0 + min(l, cnt - 1);
+        s = (int)(L / lines_per_sub);
+        const int64_t q = L - (int64_t)s * lines_per_sub;
+        if (AXIS == 0) {
+            base = L * a.nx;
+        } else if (AXIS == 1) {
+            base = (int64_t)s * a.V + (q / a.nx) * a.nx * a.ny + q % a.nx;
+            stride = a.nx;
+        } else {
+            base = (int64_t)s * a.V + q;
+            stride = (int64_t)a.nx * a.ny;
+        }
+    }
+    if (AXIS == 0) {
+        const double* g = a.rho + L0 * a.nx;
+        const int tot = cnt * n;
+        for (int t = threadIdx.x; t < tot; t += blockDim.x) tile[(t % n) * LS + t / n] = g[t];
+    } else if (l < cnt) {
+        const double* p = a.rho + base;
+#pragma unroll 4
+        for (int i = w; i < n; i += nseg) tile[i * LS + l] = p[i * stride];
+    }
+    __syncthreads();
+    const Factors F = factors(a, s, AXIS);
+    const int i0 = min(n, w * seg_len), len = min(n, i0 + seg_len) - i0;
+    const bool on = l < cnt;
+    // the segment's values and factors, all loads issued before the arithmetic
+    double v[SEG_LEN_MAX], m[SEG_LEN_MAX], c[SEG_LEN_MAX];
+#pragma unroll
+    for (int k = 0; k < SEG_LEN_MAX; ++k)
+        if (k < len) {
+            v[k] = tile[(i0 + k) * LS + l];
+            m[k] = F.inv_m[i0 + k];
+            c[k] = F.c[i0 + k];
+        }
+    // forward: the segment's map y_out = P y_in + Q, the starting value, the recurrence
+    double P = 1.0, Q = 0.0;
+#pragma unroll
+    for (int k = 0; k < SEG_LEN_MAX; ++k)
+        if (k < len) {
+            P = m[k] * F.r * P;
+            Q = (v[k] + F.r * Q) * m[k];
+        }
+    mp[w * LB + l] = P;
+    mq[w * LB + l] = Q;
+    __syncthreads();
+    double y = 0.0;
+    if (on)
+        for (int j = 0; j < w; ++j) y = mp[j * LB + l] * y + mq[j * LB + l];
+#pragma unroll
+    for (int k = 0; k < SEG_LEN_MAX; ++k)
+        if (k < len) {
+            y = (v[k] + F.r * y) * m[k];
+            v[k] = y;
+        }
+    __syncthreads();   // every thread has read the forward maps
+    // back substitution: the map from the value after the segment down to its first
+    P = 1.0;
+    Q = 0.0;
+#pragma unroll
+    for (int k = SEG_LEN_MAX - 1; k >= 0; --k)
+        if (k < len) {
+            P = -c[k] * P;
+            Q = v[k] - c[k] * Q;
+        }
+    mp[w * LB + l] = P;
+    mq[w * LB + l] = Q;
+    __syncthreads();
+    double u = 0.0;
+    if (on)
+        for (int j = nseg - 1; j > w; --j) u = mp[j * LB + l] * u + mq[j * LB + l];
+#pragma unroll
+    for (int k = SEG_LEN_MAX - 1; k >= 0; --k)
+        if (k < len) {
+            u = v[k] - c[k] * u;
+            tile[(i0 + k) * LS + l] = u;
+        }
+    __syncthreads();
+    if (AXIS == 0) {
+        double* g = a.rho + L0 * a.nx;
+        const int tot = cnt * n;
+        for (int t = threadIdx.x; t < tot; t += blockDim.x) g[t] = tile[(t % n) * LS + t / n];
+    } else if (l < cnt) {
+        double* p = a.rho + base;
+#pragma unroll 4
+        for (int i = w; i < n; i += nseg) p[i * stride] = tile[i * LS + l];
+    }
+}
+
 // Gradients: one thread per voxel and substrate (grid-stride), x fastest.
 __global__ __launch_bounds__(GRAD_BLOCK) void k_gradients(const double* __restrict__ rho, double* __restrict__ grad,
                                                           int nx, int ny, int nz, int64_t V, int64_t total,
@@ -264,6 +388,7 @@ struct MechMicroenv {
     hipGraphExec_t exec = nullptr;
     hipEvent_t ev[5] = {};
     int grad_blocks = 0;
+    int cus = 256;
 };
 
 namespace {
@@ -333,14 +458,45 @@ SolveArgs solve_args(const MechMicroenv* E)
     return SolveArgs{E->rho, E->fac, E->rr, E->nmax, E->p.dims[0], E->p.dims[1], E->p.dims[2], E->V};
 }
 
+template <int AXIS, int LB>
+void launch_seg(MechMicroenv* E, const SolveArgs& a, int64_t lines, int n)
+{
+    const int nseg = std::min(SEG_MAX, std::max(1, (n + SEG_MIN_LEN - 1) / SEG_MIN_LEN));
+    const int seg_len = (n + nseg - 1) / nseg;
+    const unsigned blocks = (unsigned)((lines + LB - 1) / LB);
+    const size_t shm = ((size_t)n * (LB + 1) + 2 * (size_t)nseg * LB) * sizeof(double);
+    k_solve_seg<AXIS, LB><<<blocks, nseg * LB, shm, E->stream>>>(a, lines, seg_len);
+}
+
+template <int AXIS>
+void launch_seg_lb(MechMicroenv* E, const SolveArgs& a, int64_t lines, int n)
+{
+    // lines per block: as many as still give every compute unit two blocks
+    if (lines >= (int64_t)32 * 2 * E->cus)
+        launch_seg<AXIS, 32>(E, a, lines, n);
+    else
+        launch_seg<AXIS, 16>(E, a, lines, n);
+}
+
 // One launch of the solve along `axis`.
 int launch_solve(MechMicroenv* E, int axis)
 {
     const SolveArgs a = solve_args(E);
     const int64_t ns = E->p.n_substrates;
     const int n = E->p.dims[axis];
-    const bool lds = n <= LDS_MAX_N;
     const int64_t lines = ns * (E->V / n);
+    // Segments pay when the lines alone would leave compute units idle (fewer lines than
+    // one wave per compute unit holds lanes); with more lines the chip is full anyway and
+    // the per-line walk does half the arithmetic.
+    const int nseg = std::min(SEG_MAX, std::max(1, (n + SEG_MIN_LEN - 1) / SEG_MIN_LEN));
+    if (n <= SEG_MAX_N && (n + nseg - 1) / nseg <= SEG_LEN_MAX && lines <= (int64_t)LINES * E->cus) {
+        if (axis == 0) launch_seg_lb<0>(E, a, lines, n);
+        else if (axis == 1) launch_seg_lb<1>(E, a, lines, n);
+        else launch_seg_lb<2>(E, a, lines, n);
+        HIP_TRY(hipGetLastError());
+        return MECH_OK;
+    }
+    const bool lds = n <= LDS_MAX_N;
     const unsigned blocks = (unsigned)((lines + LINES - 1) / LINES);
     const size_t shm = lds ? (size_t)LINES * (size_t)n * sizeof(double) : 0;
     if (axis == 0) {
@@ -471,6 +627,7 @@ int create_microenvironment(const MechMicroenvParams* params, const double* dens
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, E->device) != hipSuccess || cus < 1)
         cus = 256;
+    E->cus = cus;
     const int64_t need = (nv + GRAD_BLOCK - 1) / GRAD_BLOCK;
     E->grad_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(need, (int64_t)cus * 16));
     *out = E;

@@ -71,7 +71,10 @@ def test_paper_mesh_75_cubed_100_steps():
     ((66, 65, 3), 4, 64),      # line counts that leave a ragged last block
     ((1, 1, 1), 1, 65),        # one voxel: decay only
     ((1, 70, 1), 2, 66), ((70, 1, 1), 1, 67), ((2, 1, 2), 3, 68),
-    ((128, 128, 2), 1, 69),    # the longest lines staged in LDS
+    ((128, 128, 2), 1, 69),    # the longest lines staged in LDS whole
+    ((112, 9, 113), 2, 76),    # the longest segmented lines (x), the shortest whole ones (z)
+    ((21, 11, 19), 3, 77),     # two and three segments with a ragged last one
+    ((40, 40, 40), 11, 78),    # more lines than one wave per compute unit: one lane per line
 ])
 def test_ragged_and_multi_substrate_meshes(dims, ns, seed):
     require_gpu()
