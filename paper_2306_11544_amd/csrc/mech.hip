@@ -151,6 +151,7 @@ typedef short short2v __attribute__((ext_vector_type(2)));
 constexpr uint32_t Q_MARGIN = 3;
 // entries of the quantised shadow past the last cell that the force kernel's trips may read
 constexpr size_t QS_PAD = 16;
+static_assert(QS_PAD >= 2 * 8, "a trip of up to 8 candidates from at most 7 past a row's end");
 
 // The quantised shadow of a cell, the prefilter's input: each coordinate as
 // round(x S) mod 2^16 (S = q_scale, a power of two, so x S is exact) and the reach
@@ -1131,7 +1132,8 @@ __device__ __forceinline__ bool pair64(double xi, double yi, double zi, double r
         d2 = dx * dx + dy * dy + dz * dz;
         R = ri + rj;
         RA = alpha * R;
-        if (!(d2 > 0.0 && d2 < RA * RA)) return false;
+        // both comparisons as one predicate (not short-circuit): one branch per pair
+        if (!((d2 > 0.0) & (d2 < RA * RA))) return false;
     }
     const double inv_d = rsqrt_nr(d2);
     const double d = d2 * inv_d;
@@ -1170,7 +1172,7 @@ __device__ __forceinline__ bool pair32(float xi, float yi, float zi, float ri, f
         d2 = dx * dx + dy * dy + dz * dz;
         R = ri + q.w;
         RA = alpha * R;
-        if (!(d2 > 0.0f && d2 < RA * RA)) return false;
+        if (!((d2 > 0.0f) & (d2 < RA * RA))) return false;
     }
     float inv_d = __builtin_amdgcn_rsqf(d2);
     float d = d2 * inv_d;
@@ -1634,12 +1636,28 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
                 }
                 if (full()) flush(KEEP);
             }
-            for (; j < e; ++j, ++sp) {
-                const bool in = near(*sp);
-                if constexpr (PACK)
-                    push((j << 4) | 1u, in);
-                else
-                    push(j, in);
+            // fewer than FC_UNROLL left: one more trip, testing only the candidates below e
+            // (the shadow array is padded by QS_PAD >= 2 FC_UNROLL entries past the last
+            // cell, so a trip that starts below e reads inside it; a lane with nothing left
+            // reads from its e and lists nothing)
+            if (__any(j < e)) {
+                const uint32_t lim = j < e ? e - j : 0u;
+                uint2 c[FC_UNROLL];
+#pragma unroll
+                for (int u = 0; u < FC_UNROLL; ++u) c[u] = sp[u];
+                if constexpr (PACK) {
+#pragma unroll
+                    for (int g4 = 0; g4 < FC_UNROLL; g4 += 4) {
+                        uint32_t m = 0;
+#pragma unroll
+                        for (int u = g4; u < FC_UNROLL && u < g4 + 4; ++u)
+                            m |= (uint32_t)(near(c[u]) & ((uint32_t)u < lim)) << (u - g4);   // no branch
+                        push(((j + g4) << 4) | m, m != 0u);
+                    }
+                } else {
+#pragma unroll
+                    for (int u = 0; u < FC_UNROLL; ++u) push(j + u, near(c[u]) & ((uint32_t)u < lim));
+                }
                 if (full()) flush(KEEP);
             }
         }
