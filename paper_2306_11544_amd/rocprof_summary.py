@@ -150,6 +150,7 @@ def pmc(paths, kernel: str, commands, candidates=None, source=SOURCE) -> str:
     lines.append(f"kernel: {kernel}")
     if candidates is not None:
         lines.append(f"candidates_per_launch: {candidates:.6g}")
+    mean = {}
     for path in paths:
         acc = collections.defaultdict(lambda: collections.defaultdict(float))
         name = {}
@@ -160,7 +161,18 @@ def pmc(paths, kernel: str, commands, candidates=None, source=SOURCE) -> str:
             name[r["Dispatch_Id"]] = r["Kernel_Name"]
         for counter in sorted(acc):
             vals = list(acc[counter].values())
-            lines.append(f"{counter}: {sum(vals) / len(vals):.6g}  ({len(vals)} dispatches)")
+            mean[counter] = sum(vals) / len(vals)
+            lines.append(f"{counter}: {mean[counter]:.6g}  ({len(vals)} dispatches)")
+    # derived figures: lane use is thread-cycles of VALU work over 64 lanes of the
+    # cycles with a VALU instruction issued; per candidate, a wave instruction counts
+    # once per lane
+    if "SQ_THREAD_CYCLES_VALU" in mean and mean.get("SQ_ACTIVE_INST_VALU"):
+        util = mean["SQ_THREAD_CYCLES_VALU"] / (64.0 * mean["SQ_ACTIVE_INST_VALU"])
+        lines.append(f"derived lane_utilisation: {util:.3f}")
+        if candidates and "SQ_INSTS_VALU" in mean:
+            per = mean["SQ_INSTS_VALU"] * 64.0 / candidates
+            lines.append(f"derived valu_lane_insts_per_candidate: {per:.2f}")
+            lines.append(f"derived active_valu_lane_insts_per_candidate: {per * util:.2f}")
     return "\n".join(lines) + "\n"
 
 
