@@ -102,9 +102,9 @@ typedef struct MechTuning {
                                    MECH_FLAG_VOXEL_FORCE or MECH_FLAG_PRUNED_FORCE (the
                                    force bits of flags)                                 */
     int32_t block_waves;        /* wave64s per workgroup of the per-cell kernels:
-                                   1, 2, 4 (default) or 8                               */
+                                   1 (default), 2, 4 or 8                               */
     int32_t unroll;             /* candidates the list kernel tests per loop trip:
-                                   2, 4 (default) or 8                                  */
+                                   2, 4 or 8 (default)                                  */
     int32_t blocks_per_cu;      /* force-kernel workgroups per compute unit, 1..64, or 0
                                    (default): one per block_waves*64 cells of capacity
                                    (at most 32768 wave64s) for the per-cell kernels and

@@ -82,7 +82,7 @@ class MechTuning(C.Structure):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
-def tuning(force_kernel=0, block_waves=4, unroll=4, blocks_per_cu=0, list_len=0) -> MechTuning:
+def tuning(force_kernel=0, block_waves=1, unroll=8, blocks_per_cu=0, list_len=0) -> MechTuning:
     if isinstance(force_kernel, str):
         force_kernel = FORCE_KERNELS[force_kernel]
     return MechTuning(int(force_kernel), int(block_waves), int(unroll), int(blocks_per_cu),

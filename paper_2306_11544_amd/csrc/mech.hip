@@ -3,8 +3,10 @@
 // One step, all on the device, on the batch's stream:
 //   k_bin          a1+a2  storage bin of every cell (its voxel, cut into XSUB slabs along x;
 //                         FP64 key) and an integer-atomic histogram, one atomic per run of
-//                         equal bins in a wave; its first workgroup also does the step's
-//                         per-simulation bookkeeping (step counters, Euler start)
+//                         equal bins in a wave; a workgroup also does the step's
+//                         per-simulation bookkeeping (step counters, Euler start), and on
+//                         large grids an extra first one cuts the force kernel's XCD runs
+//                         from the last launch's measured work
 //   k_scan_reduce  a3     per-tile sums of (count, occupied voxels) packed in 64 bits
 //   k_scan_top            exclusive scan of the tile sums (one workgroup; on grids of at
 //                         most FUSED_SCAN_TILES tiles k_scan_down adds them up itself)
@@ -12,7 +14,8 @@
 //   k_scatter      a4     cells into their bin's segment (arbitrary order inside it)
 //   k_rank_gather  a4+a5  rank inside the bin by ascending id -> final slot; gather of the
 //                         cell state into that order (+ the float and quantised shadows)
-//   k_force_*      a6+a7  27-voxel neighbour forces -> velocity, Adams-Bashforth, walls
+//   k_force_*      a6+a7  27-voxel neighbour forces -> velocity, Adams-Bashforth, walls;
+//                         k_force_cells gives each XCD one contiguous run of cells
 //   k_div_*               growing populations only: division after the walls
 //   k_die_*               dying populations only: death after division
 //   k_step_end            the bookkeeping alone, for a step without cells
@@ -45,7 +48,7 @@
 //   slot_of u32  slot of the cell at each index (constant between repacks)
 // Binning scratch: vid_cur, off, tmp_key, tmp_src, vid_sorted (u32 per cell);
 // count, voxel_start (u32 per bin, XSUB bins per voxel), occ (u32 per voxel); tile sums
-// (u64 per 2048 bins).
+// (u64 per 2048 bins); the force kernel's work table (BAL_ENTRIES u32) and XCD split.
 
 #include <hip/hip_runtime.h>
 
@@ -167,6 +170,19 @@ __device__ __forceinline__ uint2 quantise(double x, double y, double z, double r
     return make_uint2(qx | (qy << 16), qz | (qr << 16));
 }
 
+// Work table of the per-cell force kernel: BAL_ENTRIES sums of wave durations, each over
+// `group` consecutive wave64s of cells (group grows with the population so the table
+// covers it), read and cleared by one workgroup of the next step's k_bin.
+constexpr uint32_t BAL_ENTRIES = 8192;
+// the balanced runs are kept only when the uniform runs' fullest holds more than this
+// share (in percent) above an even eighth of the measured work
+constexpr uint32_t BAL_KEEP_PCT = 3;
+__host__ __device__ inline uint32_t bal_group(uint32_t n)
+{
+    const uint32_t nw = (n + WAVE - 1) / WAVE;
+    return nw > BAL_ENTRIES ? (nw + BAL_ENTRIES - 1) / BAL_ENTRIES : 1u;
+}
+
 // Workgroups are dealt to the 8 XCDs round robin; renumber the first nb of them so that
 // each XCD gets a contiguous run of the voxel-ordered cells and its own L2 keeps the
 // shared neighbours.
@@ -269,6 +285,92 @@ __device__ __forceinline__ void begin_step(SlotDesc* slots, uint32_t n_slots, ui
     }
 }
 
+// The XCD runs of the next launch of k_force_cells, by one workgroup of BLOCK threads:
+// cut the cells, in whole entries of the work table, into N_XCD runs of equal measured
+// work (the wave durations the last launch added up) and clear the table.  The cut is
+// kept when it beats the uniform runs (equal cell counts) by more than BAL_KEEP_PCT;
+// split[N_XCD] = the cell count the cut was made for, or 0 for uniform runs.
+__device__ __forceinline__ void balance_block(uint32_t* __restrict__ work, uint32_t n, uint32_t* __restrict__ split)
+{
+    constexpr uint32_t PER = BAL_ENTRIES / BLOCK;
+    static_assert(PER % 4 == 0 && BAL_ENTRIES % BLOCK == 0, "each thread takes whole uint4s of the table");
+    __shared__ unsigned long long s_wave[BLOCK / WAVE];
+    __shared__ unsigned long long s_uni[N_XCD + 1];
+    __shared__ uint32_t s_cut[N_XCD + 1];
+    const uint32_t t = threadIdx.x, lane = t & (WAVE - 1);
+    const uint4* const mine = reinterpret_cast<const uint4*>(work + t * PER);   // this thread's entries
+    // the entries are loaded a few at a time where they are needed and not kept: this
+    // block shares k_bin's register budget (62 VGPRs keep 8 waves per SIMD)
+    unsigned long long own = 0;
+#pragma unroll 4
+    for (uint32_t k = 0; k < PER / 4; ++k) {
+        const uint4 q = mine[k];
+        own += (unsigned long long)q.x + q.y + q.z + q.w;
+    }
+    // block-wide inclusive scan of the threads' sums
+    unsigned long long inc = own;
+    for (int off = 1; off < WAVE; off <<= 1) {
+        const unsigned long long v = __shfl_up(inc, off, WAVE);
+        if (lane >= (uint32_t)off) inc += v;
+    }
+    if (lane == WAVE - 1) s_wave[t / WAVE] = inc;
+    __syncthreads();
+    unsigned long long total = 0;
+    for (uint32_t i = 0; i < BLOCK / WAVE; ++i) {
+        if (i < t / WAVE) inc += s_wave[i];
+        total += s_wave[i];
+    }
+    const unsigned long long excl = inc - own;
+    const bool cut = total >= (unsigned long long)N_XCD * N_XCD;   // else nothing measured: uniform runs
+    const uint32_t group = bal_group(n);
+#pragma unroll 1
+    for (uint32_t q = 1; cut && q < N_XCD; ++q) {
+        // the measured work before the uniform run q's first entry
+        const uint32_t u = (uint32_t)(((uint64_t)n * q / N_XCD) / ((uint64_t)group * WAVE));
+        // run q of the cut starts at the first entry whose preceding work reaches
+        // q / N_XCD of the total
+        const unsigned long long target = total * q / N_XCD;
+        const bool uni = u / PER == t, at = excl < target && target <= inc;
+        if (uni || at) {
+            uint4 v[PER / 4];
+#pragma unroll
+            for (uint32_t k = 0; k < PER / 4; ++k) v[k] = mine[k];
+            unsigned long long acc = excl, pre = excl;
+            uint32_t end = PER;
+#pragma unroll
+            for (uint32_t j = 0; j < PER; ++j) {
+                const uint32_t e = j % 4 == 0 ? v[j / 4].x : j % 4 == 1 ? v[j / 4].y : j % 4 == 2 ? v[j / 4].z : v[j / 4].w;
+                if (j < u % PER) pre += e;
+                if (acc < target) {
+                    acc += e;
+                    end = j + 1;
+                }
+            }
+            if (uni) s_uni[q] = pre;
+            if (at) s_cut[q] = t * PER + end;
+        }
+    }
+    __syncthreads();   // every read of the table is done: clear it for the next launch
+#pragma unroll 1
+    for (uint32_t k = 0; k < PER / 4; ++k) reinterpret_cast<uint4*>(work + t * PER)[k] = make_uint4(0u, 0u, 0u, 0u);
+    if (t == 0) {
+        bool keep = false;
+        if (cut) {
+            s_uni[0] = 0;
+            s_uni[N_XCD] = total;
+            unsigned long long fullest = 0;
+            for (uint32_t q = 0; q < N_XCD; ++q) fullest = max(fullest, s_uni[q + 1] - s_uni[q]);
+            keep = fullest * 100u * N_XCD > total * (100u + BAL_KEEP_PCT);
+        }
+        if (keep) {
+            split[0] = 0u;
+            for (uint32_t q = 1; q < N_XCD; ++q)
+                split[q] = (uint32_t)min<uint64_t>((uint64_t)s_cut[q] * group * WAVE, n);
+        }
+        split[N_XCD] = keep ? max(n, 1u) : 0u;
+    }
+}
+
 __global__ __launch_bounds__(BLOCK) void k_bin(const double* __restrict__ px,
                                                const double* __restrict__ py,
                                                const double* __restrict__ pz,
@@ -278,14 +380,26 @@ __global__ __launch_bounds__(BLOCK) void k_bin(const double* __restrict__ px,
                                                uint32_t* __restrict__ count,
                                                uint32_t* __restrict__ vid,
                                                uint32_t* __restrict__ off,
-                                               uint32_t n_slots, int step_start)
+                                               uint32_t n_slots, int step_start,
+                                               uint32_t* __restrict__ work, uint32_t* __restrict__ split)
 {
-    if (step_start && blockIdx.x == 0) begin_step(slots, n_slots, hdr, threadIdx.x, BLOCK);
+    // with a work table, the grid's first workgroup (dispatched first, so it runs beside
+    // the binning) cuts the force kernel's XCD runs; the others bin
+    uint32_t bid = blockIdx.x, nbin = gridDim.x;
+    if (work) {
+        if (bid == 0) {
+            balance_block(work, hdr[H_CELLS], split);
+            return;
+        }
+        --bid;
+        --nbin;
+    }
+    if (step_start && bid == 0) begin_step(slots, n_slots, hdr, threadIdx.x, BLOCK);
     const uint32_t n = hdr[H_CELLS];
     const uint32_t lane = threadIdx.x & (WAVE - 1);
     const uint64_t le = lane == WAVE - 1 ? ~0ull : (2ull << lane) - 1ull;  // lanes <= this one
     // the trip count is uniform per wave, so every lane takes part in the shuffles
-    for (uint32_t s0 = blockIdx.x * BLOCK + (threadIdx.x & ~(WAVE - 1)); s0 < n; s0 += gridDim.x * BLOCK) {
+    for (uint32_t s0 = bid * BLOCK + (threadIdx.x & ~(WAVE - 1)); s0 < n; s0 += nbin * BLOCK) {
         const uint32_t s = s0 + lane;
         const bool live = s < n;
         uint32_t v = 0xffffffffu;
@@ -1066,6 +1180,8 @@ struct ForceArgs {
     double* X[3];              // new positions
     const uint32_t* perm;      // cells left in place: storage index of each sorted slot
     unsigned long long* stats; // STAT_SLOTS pairs (interactions, candidates)
+    uint32_t* work;            // BAL_ENTRIES sums of wave durations, zero before the launch (or null)
+    const uint32_t* split;     // first cell of each XCD's run, from the durations (or null)
 };
 
 // a7 for one cell: two-step Adams-Bashforth from the gathered position, reflecting
@@ -1745,12 +1861,44 @@ __global__ __launch_bounds__(WPB * WAVE) void k_force_cells(PhysArgs P, ForceArg
         rng0 = &s_rng[threadIdx.x / WAVE][0][threadIdx.x & (WAVE - 1)];
     }
     uint32_t inter = 0, cand = 0;
-    // rounds of gridDim.x blocks, renumbered per round as in k_force_rows
-    for (uint32_t lb0 = 0; lb0 < nb; lb0 += gridDim.x) {
-        const uint32_t active = min(gridDim.x, nb - lb0);
-        if (blockIdx.x >= active) break;
-        const uint32_t i = (lb0 + xcd_block(blockIdx.x, active)) * TB + threadIdx.x;
-        force_cells_cell<PREC, MULTI, VPT, UNROLL, LIST, IND, PRUNE>(P, a, i, n, list0, rng0, inter, cand);
+    // Each XCD takes one contiguous run of tiles, so its L2 keeps the neighbours its
+    // cells share; the runs hold equal shares of the last launch's measured work, or
+    // equal numbers of tiles before there is any.  The runs partition [0, nb) whatever
+    // the split holds: the bounds are clamped and made non-decreasing.
+    const uint32_t X = min(gridDim.x, N_XCD);
+    const uint32_t x = blockIdx.x % X, nbx = (gridDim.x - x + X - 1) / X;
+    uint32_t t0, t1;
+    if (a.split && X == N_XCD && a.split[N_XCD] != 0u) {
+        uint32_t lo = 0, hi = 0;
+#pragma unroll
+        for (uint32_t q = 1; q <= N_XCD; ++q) {
+            const uint32_t b = q == N_XCD ? nb : max(hi, min((a.split[q] + TB / 2) / TB, nb));
+            if (q == x) lo = b;
+            hi = b;
+            if (q == x + 1) break;
+        }
+        t0 = x == 0 ? 0u : lo;
+        t1 = hi;
+    } else {
+        // equal runs, the longer ones on the XCDs that the round robin gives one
+        // workgroup more: with a tile per workgroup, no workgroup takes two
+        const uint32_t q = nb / X, r = nb % X;
+        t0 = x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q;
+        t1 = t0 + q + (x < r ? 1u : 0u);
+    }
+    const uint32_t group = bal_group(n);
+    for (uint32_t t = t0 + blockIdx.x / X; t < t1; t += nbx) {
+        // read unconditionally: a conditional read costs the FP64 kernels a register
+        const uint64_t c0 = wall_clock64();
+        force_cells_cell<PREC, MULTI, VPT, UNROLL, LIST, IND, PRUNE>(P, a, t * TB + threadIdx.x, n, list0, rng0,
+                                                                     inter, cand);
+        if (a.work) {
+            // the wave's index among the wave64s of cells; waves past the last cell record
+            // nothing, so the entry (wave / group) is below BAL_ENTRIES
+            const uint32_t wave = t * WPB + __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+            if ((threadIdx.x & (WAVE - 1)) == 0 && wave * WAVE < n)
+                atomicAdd(&a.work[wave / group], (uint32_t)max<uint64_t>(wall_clock64() - c0, 1));
+        }
     }
     add_stats(a.stats, inter, cand);
 }
@@ -2049,7 +2197,7 @@ inline uint32_t blocks_for(uint64_t n, uint32_t per) { return (uint32_t)((n + pe
 
 struct Layout {
     size_t X[3], XS[3], R[2], T[2], ID[2], VP[2][3], SH, QS, slot_of, vid_cur, off, tmp_key, dtsum,
-        tmp_src, vid_sorted, count, start, occ, hdr, tsum, stats, cadh, cadh_f, slots, stage;
+        tmp_src, vid_sorted, count, start, occ, hdr, tsum, stats, cadh, cadh_f, slots, stage, work, split;
     size_t total;
 };
 
@@ -2094,6 +2242,8 @@ Layout make_layout(const MechParams& p, int64_t ncap, uint64_t vcap, int32_t sca
     L.slots = take((size_t)std::max(scap, 1) * sizeof(SlotDesc));
     L.stage = take(nn * 48);
     L.dtsum = take((size_t)blocks_for(nn, SCAN_TILE) * 8);
+    L.work = take(BAL_ENTRIES * 4);
+    L.split = take((N_XCD + 1) * 4);
     L.total = cur;
     return L;
 }
@@ -2227,7 +2377,7 @@ struct MechBatch {
     int parity = 0;
     int64_t steps = 0;
     int32_t cus = 256;                    // compute units of the device
-    MechTuning tune{0, 4, 4, 0, 0};       // force-kernel launch configuration
+    MechTuning tune{0, 1, 8, 0, 0};       // force-kernel launch configuration
     // locality study: reorder (gather) every reorder_every steps, 0 = never
     int32_t reorder_every = 1;
     // growing populations: division probability per cell and step, draw seed
@@ -2267,19 +2417,23 @@ uint32_t cell_grid(const MechBatch* B)
     return std::max<uint32_t>(1, std::min<uint32_t>(blocks_for((uint64_t)B->cap_cells, BLOCK), CELL_GRID_MAX));
 }
 
-// a1..a3 and the scatter of a4 (sorted slots of the cells, before the rank by id)
-void enqueue_keys(MechBatch* B)
+bool force_balanced(const MechBatch* B);
+
+// a1..a3 and the scatter of a4 (sorted slots of the cells, before the rank by id); with
+// `balance`, k_bin also cuts the next force launch's XCD runs from the last one's work
+void enqueue_keys(MechBatch* B, bool balance)
 {
     const Layout& L = B->L;
     const int cur = B->parity;
     const uint32_t nbc = cell_grid(B);
     const uint32_t nbt = std::min<uint32_t>(blocks_for((uint64_t)B->cap_voxels * XSUB, SCAN_TILE), TILE_GRID_MAX);
     const uint32_t* hdr = B->at<uint32_t>(L.hdr);
-    hipLaunchKernelGGL(k_bin, dim3(nbc), dim3(BLOCK), 0, B->stream, B->at<double>(L.X[0]),
+    hipLaunchKernelGGL(k_bin, dim3(nbc + (balance ? 1 : 0)), dim3(BLOCK), 0, B->stream, B->at<double>(L.X[0]),
                        B->at<double>(L.X[1]), B->at<double>(L.X[2]), B->at<uint32_t>(L.slot_of),
                        B->at<SlotDesc>(L.slots), B->at<uint32_t>(L.hdr), B->at<uint32_t>(L.count),
                        B->at<uint32_t>(L.vid_cur), B->at<uint32_t>(L.off), (uint32_t)B->cap_slots,
-                       B->step_start ? 1 : 0);
+                       B->step_start ? 1 : 0, balance ? B->at<uint32_t>(L.work) : nullptr,
+                       B->at<uint32_t>(L.split));
     hipLaunchKernelGGL(k_scan_reduce, dim3(nbt), dim3(BLOCK), 0, B->stream, B->at<uint32_t>(L.count), hdr,
                        B->at<uint64_t>(L.tsum));
     if (blocks_for((uint64_t)B->cap_voxels * XSUB, SCAN_TILE) <= FUSED_SCAN_TILES) {
@@ -2312,7 +2466,7 @@ void enqueue_binning(MechBatch* B)
     const int cur = B->parity, nxt = cur ^ 1;
     const uint32_t nbc = cell_grid(B);
     const uint32_t* hdr = B->at<uint32_t>(L.hdr);
-    if (!small_binning(B)) enqueue_keys(B);
+    if (!small_binning(B)) enqueue_keys(B, force_balanced(B));
     GatherArgs<VPT> g{};
     for (int c = 0; c < 3; ++c) {
         g.X[c] = B->at<double>(L.X[c]);
@@ -2355,10 +2509,27 @@ uint32_t force_cell_grid(const MechBatch* B, int wpb)
     return std::min(tiles, cap);
 }
 
+// Whether the step's force launch records its waves' durations and takes work-balanced
+// XCD runs: the per-cell list kernel, with a grid that fills every resident slot at
+// least once (with fewer workgroups, a longer run would make some of them take two
+// tiles in turn).
+bool force_balanced(const MechBatch* B)
+{
+    if (B->prm.flags & (MECH_FLAG_SIMPLE_FORCE | MECH_FLAG_VOXEL_FORCE)) return false;
+    const int w = B->tune.block_waves;
+    const uint32_t wpb = (w == 1 || w == 2 || w == 8) ? (uint32_t)w : 4u;
+    return force_cell_grid(B, (int)wpb) >= (uint32_t)B->cus * (32u / wpb);
+}
+
 template <int PREC, bool MULTI, typename VPT, int WPB, int LIST, bool PRUNE>
-void launch_cells_p(MechBatch* B, const ForceArgs<VPT>& a)
+void launch_cells_p(MechBatch* B, const ForceArgs<VPT>& args)
 {
     const dim3 grid(force_cell_grid(B, WPB)), block(WPB * WAVE);
+    ForceArgs<VPT> a = args;
+    if (!force_balanced(B)) {
+        a.work = nullptr;
+        a.split = nullptr;
+    }
     switch (B->tune.unroll) {
     case 2:
         hipLaunchKernelGGL((k_force_cells<PREC, MULTI, VPT, WPB, 2, LIST, false, PRUNE>), grid, block, 0, B->stream,
@@ -2470,6 +2641,8 @@ void enqueue_force(MechBatch* B, int parity_after_sort)
             hipLaunchKernelGGL((k_force_lds<PREC, false, VPT>), dim3(grid), dim3(FL_WAVES * WAVE), 0,
                                B->stream, B->phys, a, occ);
     } else {
+        a.work = B->at<uint32_t>(L.work);
+        a.split = B->at<uint32_t>(L.split);
         if (multi)
             launch_cells<PREC, true, VPT>(B, a);
         else
@@ -2542,7 +2715,7 @@ void enqueue_binning_inplace(MechBatch* B)
                        is_fp32(B->prm) ? B->at<float4>(L.SH) : nullptr, B->at<uint2>(L.QS),
                        B->at<uint32_t>(L.slot_of),
                        B->at<SlotDesc>(L.slots), B->phys.alpha);
-    enqueue_keys(B);
+    enqueue_keys(B, false);
     hipLaunchKernelGGL(k_rank_perm, dim3(nbc), dim3(BLOCK), 0, B->stream, hdr, B->at<uint32_t>(L.vid_cur),
                        B->at<uint32_t>(L.tmp_key), B->at<uint32_t>(L.tmp_src), B->at<uint32_t>(L.start),
                        B->at<uint32_t>(L.off));
@@ -2874,6 +3047,8 @@ int create_batch_impl(const MechParams* params, int64_t max_cells, int64_t max_v
         hipMemsetAsync(B->arena + L.stats, 0, STAT_SLOTS * 16, B->stream) != hipSuccess ||
         hipMemsetAsync(B->arena + L.start, 0, ((size_t)max_voxels * XSUB + 1) * 4, B->stream) != hipSuccess ||
         hipMemsetAsync(B->arena + L.hdr, 0, HDR_WORDS * 4, B->stream) != hipSuccess ||
+        hipMemsetAsync(B->arena + L.split, 0, (N_XCD + 1) * 4, B->stream) != hipSuccess ||
+        hipMemsetAsync(B->arena + L.work, 0, BAL_ENTRIES * 4, B->stream) != hipSuccess ||
         hipMemsetAsync(B->arena + L.slots, 0, (size_t)max_slots * sizeof(SlotDesc), B->stream) != hipSuccess)
         return bail(fail(MECH_E_DEVICE, "arena initialisation failed"));
     rc = sync_check(B);
@@ -3364,6 +3539,8 @@ int noalloc_impl(const MechParams* params, int64_t n, const double* pos, const d
     HIP_TRY(hipMemsetAsync(B.arena + L.start, 0, ((size_t)V * XSUB + 1) * 4, st));
     HIP_TRY(hipMemsetAsync(B.arena + L.stats, 0, STAT_SLOTS * 16, st));
     HIP_TRY(hipMemsetAsync(B.arena + L.hdr, 0, HDR_WORDS * 4, st));
+    HIP_TRY(hipMemsetAsync(B.arena + L.split, 0, (N_XCD + 1) * 4, st));
+    HIP_TRY(hipMemsetAsync(B.arena + L.work, 0, BAL_ENTRIES * 4, st));
     const SlotDesc d = slot_desc(*params, params->domain_lo, params->domain_hi, dims, rmax, n, -1, vprev != nullptr,
                                  0u, 0u);
     hipLaunchKernelGGL(k_set_slot, dim3(1), dim3(1), 0, st, B.at<SlotDesc>(L.slots), 0u, d);
