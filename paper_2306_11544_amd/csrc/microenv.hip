@@ -70,6 +70,15 @@ constexpr int SEG_MAX_N = 112;     // longest line of k_solve_seg: the tile and 
 constexpr int SEG_LEN_MAX = 16;    // longest segment: ceil(112 / 8) = 14 fits
 constexpr int GRAD_BLOCK = 256;
 constexpr int MAX_DIM = 4096;
+constexpr unsigned N_XCD = 8;      // MI355X: 8 accelerator complex dies, each with its own L2
+
+// Workgroups reach the XCDs round robin; renumber them so that each XCD takes one
+// contiguous run of the nb tiles, and tiles that share cache lines share an L2.
+__device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned nb)
+{
+    const unsigned xcd = b % N_XCD, k = b / N_XCD, q = nb / N_XCD, r = nb % N_XCD;
+    return xcd < r ? xcd * (q + 1) + k : r * (q + 1) + (xcd - r) * q + k;
+}
 
 // Elimination factors of one substrate and axis: c[n] then inv_m[n], and r.
 struct Factors {
@@ -246,7 +255,7 @@ __global__ __launch_bounds__(SEG_MAX * LINES) void k_solve_seg(SolveArgs a, int6
     double* mp = sh + (size_t)n * LS;        // [nseg][LB] composed maps: y_out = P y_in + Q
     double* mq = mp + (size_t)nseg * LB;
     const int l = threadIdx.x % LB, w = threadIdx.x / LB;
-    const int64_t L0 = (int64_t)blockIdx.x * LB;
+    const int64_t L0 = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * LB;
     const int cnt = (int)min<int64_t>(LB, lines - L0);
     const int64_t lines_per_sub = AXIS == 0 ? (int64_t)a.ny * a.nz
                                             : AXIS == 1 ? (int64_t)a.nx * a.nz : (int64_t)a.nx * a.ny;
