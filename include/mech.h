@@ -226,6 +226,15 @@ int read_binning(MechPopulation* pop, uint32_t* voxel_of_cell, uint32_t* voxel_s
 int read_stats(MechPopulation* pop, int64_t* steps, int64_t* interactions,
                int64_t* candidates);
 
+/* Defined by this library (measurement and tests): wait and copy the per-cell force
+ * kernel's current cut of the cells into the 8 XCDs' runs (9 uint32):
+ *   split[0..7]  first cell of each XCD's run
+ *   split[8]     the cell count the cut was made for; 0 when the runs are the
+ *                equal-count ones (no cut kept, or none measured yet)
+ * The cut is made from the measured work of the last launch, on grids that fill every
+ * resident slot at least once; it moves which workgroup takes a cell, never a result. */
+int read_xcd_split(MechPopulation* pop, uint32_t* split);
+
 /* Run n_steps steps (a1-a7, same results as step_mechanics) with direct launches and
  * HIP events on the population's stream around the two phases; on return
  *   phase_ms[0]  mean ms per step of binning and reorder (a1-a5)

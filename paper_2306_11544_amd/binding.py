@@ -33,7 +33,8 @@ PRECISIONS = {"fp64": MECH_FP64, "fp32": MECH_FP32, "fp32k": MECH_FP32_KAHAN}
 # every symbol include/mech.h declares
 EXPORTS = ("mech_last_error", "mech_abi_version", "mech_device_count",
            "population_workspace_bytes", "create_population", "create_population_in",
-           "step_mechanics", "read_state", "read_binning", "read_stats", "profile_step",
+           "step_mechanics", "read_state", "read_binning", "read_stats", "read_xcd_split",
+           "profile_step",
            "create_population_cap", "population_set_division", "population_set_death",
            "population_size",
            "population_set_reorder", "population_get_tuning", "population_set_tuning",
@@ -120,6 +121,7 @@ def lib():
             "read_state": (C.c_int, [vp, dp, dp, C.c_int64]),
             "read_binning": (C.c_int, [vp, up, up, up, up, lp, lp]),
             "read_stats": (C.c_int, [vp, lp, lp, lp]),
+            "read_xcd_split": (C.c_int, [vp, C.POINTER(C.c_uint32)]),
             "profile_step": (C.c_int, [vp, C.c_int64, dp]),
             "create_population_cap": (C.c_int, [P(MechParams), C.c_int64, C.c_int64, dp, dp, ip,
                                                 dp, vp, P(vp)]),
@@ -328,6 +330,12 @@ def read_stats(h):
     return int(s.value), int(i.value), int(c.value)
 
 
+def read_xcd_split(h):
+    split = np.zeros(9, np.uint32)
+    _ck(lib().read_xcd_split(h, split.ctypes.data_as(C.POINTER(C.c_uint32))))
+    return split
+
+
 def profile_step(h, n_steps: int = 1):
     """Mean ms per step of (binning + reorder, force + update), timed with HIP events."""
     ms = np.zeros(2, np.float64)
@@ -373,6 +381,9 @@ class Population:
 
     def stats(self):
         return read_stats(self.h)
+
+    def xcd_split(self):
+        return read_xcd_split(self.h)
 
     def profile(self, n_steps=1):
         return profile_step(self.h, n_steps)

@@ -3817,6 +3817,18 @@ int read_stats(MechPopulation* P, int64_t* steps, int64_t* interactions, int64_t
     return stats_impl(P->b, steps, interactions, candidates);
 }
 
+int read_xcd_split(MechPopulation* P, uint32_t* split)
+{
+    if (!P) return fail(MECH_E_INVALID, "population is NULL");
+    if (!split) return fail(MECH_E_INVALID, "split is NULL");
+    MechBatch* B = P->b;
+    HIP_TRY(hipSetDevice(B->device));
+    const int rc = sync_check(B);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpy(split, B->arena + B->L.split, (N_XCD + 1) * 4, hipMemcpyDeviceToHost));
+    return MECH_OK;
+}
+
 int population_set_reorder(MechPopulation* P, int32_t every)
 {
     if (!P) return fail(MECH_E_INVALID, "population is NULL");

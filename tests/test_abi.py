@@ -213,6 +213,7 @@ def test_null_handles_are_rejected():
     lib = B.lib()
     assert lib.step_mechanics(None, 1) == B.MECH_E_INVALID
     assert lib.read_stats(None, None, None, None) == B.MECH_E_INVALID
+    assert lib.read_xcd_split(None, None) == B.MECH_E_INVALID
     assert lib.destroy_population(None) == B.MECH_OK
     assert lib.population_stream(None) is None
 
