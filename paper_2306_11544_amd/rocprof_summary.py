@@ -66,7 +66,21 @@ def _short(name: str) -> str:
     return s if len(s) <= 110 else s[:107] + "..."
 
 
-def stats(path: str, command: str, top: int = 25, sources=(SOURCE,)) -> str:
+def last_dispatches(trace_path: str, kernel: str, n: int) -> str:
+    """Mean, min and max duration of the last n dispatches (by start time) of the kernels
+    whose name contains `kernel`, from a kernel-trace CSV: the launches a run times last."""
+    d = [(int(r["Start_Timestamp"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+         for r in csv.DictReader(open(trace_path)) if kernel in r["Kernel_Name"]]
+    if len(d) < n:
+        raise SystemExit(f"{len(d)} dispatches of {kernel!r}, fewer than {n}")
+    last = [dt for _, dt in sorted(d)[-n:]]
+    return (f"last {n} dispatches of {kernel}: mean {sum(last) / n / 1e3:.3f} us, "
+            f"min {min(last) / 1e3:.3f}, max {max(last) / 1e3:.3f}")
+
+
+def stats(path: str, command: str, top: int = 25, sources=(SOURCE,), last=None) -> str:
+    """Per-kernel totals of a kernel-stats CSV; with last = (kernel-trace CSV, kernel, n)
+    also the mean of that kernel's last n dispatches."""
     rows = list(csv.DictReader(open(path)))
     total = sum(float(r["TotalDurationNs"]) for r in rows)
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
@@ -77,6 +91,8 @@ def stats(path: str, command: str, top: int = 25, sources=(SOURCE,)) -> str:
         out.append(f"{int(r['Calls']):7d} {float(r['AverageNs']) / 1e3:10.3f} "
                    f"{float(r['MinNs']) / 1e3:10.3f} {float(r['MaxNs']) / 1e3:10.3f} "
                    f"{100.0 * float(r['TotalDurationNs']) / total:6.2f}  {_short(r['Name'])}")
+    if last is not None:
+        out += ["", last_dispatches(*last)]
     return "\n".join(out) + "\n"
 
 
@@ -207,6 +223,8 @@ def main(argv=None):
     s.add_argument("--top", type=int, default=25)
     s.add_argument("--source", action="append", default=None,
                    help="kernel source(s) whose code hash the summary records (default csrc/mech.hip)")
+    s.add_argument("--last", nargs=3, metavar=("TRACE_CSV", "KERNEL", "N"), default=None,
+                   help="also the mean of KERNEL's last N dispatches in the kernel-trace CSV")
     t = sub.add_parser("traffic")
     t.add_argument("--fetch", required=True)
     t.add_argument("--write", required=True)
@@ -226,7 +244,8 @@ def main(argv=None):
     m.add_argument("--source", default=SOURCE)
     a = ap.parse_args(argv)
     if a.cmd == "stats":
-        sys.stdout.write(stats(a.csv, a.command, a.top, tuple(a.source or (SOURCE,))))
+        last = None if a.last is None else (a.last[0], a.last[1], int(a.last[2]))
+        sys.stdout.write(stats(a.csv, a.command, a.top, tuple(a.source or (SOURCE,)), last))
     elif a.cmd == "traffic":
         sys.stdout.write(traffic(a))
     else:

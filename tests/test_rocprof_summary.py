@@ -44,3 +44,19 @@ def test_pmc_without_candidates_has_no_per_candidate_line(tmp_path):
     out = rs.pmc([str(a)], "kk", ["c"])
     assert _field(out, "derived lane_utilisation") == pytest.approx(1.0)
     assert "per_candidate" not in out
+
+
+def test_last_dispatches_takes_the_latest_by_start_time(tmp_path):
+    p = tmp_path / "trace.csv"
+    with open(p, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Kernel_Name", "Start_Timestamp", "End_Timestamp"])
+        w.writeheader()
+        # written out of order; durations 10, 20, 30, 40 us by start time, plus another kernel
+        for start, dur in ((3000, 30), (1000, 10), (4000, 40), (2000, 20)):
+            w.writerow({"Kernel_Name": "k_force_cells<0>", "Start_Timestamp": start * 1000,
+                        "End_Timestamp": start * 1000 + dur * 1000})
+        w.writerow({"Kernel_Name": "k_bin", "Start_Timestamp": 9_000_000, "End_Timestamp": 9_900_000})
+    line = rs.last_dispatches(str(p), "k_force_cells", 2)
+    assert "mean 35.000 us" in line and "min 30.000" in line and "max 40.000" in line
+    with pytest.raises(SystemExit):
+        rs.last_dispatches(str(p), "k_force_cells", 5)
