@@ -1617,13 +1617,28 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
     // rounding of its decision (2^-50 in FP64, a few 2^-24 in FP32, there plus the
     // rounding of the positions to float, at most 2^-22 P S units, which q_pad covers),
     // so sqrt(D) < t - Q_MARGIN + 2 and every interacting pair is listed.
-    auto near = [&](uint2 c) -> bool {
-        const ushort2v du = __builtin_bit_cast(ushort2v, q_xy) - __builtin_bit_cast(ushort2v, c.x);
-        const int dz = (int)(short)(uint16_t)(q_z - c.y);
-        const int d2 = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2v, du), __builtin_bit_cast(short2v, du),
-                                              dz * dz, false);
-        const uint32_t t = q_a + (c.y >> 16);
-        return (uint32_t)d2 < __umul24(t, t);
+    // The test takes D - t^2 in int32 from three int16 pairs: du = (dx, dy), w = (dz, -t)
+    // and (dz, t), with D - t^2 = du.du + w.(dz, t).  t < 2^15 (each reach is at most 2^12
+    // units and the domain check bounds q_pad), so -t is an int16; |D - t^2| < 2^31.  The
+    // sign bit of D - t^2 is the decision.
+    const uint32_t q_zt = q_z | ((0u - q_a) & 0xffffu) << 16;   // (q_z, -q_a) as two int16
+    auto gap = [&](uint2 c) -> int {
+        const short2v du = __builtin_bit_cast(
+            short2v, __builtin_bit_cast(ushort2v, q_xy) - __builtin_bit_cast(ushort2v, c.x));
+        const short2v w = __builtin_bit_cast(
+            short2v, __builtin_bit_cast(ushort2v, q_zt) - __builtin_bit_cast(ushort2v, c.y));
+        const short2v wt = w * (short2v){1, -1};
+        // clamp set on the first product (it never saturates: |dz^2 - t^2| < 2^31) selects the
+        // three-operand form, whose zero addend is an inline constant and not a register move
+        return __builtin_amdgcn_sdot2(du, du, __builtin_amdgcn_sdot2(w, wt, 0, true), false);
+    };
+    auto near = [&](uint2 c) -> bool { return gap(c) < 0; };
+    // bit u set when candidate c[u] is listed, u < N: the signs shifted in from the last
+    auto bits = [&](const uint2* c, auto N) -> uint32_t {
+        uint32_t m = 0;
+#pragma unroll
+        for (int u = decltype(N)::value - 1; u >= 0; --u) m = __builtin_amdgcn_alignbit(m, (uint32_t)gap(c[u]), 31);
+        return m;
     };
     // The candidate data a flush evaluates.  With the long lists (few waves per SIMD
     // hide little latency) the next entry's data is fetched before the current one is
@@ -1739,11 +1754,10 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
 #pragma unroll
                 for (int u = 0; u < FC_UNROLL; ++u) c[u] = sp[u];
                 if constexpr (PACK) {
+                    const uint32_t mb = bits(c, std::integral_constant<int, FC_UNROLL>{});
 #pragma unroll
                     for (int g4 = 0; g4 < FC_UNROLL; g4 += 4) {
-                        uint32_t m = 0;
-#pragma unroll
-                        for (int u = g4; u < FC_UNROLL && u < g4 + 4; ++u) m |= (near(c[u]) ? 1u : 0u) << (u - g4);
+                        const uint32_t m = (mb >> g4) & 15u;
                         push(((j + g4) << 4) | m, m != 0u);
                     }
                 } else {
@@ -1762,12 +1776,11 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
 #pragma unroll
                 for (int u = 0; u < FC_UNROLL; ++u) c[u] = sp[u];
                 if constexpr (PACK) {
+                    // the bits at and past the row's end are masked off (lim < FC_UNROLL)
+                    const uint32_t mb = bits(c, std::integral_constant<int, FC_UNROLL>{}) & ((1u << lim) - 1u);
 #pragma unroll
                     for (int g4 = 0; g4 < FC_UNROLL; g4 += 4) {
-                        uint32_t m = 0;
-#pragma unroll
-                        for (int u = g4; u < FC_UNROLL && u < g4 + 4; ++u)
-                            m |= (uint32_t)(near(c[u]) & ((uint32_t)u < lim)) << (u - g4);   // no branch
+                        const uint32_t m = (mb >> g4) & 15u;
                         push(((j + g4) << 4) | m, m != 0u);
                     }
                 } else {
@@ -2287,16 +2300,16 @@ double quant_scale(double h) { return std::ldexp(1.0, (int)std::floor(std::log2(
 int validate_domain(const double lo[3], const double hi[3], double h, int32_t dims[3], uint64_t* V)
 {
     // The quantised shadow rounds x S to an integer: it must stay exact in a double (and
-    // S finite in a float).  The prefilter squares its threshold t = (reach_i + reach_j
-    // + Q_MARGIN + q_pad) units in 32 bits, so t must stay below 2^16: each reach is at
-    // most alpha r_max S <= h S / 2 <= 2^12 units (the voxel holds 2 alpha r_max), and
-    // q_pad = ceil(2^-20 P S) grows with the largest coordinate P.
+    // S finite in a float).  The prefilter takes its threshold t = (reach_i + reach_j
+    // + Q_MARGIN + q_pad) units as an int16 and squares it in 32 bits, so t must stay
+    // below 2^15: each reach is at most alpha r_max S <= h S / 2 <= 2^12 units (the voxel
+    // holds 2 alpha r_max), and q_pad = ceil(2^-20 P S) grows with the largest coordinate P.
     {
         const double S = quant_scale(h);
         double pm = 0.0;
         for (int a = 0; a < 3; ++a) pm = std::max(pm, std::max(std::fabs(lo[a]), std::fabs(hi[a])));
         if (!(S < 0x1p100)) return fail(MECH_E_INVALID, "voxel_size %.17g is too small", h);
-        if (!(pm * S < 0x1p52) || !(std::ceil(pm * S * 0x1p-20) + 2.0 * 4096.0 + (double)Q_MARGIN < 65536.0))
+        if (!(pm * S < 0x1p52) || !(std::ceil(pm * S * 0x1p-20) + 2.0 * 4096.0 + (double)Q_MARGIN < 32768.0))
             return fail(MECH_E_INVALID, "domain coordinates up to %.17g um are too large for voxel_size %.17g "
                         "(the prefilter's margin would overflow)", pm, h);
     }

@@ -139,8 +139,9 @@ def _p(**kw):
     (lambda p: p.domain_hi.__setitem__(0, -200.0), B.MECH_E_INVALID),
     # the quantised prefilter needs |x| S < 2^52 (S = 256 per um at a 30 um voxel)
     (lambda p: p.domain_hi.__setitem__(1, 2.0 ** 45), B.MECH_E_INVALID),
-    # ... and its squared threshold below 2^32: ceil(2^-20 |x| S) + 2 * 2^12 + 3 < 2^16,
-    # which fails from |x| ~ 2.35e8 um at S = 256 (t^2 would wrap and drop pairs)
+    # ... and its threshold an int16: ceil(2^-20 |x| S) + 2 * 2^12 + 3 < 2^15, which fails
+    # from |x| ~ 1.007e8 um at S = 256 (-t would wrap and drop pairs)
+    (lambda p: p.domain_lo.__setitem__(2, -1.02e8), B.MECH_E_INVALID),
     (lambda p: p.domain_lo.__setitem__(2, -2.4e8), B.MECH_E_INVALID),
     (lambda p: p.domain_hi.__setitem__(0, 3.0e8), B.MECH_E_INVALID),
     (lambda p: setattr(p, "voxel_size", 1e-40), B.MECH_E_INVALID),
@@ -194,9 +195,9 @@ def test_create_rejects_bad_cells_before_any_device_call(case, code):
 
 def test_prefilter_bound_accepts_large_valid_domains():
     """Just inside the threshold bound a domain is accepted (S = 256 per um at 30 um:
-    ceil(2^-20 * 2.3e8 * 256) = 56,153 units, + 8192 + 3 < 65,536)."""
+    ceil(2^-20 * 1.0e8 * 256) = 24,415 units, + 8192 + 3 < 32,768)."""
     p, _ = _p()
-    p.domain_lo[2] = -2.3e8
+    p.domain_lo[2] = -1.0e8
     assert B.population_workspace_bytes(p, 10) > 0
 
 
