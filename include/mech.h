@@ -82,7 +82,10 @@ typedef struct MechParams {
     int32_t precision;          /* MECH_FP64 | MECH_FP32 | MECH_FP32_KAHAN             */
     int32_t ab2_start;          /* history of the first step when none is given        */
     int32_t flags;              /* MECH_FLAG_* bits, otherwise 0                        */
-    double domain_lo[3];        /* um; reflecting walls                                 */
+    double domain_lo[3];        /* um; reflecting walls.  |lo|, |hi| < 24572 * 2^20 / S
+                                   with S the largest power of two with h S <= 2^13
+                                   (1.0e8 um at h = 30 um), else MECH_E_INVALID: the
+                                   prefilter's quantised threshold is an int16          */
     double domain_hi[3];
     double voxel_size;          /* h, um (30)                                           */
     double dt;                  /* min (0.1)                                            */
