@@ -1580,9 +1580,9 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
     // The short list (LIST = 16, picked for dense populations) is a ring,
     // list0[(k mod LIST) * WAVE]: the listed entries run from head up to tail
     // (excluded), oldest first, and a flush inside the walk evaluates only the oldest
-    // entries (below).  In the ring an entry is up to 4 candidates of a trip:
-    // (j << 4) | m, the candidates j + u with bit u of m set (j < 2^28), so a trip of 4
-    // writes one entry and moves tail at most once.  The
+    // entries (below).  In the ring an entry is up to EB candidates of a trip:
+    // (j << EB) | m, the candidates j + u with bit u of m set (j < 2^(32 - EB); EB = 8 for
+    // trips of 8 of one cell type, else 4), so a trip of EB writes one entry.  The
     // long lists (32, 64: small populations, few waves per SIMD) and the walk through
     // perm hold one candidate per entry, from list0, emptied whole.  Every trip writes
     // its entry at tail, which advances only when the entry holds a candidate (no
@@ -1593,11 +1593,14 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
     constexpr bool PACK = RING && !IND;
     constexpr uint32_t MASK = RING ? (uint32_t)LIST - 1u : 0xffffffffu;
     static_assert(!RING || (LIST & (LIST - 1)) == 0, "the ring length is a power of two");
-    // packed entries a trip writes (4 candidates each at most), entries after which a
+    // candidates per packed entry, packed entries a trip writes, entries after which a
     // trip flushes, and entries a lane may keep after a flush: the packed ring flushes
     // only as much as the next trip needs, so that each pass finds entries in as many
     // lanes as possible (measured: 2% faster than keeping 10 of 16)
-    constexpr uint32_t EPT = (uint32_t)(FC_UNROLL + 3) / 4u;
+    // (entries of 8 for trips of 8 of one cell type: the single-type tumour ran 7% faster
+    // in FP32 with them, the two-type batch of spheroids 4% slower)
+    constexpr uint32_t EB = FC_UNROLL == 8 && !MULTI ? 8u : 4u, EMASK = (1u << EB) - 1u;
+    constexpr uint32_t EPT = ((uint32_t)FC_UNROLL + EB - 1u) / EB;
     constexpr uint32_t FULL = PACK ? (uint32_t)LIST - EPT : (uint32_t)(LIST - FC_UNROLL);
     constexpr uint32_t KEEP = PACK ? FULL - 1u : RING ? (uint32_t)LIST * 5u / 8u : 0u;
     static_assert(KEEP < FULL, "a flush makes room for the next trip");
@@ -1689,9 +1692,9 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
                 if (!__any(c > keep)) break;
                 if (c > 0) {
                     const uint32_t e = list0[head * WAVE];
-                    const uint32_t m = e & 15u & ~done;
+                    const uint32_t m = e & EMASK & ~done;
                     const uint32_t b = (uint32_t)__builtin_ctz(m);
-                    eval(fetch((e >> 4) + b));
+                    eval(fetch((e >> EB) + b));
                     const bool last = (m & (m - 1u)) == 0u;
                     done = last ? 0u : done | (1u << b);
                     head = (head + (last ? 1u : 0u)) & MASK;
@@ -1755,10 +1758,14 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
                 for (int u = 0; u < FC_UNROLL; ++u) c[u] = sp[u];
                 if constexpr (PACK) {
                     const uint32_t mb = bits(c, std::integral_constant<int, FC_UNROLL>{});
+                    if constexpr (EB == 8) {
+                        push((j << 8) | mb, mb != 0u);
+                    } else {
 #pragma unroll
-                    for (int g4 = 0; g4 < FC_UNROLL; g4 += 4) {
-                        const uint32_t m = (mb >> g4) & 15u;
-                        push(((j + g4) << 4) | m, m != 0u);
+                        for (int g4 = 0; g4 < FC_UNROLL; g4 += 4) {
+                            const uint32_t m = (mb >> g4) & 15u;
+                            push(((j + g4) << 4) | m, m != 0u);
+                        }
                     }
                 } else {
 #pragma unroll
@@ -1778,10 +1785,14 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
                 if constexpr (PACK) {
                     // the bits at and past the row's end are masked off (lim < FC_UNROLL)
                     const uint32_t mb = bits(c, std::integral_constant<int, FC_UNROLL>{}) & ((1u << lim) - 1u);
+                    if constexpr (EB == 8) {
+                        push((j << 8) | mb, mb != 0u);
+                    } else {
 #pragma unroll
-                    for (int g4 = 0; g4 < FC_UNROLL; g4 += 4) {
-                        const uint32_t m = (mb >> g4) & 15u;
-                        push(((j + g4) << 4) | m, m != 0u);
+                        for (int g4 = 0; g4 < FC_UNROLL; g4 += 4) {
+                            const uint32_t m = (mb >> g4) & 15u;
+                            push(((j + g4) << 4) | m, m != 0u);
+                        }
                     }
                 } else {
 #pragma unroll
@@ -1823,13 +1834,15 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
     #pragma unroll
                 for (int u = 0; u < FC_UNROLL; ++u) c[u] = a.QS[j + u];
                 if constexpr (PACK) {
+                    const uint32_t mb = bits(c, std::integral_constant<int, FC_UNROLL>{}) & ((1u << lim) - 1u);
+                    if constexpr (EB == 8) {
+                        push((j << 8) | mb, mb != 0u);
+                    } else {
     #pragma unroll
-                    for (int g4 = 0; g4 < FC_UNROLL; g4 += 4) {
-                        uint32_t mk = 0;
-    #pragma unroll
-                        for (int u = g4; u < FC_UNROLL && u < g4 + 4; ++u)
-                            mk |= ((uint32_t)u < lim && near(c[u]) ? 1u : 0u) << (u - g4);
-                        push(((j + g4) << 4) | mk, mk != 0u);
+                        for (int g4 = 0; g4 < FC_UNROLL; g4 += 4) {
+                            const uint32_t m = (mb >> g4) & 15u;
+                            push(((j + g4) << 4) | m, m != 0u);
+                        }
                     }
                 } else {
     #pragma unroll
@@ -2538,12 +2551,17 @@ template <int PREC, bool MULTI, typename VPT, int WPB, int LIST, bool PRUNE>
 void launch_cells_p(MechBatch* B, const ForceArgs<VPT>& args)
 {
     const dim3 grid(force_cell_grid(B, WPB)), block(WPB * WAVE);
+    // a ring entry of a single-type trip of 8 holds candidate indices below 2^24: larger
+    // arenas take trips of 4 (same results: the candidates are listed and evaluated in the
+    // same order)
+    const int unroll = !MULTI && LIST < 32 && B->tune.unroll == 8 && B->cap_cells >= ((int64_t)1 << 24)
+                           ? 4 : B->tune.unroll;
     ForceArgs<VPT> a = args;
     if (!force_balanced(B)) {
         a.work = nullptr;
         a.split = nullptr;
     }
-    switch (B->tune.unroll) {
+    switch (unroll) {
     case 2:
         hipLaunchKernelGGL((k_force_cells<PREC, MULTI, VPT, WPB, 2, LIST, false, PRUNE>), grid, block, 0, B->stream,
                            B->phys, a);
