@@ -170,6 +170,28 @@ __device__ __forceinline__ uint2 quantise(double x, double y, double z, double r
     return make_uint2(qx | (qy << 16), qz | (qr << 16));
 }
 
+// Candidates of one neighbour row a wave stages in LDS for its lanes (the union of their
+// slab windows), and the padding a masked trip may read past them.
+constexpr uint32_t STAGE_CAP = 256;
+#ifndef MECH_STAGE_ROWS
+#define MECH_STAGE_ROWS 1
+#endif
+constexpr bool STAGE_ROWS = MECH_STAGE_ROWS != 0;
+
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v)
+{
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, o, WAVE));
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v)
+{
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o, WAVE));
+    return v;
+}
+
 // Work table of the per-cell force kernel: BAL_ENTRIES sums of wave durations, each over
 // `group` consecutive wave64s of cells (group grows with the population so the table
 // covers it), read and cleared by one workgroup of the next step's k_bin.
@@ -1482,8 +1504,12 @@ __global__ __launch_bounds__(WPB * WAVE) void k_force_rows(PhysArgs P, ForceArgs
 template <int PREC, bool MULTI, typename VPT, int FC_UNROLL, int LIST, bool IND = false, bool PRUNE = false>
 __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceArgs<VPT>& a, uint32_t i,
                                                  uint32_t n, uint32_t* const list0, uint2* const rng0,
-                                                 uint32_t& inter, uint32_t& cand)
+                                                 uint2* const stage0, uint32_t& inter, uint32_t& cand)
 {
+    // the slab walk stages shared rows in LDS (stage0: STAGE_CAP + FC_UNROLL entries); in
+    // the one-type FP64 kernel only, whose candidate stream limits it most (the others ran
+    // slower with the registers staging takes)
+    constexpr bool STAGE = !PRUNE && !IND && PREC == 0 && !MULTI && STAGE_ROWS;
     using Real = typename std::conditional<PREC == 0, double, float>::type;
     const bool in_pop = i < n;
     const uint32_t ii = in_pop ? i : n - 1;  // idle lanes mirror the last cell
@@ -1735,70 +1761,195 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
             j = r0 < 0 ? 0u : a.voxel_start[XSUB * r0 + w0];
             e = r0 < 0 ? 0u : a.voxel_start[XSUB * r0 + w1];
         };
-        uint32_t j_next, e_next;
-        range(0, j_next, e_next);
-        for (int q = 0; q < 9; ++q) {
-            uint32_t j = j_next;
-            const uint32_t e = e_next;
-            if (q < 8) range(q + 1, j_next, e_next);
-            cand += e - j;
-            if constexpr (IND) {
-                // gathers through the sorted order: no locality between consecutive lanes
-                for (; j < e; ++j) {
-                    const uint32_t jj = a.perm[j];
-                    push(jj, near(a.QS[jj]));
+        if constexpr (STAGE) {
+            // A row's candidates [j, e) from src (src[0] is candidate j): trips of FC_UNROLL,
+            // then one masked trip for the rest.
+            auto walk = [&](auto sp, uint32_t j, const uint32_t e) {
+                for (; j + FC_UNROLL <= e; j += FC_UNROLL, sp += FC_UNROLL) {
+                    uint2 c[FC_UNROLL];
+    #pragma unroll
+                    for (int u = 0; u < FC_UNROLL; ++u) c[u] = sp[u];
+                    if constexpr (PACK) {
+                        const uint32_t mb = bits(c, std::integral_constant<int, FC_UNROLL>{});
+                        if constexpr (EB == 8) {
+                            push((j << 8) | mb, mb != 0u);
+                        } else {
+    #pragma unroll
+                            for (int g4 = 0; g4 < FC_UNROLL; g4 += 4) {
+                                const uint32_t m = (mb >> g4) & 15u;
+                                push(((j + g4) << 4) | m, m != 0u);
+                            }
+                        }
+                    } else {
+    #pragma unroll
+                        for (int u = 0; u < FC_UNROLL; ++u) push(j + u, near(c[u]));
+                    }
                     if (full()) flush(KEEP);
                 }
-                continue;
-            }
-            const uint2* sp = a.QS + j;
-            for (; j + FC_UNROLL <= e; j += FC_UNROLL, sp += FC_UNROLL) {
-                uint2 c[FC_UNROLL];
-#pragma unroll
-                for (int u = 0; u < FC_UNROLL; ++u) c[u] = sp[u];
-                if constexpr (PACK) {
-                    const uint32_t mb = bits(c, std::integral_constant<int, FC_UNROLL>{});
-                    if constexpr (EB == 8) {
-                        push((j << 8) | mb, mb != 0u);
+                // fewer than FC_UNROLL left: one more trip, testing only the candidates below e
+                // (the shadow array is padded by QS_PAD >= 2 FC_UNROLL entries past the last
+                // cell and the stage by FC_UNROLL, so a trip that starts below e reads inside
+                // them; a lane with nothing left reads from its e and lists nothing)
+                if (__any(j < e)) {
+                    const uint32_t lim = j < e ? e - j : 0u;
+                    uint2 c[FC_UNROLL];
+    #pragma unroll
+                    for (int u = 0; u < FC_UNROLL; ++u) c[u] = sp[u];
+                    if constexpr (PACK) {
+                        // the bits at and past the row's end are masked off (lim < FC_UNROLL)
+                        const uint32_t mb = bits(c, std::integral_constant<int, FC_UNROLL>{}) & ((1u << lim) - 1u);
+                        if constexpr (EB == 8) {
+                            push((j << 8) | mb, mb != 0u);
+                        } else {
+    #pragma unroll
+                            for (int g4 = 0; g4 < FC_UNROLL; g4 += 4) {
+                                const uint32_t m = (mb >> g4) & 15u;
+                                push(((j + g4) << 4) | m, m != 0u);
+                            }
+                        }
                     } else {
-#pragma unroll
-                        for (int g4 = 0; g4 < FC_UNROLL; g4 += 4) {
-                            const uint32_t m = (mb >> g4) & 15u;
-                            push(((j + g4) << 4) | m, m != 0u);
+    #pragma unroll
+                        for (int u = 0; u < FC_UNROLL; ++u) push(j + u, near(c[u]) & ((uint32_t)u < lim));
+                    }
+                    if (full()) flush(KEEP);
+                }
+            };
+            // Shared rows: when the wave's working lanes sit in one y-z row of voxels of one
+            // simulation (the common case: 64 consecutive cells span two or three voxels along
+            // x), they read the same 9 neighbour rows, and each lane's slab window is one
+            // range [A0, A1) of absolute x slabs, the same in every row.  The wave then stages
+            // the union of the lanes' windows of a row, [U0, U1), into LDS once (coalesced,
+            // one load per candidate instead of one per lane that reads it) and the lanes walk
+            // their own windows there: the vector memory return path carried each lane's copy.
+            // Rows whose union exceeds the stage, and waves that span two rows, walk from the
+            // shadow in memory.  Same candidates, same order: the results are unchanged.
+            bool share = false;
+            uint32_t s_min = 0, s_max = 0, s_base = 0;
+            int s_ky = 0, s_kz = 0, s_nx = 0, s_ny = 0, s_nz = 0;
+            if constexpr (STAGE) {
+                const uint64_t vm = __ballot(valid);
+                if (vm != 0u) {
+                    const int ref = __ffsll((long long)vm) - 1;
+                    s_ky = __shfl(g.ky, ref, WAVE);
+                    s_kz = __shfl(g.kz, ref, WAVE);
+                    const uint32_t voff = (uint32_t)__shfl((int)d.voxel_off, ref, WAVE);
+                    share = __all(!valid || (g.ky == s_ky && g.kz == s_kz && d.voxel_off == voff));
+                    if (share) {
+                        // every row decision below uses the working lanes' simulation (lanes of a
+                        // finished one, or idle lanes, may hold another): wave-uniform values
+                        const uint32_t a0 = (uint32_t)(XSUB * g.x0) + w0, a1 = (uint32_t)(XSUB * g.x0) + w1;
+                        s_min = __builtin_amdgcn_readfirstlane(wave_min_u32(valid ? a0 : 0xffffffffu));
+                        s_max = __builtin_amdgcn_readfirstlane(wave_max_u32(valid ? a1 : 0u));
+                        s_ky = __builtin_amdgcn_readfirstlane(s_ky);
+                        s_kz = __builtin_amdgcn_readfirstlane(s_kz);
+                        s_base = __builtin_amdgcn_readfirstlane(voff);
+                        s_nx = __builtin_amdgcn_readfirstlane(__shfl(d.nx, ref, WAVE));
+                        s_ny = __builtin_amdgcn_readfirstlane(__shfl(d.ny, ref, WAVE));
+                        s_nz = __builtin_amdgcn_readfirstlane(__shfl(d.nz, ref, WAVE));
+                    }
+                }
+            }
+            uint32_t j_next, e_next;
+            range(0, j_next, e_next);
+            for (int q = 0; q < 9; ++q) {
+                uint32_t j = j_next;
+                const uint32_t e = e_next;
+                if (q < 8) range(q + 1, j_next, e_next);
+                cand += e - j;
+                if constexpr (IND) {
+                    // gathers through the sorted order: no locality between consecutive lanes
+                    for (; j < e; ++j) {
+                        const uint32_t jj = a.perm[j];
+                        push(jj, near(a.QS[jj]));
+                        if (full()) flush(KEEP);
+                    }
+                    continue;
+                }
+                if constexpr (STAGE) {
+                    if (share) {
+                        const int y = s_ky + q % 3 - 1, z = s_kz + q / 3 - 1;
+                        if (y < 0 || y >= s_ny || z < 0 || z >= s_nz) continue;   // no row: every window empty
+                        const uint32_t b = XSUB * (s_base + (uint32_t)s_nx * ((uint32_t)y + (uint32_t)s_ny * (uint32_t)z));
+                        const uint32_t u0 = a.voxel_start[b + s_min], u1 = a.voxel_start[b + s_max];
+                        if (u1 - u0 <= STAGE_CAP) {
+                            __builtin_amdgcn_wave_barrier();   // the last row's reads are issued
+                            for (uint32_t k = threadIdx.x & (WAVE - 1); k < u1 - u0; k += WAVE) stage0[k] = a.QS[u0 + k];
+                            __builtin_amdgcn_wave_barrier();   // ... and this row's writes, before its reads
+                            // a lane with no window (idle, or its simulation done) has j = e = 0:
+                            // its masked trip reads from the stage's start
+                            walk(stage0 + (j >= u0 ? j - u0 : 0u), j, e);
+                            continue;
                         }
                     }
-                } else {
-#pragma unroll
-                    for (int u = 0; u < FC_UNROLL; ++u) push(j + u, near(c[u]));
                 }
-                if (full()) flush(KEEP);
+                walk(a.QS + j, j, e);
             }
-            // fewer than FC_UNROLL left: one more trip, testing only the candidates below e
-            // (the shadow array is padded by QS_PAD >= 2 FC_UNROLL entries past the last
-            // cell, so a trip that starts below e reads inside it; a lane with nothing left
-            // reads from its e and lists nothing)
-            if (__any(j < e)) {
-                const uint32_t lim = j < e ? e - j : 0u;
-                uint2 c[FC_UNROLL];
-#pragma unroll
-                for (int u = 0; u < FC_UNROLL; ++u) c[u] = sp[u];
-                if constexpr (PACK) {
-                    // the bits at and past the row's end are masked off (lim < FC_UNROLL)
-                    const uint32_t mb = bits(c, std::integral_constant<int, FC_UNROLL>{}) & ((1u << lim) - 1u);
-                    if constexpr (EB == 8) {
-                        push((j << 8) | mb, mb != 0u);
-                    } else {
-#pragma unroll
-                        for (int g4 = 0; g4 < FC_UNROLL; g4 += 4) {
-                            const uint32_t m = (mb >> g4) & 15u;
-                            push(((j + g4) << 4) | m, m != 0u);
-                        }
+        } else {
+            uint32_t j_next, e_next;
+            range(0, j_next, e_next);
+            for (int q = 0; q < 9; ++q) {
+                uint32_t j = j_next;
+                const uint32_t e = e_next;
+                if (q < 8) range(q + 1, j_next, e_next);
+                cand += e - j;
+                if constexpr (IND) {
+                    // gathers through the sorted order: no locality between consecutive lanes
+                    for (; j < e; ++j) {
+                        const uint32_t jj = a.perm[j];
+                        push(jj, near(a.QS[jj]));
+                        if (full()) flush(KEEP);
                     }
-                } else {
-#pragma unroll
-                    for (int u = 0; u < FC_UNROLL; ++u) push(j + u, near(c[u]) & ((uint32_t)u < lim));
+                    continue;
                 }
-                if (full()) flush(KEEP);
+                const uint2* sp = a.QS + j;
+                for (; j + FC_UNROLL <= e; j += FC_UNROLL, sp += FC_UNROLL) {
+                    uint2 c[FC_UNROLL];
+    #pragma unroll
+                    for (int u = 0; u < FC_UNROLL; ++u) c[u] = sp[u];
+                    if constexpr (PACK) {
+                        const uint32_t mb = bits(c, std::integral_constant<int, FC_UNROLL>{});
+                        if constexpr (EB == 8) {
+                            push((j << 8) | mb, mb != 0u);
+                        } else {
+    #pragma unroll
+                            for (int g4 = 0; g4 < FC_UNROLL; g4 += 4) {
+                                const uint32_t m = (mb >> g4) & 15u;
+                                push(((j + g4) << 4) | m, m != 0u);
+                            }
+                        }
+                    } else {
+    #pragma unroll
+                        for (int u = 0; u < FC_UNROLL; ++u) push(j + u, near(c[u]));
+                    }
+                    if (full()) flush(KEEP);
+                }
+                // fewer than FC_UNROLL left: one more trip, testing only the candidates below e
+                // (the shadow array is padded by QS_PAD >= 2 FC_UNROLL entries past the last
+                // cell, so a trip that starts below e reads inside it; a lane with nothing left
+                // reads from its e and lists nothing)
+                if (__any(j < e)) {
+                    const uint32_t lim = j < e ? e - j : 0u;
+                    uint2 c[FC_UNROLL];
+    #pragma unroll
+                    for (int u = 0; u < FC_UNROLL; ++u) c[u] = sp[u];
+                    if constexpr (PACK) {
+                        // the bits at and past the row's end are masked off (lim < FC_UNROLL)
+                        const uint32_t mb = bits(c, std::integral_constant<int, FC_UNROLL>{}) & ((1u << lim) - 1u);
+                        if constexpr (EB == 8) {
+                            push((j << 8) | mb, mb != 0u);
+                        } else {
+    #pragma unroll
+                            for (int g4 = 0; g4 < FC_UNROLL; g4 += 4) {
+                                const uint32_t m = (mb >> g4) & 15u;
+                                push(((j + g4) << 4) | m, m != 0u);
+                            }
+                        }
+                    } else {
+    #pragma unroll
+                        for (int u = 0; u < FC_UNROLL; ++u) push(j + u, near(c[u]) & ((uint32_t)u < lim));
+                    }
+                    if (full()) flush(KEEP);
+                }
             }
         }
     } else {
@@ -1881,10 +2032,15 @@ __global__ __launch_bounds__(WPB * WAVE) void k_force_cells(PhysArgs P, ForceArg
     const uint32_t nb = (n + TB - 1) / TB;
     uint32_t* const list0 = &s_list[threadIdx.x / WAVE][0][threadIdx.x & (WAVE - 1)];
     uint2* rng0 = nullptr;
+    uint2* stage0 = nullptr;
     if constexpr (PRUNE) {
-        // the pruned walk's runs; the slab walk takes no LDS beyond its lists
+        // the pruned walk's runs
         __shared__ uint2 s_rng[WPB][9][WAVE];
         rng0 = &s_rng[threadIdx.x / WAVE][0][threadIdx.x & (WAVE - 1)];
+    } else if constexpr (!IND && PREC == 0 && !MULTI && STAGE_ROWS) {
+        // the slab walk's staged row
+        __shared__ uint2 s_stage[WPB][STAGE_CAP + UNROLL];
+        stage0 = &s_stage[threadIdx.x / WAVE][0];
     }
     uint32_t inter = 0, cand = 0;
     // Each XCD takes one contiguous run of tiles, so its L2 keeps the neighbours its
@@ -1917,7 +2073,7 @@ __global__ __launch_bounds__(WPB * WAVE) void k_force_cells(PhysArgs P, ForceArg
         // read unconditionally: a conditional read costs the FP64 kernels a register
         const uint64_t c0 = wall_clock64();
         force_cells_cell<PREC, MULTI, VPT, UNROLL, LIST, IND, PRUNE>(P, a, t * TB + threadIdx.x, n, list0, rng0,
-                                                                     inter, cand);
+                                                                     stage0, inter, cand);
         if (a.work) {
             // the wave's index among the wave64s of cells; waves past the last cell record
             // nothing, so the entry (wave / group) is below BAL_ENTRIES

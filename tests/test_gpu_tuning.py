@@ -126,3 +126,35 @@ def test_population_tuning():
             outs.append(P.state()[0])
     for o in outs[1:]:
         assert pos_err(o, outs[0], pop.half_width) <= 1e-12
+
+
+@pytest.mark.parametrize("case", ["core", "pile", "sparse"])
+def test_staged_rows_equal_inline_kernel_bitwise(case):
+    """The one-type FP64 list kernel stages a wave's shared rows in LDS: in a dense core
+    (rows staged), a pile denser than the stage holds (rows walked from memory in the
+    same waves) and scattered cells (waves spanning two rows), its trajectories are
+    bitwise those of the inline kernel, at several shapes."""
+    require_gpu()
+    if case == "core":
+        s = 0.2 ** (1.0 / 3.0)   # the 1M-cell tumour's density at 200k cells
+        pop = workloads.tumour(200_000, seed=81, steps=0, core_radius=600.0 * s, half=1000.0 * s)
+    elif case == "pile":
+        pop = workloads.plain(12_000, seed=82, steps=0, half=45.0)   # ~440 cells per voxel
+    else:
+        pop = workloads.plain(20_000, seed=83, steps=0, half=600.0)
+    p = B.params_of(pop, B.MECH_FP64)
+
+    def run(t):
+        with B.Population(p, pop.pos, pop.radius, pop.type) as P:
+            P.set_tuning(t)
+            P.step(6)
+            pos, vel = P.state()
+            _, inter, _ = P.stats()
+        return pos, vel, inter
+
+    say("staged rows", case, pop.n)
+    ref = run(B.tuning("rows", 4, 4, 0))
+    for cfg in [("cells", 1, 8, 0, 16), ("cells", 4, 4, 0, 16), ("cells", 2, 8, 0, 32), ("cells", 1, 2, 0, 64)]:
+        got = run(B.tuning(*cfg))
+        assert got[2] == ref[2], cfg
+        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), cfg
