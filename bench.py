@@ -483,6 +483,8 @@ def bench_batch(args):
     import torch
     torch.cuda.init()
     leg = leg_batch(args, n_sims=args.sims, steps=args.steps, warmup=args.warmup)
+    if args.calibrate_copy_mb:
+        copy_calibration(args.calibrate_copy_mb, torch.cuda.Stream(device=torch.device("cuda:0")))
     out = {"metric": "batched cell-steps/s (FP32, one launch per kernel for all simulations)",
            "value": leg["cell_steps_per_s"], "unit": "cell-steps/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": leg["ms_per_step"],
