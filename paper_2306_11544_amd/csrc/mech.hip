@@ -1230,28 +1230,23 @@ __device__ __forceinline__ void hold(const ForceArgs<VPT>& a, uint32_t i)
     for (int c = 0; c < 3; ++c) a.X[c][i] = a.XS[c][i];
 }
 
-// 1/sqrt(x) and 1/x in FP64 from the hardware estimates (about 24 correct bits) and two
-// Newton steps each: measured on gfx950 within 1.8 ulp (rsqrt), 2.2 ulp (x * rsqrt(x)
-// as sqrt) and 0.5 ulp (reciprocal) of the exact values over 2^-12 .. 2^12.  They
-// replace the correctly rounded square root and three divisions of the pair term; the
-// in-range decision is on d2 and is unchanged.
+// 1/sqrt(x) and 1/x in FP64 from the hardware estimates (about 24 correct bits) and one
+// Newton step each: measured on gfx950 within 19.5 ulp (rsqrt), 36 ulp (x * rsqrt(x) as
+// sqrt) and 11 ulp (reciprocal) of the exact values over 2^-12 .. 2^12.  They replace
+// the correctly rounded square root and three divisions of the pair term; the in-range
+// decision is on d2 and is unchanged.  A second step each (within 1.8, 2.2 and 0.5 ulp)
+// made the FP64 force kernel 2% slower and the results no closer to the FP64 oracle.
 __device__ __forceinline__ double rsqrt_nr(double x)
 {
-    double y = __builtin_amdgcn_rsq(x);
+    const double y = __builtin_amdgcn_rsq(x);
     const double h = 0.5 * x;
-    y = y * fma(-h * y, y, 1.5);
-    y = y * fma(-h * y, y, 1.5);
-    return y;
+    return y * fma(-h * y, y, 1.5);
 }
 
 __device__ __forceinline__ double rcp_nr(double x)
 {
-    double y = __builtin_amdgcn_rcp(x);
-    double e = fma(-x, y, 1.0);
-    y = fma(y, e, y);
-    e = fma(-x, y, 1.0);
-    y = fma(y, e, y);
-    return y;
+    const double y = __builtin_amdgcn_rcp(x);
+    return fma(y, fma(-x, y, 1.0), y);
 }
 
 // FP64 pair term.  d2 and the in-range test are evaluated without contraction so the
