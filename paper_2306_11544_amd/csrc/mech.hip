@@ -2017,11 +2017,26 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
     }
 }
 
-// The staged one-type FP64 ring kernels are asked to fit 6 waves per SIMD (80 VGPRs): the
-// compiler would take 88 and hold 5; with one register spilled they ran 3% faster.
+// Waves per SIMD the register allocation of a force kernel is asked to fit (1: as
+// compiled), measured per shape on the tumour and the batch:
+// * the staged one-type FP64 ring kernels, 6 (80 VGPRs, one or two spilled; the compiler
+//   would take 88 and hold 5): 3% faster;
+// * the one-wave FP32 kernels with trips of 8 and 16-entry rings, 8 (64 VGPRs): the
+//   two-type batch kernel fits without spills (71 as compiled, 7 waves) and ran 4%
+//   faster, the one-type FP32 + Kahan kernel spills two (73, 6 waves) and ran 1% faster;
+// * the two-type FP64 kernels held at 6 instead of 5 were 4% slower, and a one-type
+//   FP32 + Kahan kernel held at 7 no faster: those stay as compiled.
+template <int PREC, bool MULTI, int WPB, int UNROLL, int LIST, bool IND, bool PRUNE>
+constexpr int force_waves_per_simd()
+{
+    if (IND || PRUNE || LIST != 16) return 1;
+    if (PREC == 0) return !MULTI && STAGE_ROWS ? 6 : 1;
+    return WPB == 1 && UNROLL == 8 && (MULTI ? PREC == 1 : PREC == 2) ? 8 : 1;
+}
+
 template <int PREC, bool MULTI, typename VPT, int WPB, int UNROLL, int LIST, bool IND = false, bool PRUNE = false>
 __global__ __launch_bounds__(WPB * WAVE)
-__attribute__((amdgpu_waves_per_eu((PREC == 0 && !MULTI && !IND && !PRUNE && LIST == 16 && STAGE_ROWS) ? 6 : 1)))
+__attribute__((amdgpu_waves_per_eu(force_waves_per_simd<PREC, MULTI, WPB, UNROLL, LIST, IND, PRUNE>())))
 void k_force_cells(PhysArgs P, ForceArgs<VPT> a)
 {
     static_assert(2 * UNROLL <= LIST, "a trip must fit the list above the flush mark");
