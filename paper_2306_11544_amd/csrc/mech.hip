@@ -2024,8 +2024,9 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
 // * the one-wave FP32 kernels with trips of 8 and 16-entry rings, 8 (64 VGPRs): the
 //   two-type batch kernel fits without spills (71 as compiled, 7 waves) and ran 4%
 //   faster, the one-type FP32 + Kahan kernel spills two (73, 6 waves) and ran 1% faster;
-// * the two-type FP64 kernels held at 6 instead of 5 were 4% slower, and a one-type
-//   FP32 + Kahan kernel held at 7 no faster: those stay as compiled.
+// * the two-type FP64 kernels held at 6 instead of 5 were 4% slower, the one-type FP32
+//   kernel held at 8 (70 VGPRs as compiled) 0.6% slower, and the one-type FP32 + Kahan
+//   kernel held at 7 no faster: those stay as compiled.
 template <int PREC, bool MULTI, int WPB, int UNROLL, int LIST, bool IND, bool PRUNE>
 constexpr int force_waves_per_simd()
 {
