@@ -1499,7 +1499,8 @@ __global__ __launch_bounds__(WPB * WAVE) void k_force_rows(PhysArgs P, ForceArgs
 template <int PREC, bool MULTI, typename VPT, int FC_UNROLL, int LIST, bool IND = false, bool PRUNE = false>
 __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceArgs<VPT>& a, uint32_t i,
                                                  uint32_t n, uint32_t* const list0, uint2* const rng0,
-                                                 uint2* const stage0, uint32_t& inter, uint32_t& cand)
+                                                 uint2* const stage0, const void* const cadh_lds,
+                                                 uint32_t& inter, uint32_t& cand)
 {
     // the slab walk stages shared rows in LDS (stage0: STAGE_CAP + FC_UNROLL entries); in
     // the one-type FP64 kernel only, whose candidate stream limits it most (the others ran
@@ -1691,10 +1692,10 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
     };
     auto eval = [&](const Cand& c) {
         if constexpr (PREC == 0) {
-            const double cadh = MULTI ? a.cadh[ti * P.n_types + c.t] : P.c_adh0;
+            const double cadh = MULTI ? static_cast<const double*>(cadh_lds)[ti * P.n_types + c.t] : P.c_adh0;
             inter += pair64(xi, yi, zi, ri, c.x, c.y, c.z, c.r, P.alpha, P.c_rep, cadh, acc[0], acc[1], acc[2]);
         } else {
-            const float cadh = MULTI ? a.cadh_f[ti * P.n_types + c.t] : P.c_adh0_f;
+            const float cadh = MULTI ? static_cast<const float*>(cadh_lds)[ti * P.n_types + c.t] : P.c_adh0_f;
             inter += pair32<PREC == 2>(xi, yi, zi, ri, make_float4(c.x, c.y, c.z, c.r), P.alpha_f, P.c_rep_f,
                                        cadh, acc, cmp, P.inv_alpha_f);
         }
@@ -2057,6 +2058,22 @@ void k_force_cells(PhysArgs P, ForceArgs<VPT> a)
         __shared__ uint2 s_stage[WPB][STAGE_CAP + UNROLL];
         stage0 = &s_stage[threadIdx.x / WAVE][0];
     }
+    const void* cadh_lds = nullptr;
+    if constexpr (MULTI) {
+        // The adhesion table (n_types^2 <= 64 entries) in LDS, read once per listed
+        // candidate: read from global memory it took the load return path that bounds
+        // the two-type kernels (the batch ran 6% slower, the 100k spheroid 5%).
+        using Real = typename std::conditional<PREC == 0, double, float>::type;
+        __shared__ Real s_cadh[WPB][64];
+        Real* const tab = &s_cadh[threadIdx.x / WAVE][0];
+        const uint32_t l = threadIdx.x & (WAVE - 1);
+        if (l < (uint32_t)(P.n_types * P.n_types)) {
+            if constexpr (PREC == 0) tab[l] = a.cadh[l];
+            else tab[l] = a.cadh_f[l];
+        }
+        __builtin_amdgcn_wave_barrier();   // the wave's writes before its reads
+        cadh_lds = tab;
+    }
     uint32_t inter = 0, cand = 0;
     // Each XCD takes one contiguous run of tiles, so its L2 keeps the neighbours its
     // cells share; the runs hold equal shares of the last launch's measured work, or
@@ -2088,7 +2105,7 @@ void k_force_cells(PhysArgs P, ForceArgs<VPT> a)
         // read unconditionally: a conditional read costs the FP64 kernels a register
         const uint64_t c0 = wall_clock64();
         force_cells_cell<PREC, MULTI, VPT, UNROLL, LIST, IND, PRUNE>(P, a, t * TB + threadIdx.x, n, list0, rng0,
-                                                                     stage0, inter, cand);
+                                                                     stage0, cadh_lds, inter, cand);
         if (a.work) {
             // the wave's index among the wave64s of cells; waves past the last cell record
             // nothing, so the entry (wave / group) is below BAL_ENTRIES
