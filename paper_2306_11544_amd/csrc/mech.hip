@@ -161,6 +161,22 @@ static_assert(QS_PAD >= 2 * 8, "a trip of up to 8 candidates from at most 7 past
 // ceil(alpha r S), packed (x | y << 16, z | reach << 16).  Differences of two cells of one
 // 27-voxel neighbourhood are below 2 h S + 1 <= 2^14 + 1 units, so the 16-bit wrapped
 // difference is the exact difference of the rounded coordinates.
+// The float shadow (x, y, z, r) of a cell for the FP32 kernels.  Radii are positive, so
+// with exactly two cell types the sign of r carries the type (negative for type 1): the
+// two-type kernels then read no type per listed candidate.  Readers take |r|.
+__device__ __forceinline__ float4 shadow(double x, double y, double z, double r, int32_t type, bool sign_type)
+{
+    const float w = (float)r;
+    return make_float4((float)x, (float)y, (float)z, sign_type && type != 0 ? -w : w);
+}
+
+__device__ __forceinline__ float4 shadow_at(const float4* __restrict__ SH, uint32_t j)
+{
+    float4 v = SH[j];
+    v.w = fabsf(v.w);
+    return v;
+}
+
 __device__ __forceinline__ uint2 quantise(double x, double y, double z, double r, double S, double alpha)
 {
     const uint32_t qx = (uint32_t)__double2ll_rn(x * S) & 0xffffu;
@@ -677,6 +693,7 @@ struct GatherArgs {
     VPT* VP_new[3];
     float4* SH;              // nullptr in FP64
     uint2* QS;               // quantised shadow (prefilter)
+    int32_t sign_type;       // the shadow's sign carries the type (exactly two types)
     const uint32_t* slot_of;
     const SlotDesc* slots;
     double alpha;
@@ -707,12 +724,13 @@ __global__ __launch_bounds__(BLOCK) void k_rank_gather(const uint32_t* __restric
         a.XS[1][d] = y;
         a.XS[2][d] = z;
         a.R_new[d] = r;
-        a.T_new[d] = a.T_cur[s];
+        const int32_t ty = a.T_cur[s];
+        a.T_new[d] = ty;
         a.ID_new[d] = key;
 #pragma unroll
         for (int c = 0; c < 3; ++c) a.VP_new[c][d] = a.VP_cur[c][s];
         a.vid_sorted[d] = v;
-        if (a.SH) a.SH[d] = make_float4((float)x, (float)y, (float)z, (float)r);
+        if (a.SH) a.SH[d] = shadow(x, y, z, r, ty, a.sign_type != 0);
         a.QS[d] = quantise(x, y, z, r, (double)a.slots[a.slot_of[s]].q_scale, a.alpha);
     }
 }
@@ -829,12 +847,13 @@ __global__ __launch_bounds__(SMALL_BLOCK) void k_bin_small(const uint32_t* __res
         a.XS[1][d] = y;
         a.XS[2][d] = z;
         a.R_new[d] = r;
-        a.T_new[d] = a.T_cur[s];
+        const int32_t ty = a.T_cur[s];
+        a.T_new[d] = ty;
         a.ID_new[d] = key;
 #pragma unroll
         for (int c = 0; c < 3; ++c) a.VP_new[c][d] = a.VP_cur[c][s];
         a.vid_sorted[d] = v;
-        if (a.SH) a.SH[d] = make_float4((float)x, (float)y, (float)z, (float)r);
+        if (a.SH) a.SH[d] = shadow(x, y, z, r, ty, a.sign_type != 0);
         a.QS[d] = quantise(x, y, z, r, (double)a.slots[a.slot_of[s]].q_scale, a.alpha);
     }
 }
@@ -879,11 +898,12 @@ __global__ __launch_bounds__(BLOCK) void k_shadow(const uint32_t* __restrict__ h
                                                   const double* __restrict__ x1, const double* __restrict__ x2,
                                                   const double* __restrict__ r, float4* __restrict__ sh,
                                                   uint2* __restrict__ qs, const uint32_t* __restrict__ slot_of,
-                                                  const SlotDesc* __restrict__ slots, double alpha)
+                                                  const SlotDesc* __restrict__ slots, double alpha,
+                                                  const int32_t* __restrict__ type, int32_t sign_type)
 {
     const uint32_t n = hdr[H_CELLS];
     for (uint32_t s = blockIdx.x * BLOCK + threadIdx.x; s < n; s += gridDim.x * BLOCK) {
-        if (sh) sh[s] = make_float4((float)x0[s], (float)x1[s], (float)x2[s], (float)r[s]);
+        if (sh) sh[s] = shadow(x0[s], x1[s], x2[s], r[s], sign_type != 0 ? type[s] : 0, sign_type != 0);
         qs[s] = quantise(x0[s], x1[s], x2[s], r[s], (double)slots[slot_of[s]].q_scale, alpha);
     }
 }
@@ -1431,7 +1451,7 @@ __device__ __forceinline__ void force_rows_cell(const PhysArgs& P, const ForceAr
                 v[1] = ay;
                 v[2] = az;
             } else {
-                const float4 me = a.SH[i];
+                const float4 me = shadow_at(a.SH, i);
                 float acc[3] = {0.f, 0.f, 0.f}, cmp[3] = {0.f, 0.f, 0.f};
                 for (int q = 0; q < 9; ++q) {
                     const int64_t r0 = row_first(g, d, q);
@@ -1441,7 +1461,7 @@ __device__ __forceinline__ void force_rows_cell(const PhysArgs& P, const ForceAr
                     cand += e - b;
                     for (uint32_t j = b; j < e; ++j) {
                         const float c = MULTI ? a.cadh_f[ti * P.n_types + a.T[j]] : P.c_adh0_f;
-                        inter += pair32<PREC == 2>(me.x, me.y, me.z, me.w, a.SH[j], P.alpha_f,
+                        inter += pair32<PREC == 2>(me.x, me.y, me.z, me.w, shadow_at(a.SH, j), P.alpha_f,
                                                    P.c_rep_f, c, acc, cmp, P.inv_alpha_f);
                     }
                 }
@@ -1586,7 +1606,7 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
         zi = a.XS[2][ii];
         ri = a.R[ii];
     } else {
-        const float4 m = a.SH[ii];
+        const float4 m = shadow_at(a.SH, ii);
         xi = m.x;
         yi = m.y;
         zi = m.z;
@@ -1680,14 +1700,16 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
             c.y = a.XS[1][j];
             c.z = a.XS[2][j];
             c.r = a.R[j];
+            c.t = MULTI ? a.T[j] : 0;
         } else {
             const float4 v = a.SH[j];
             c.x = v.x;
             c.y = v.y;
             c.z = v.z;
-            c.r = v.w;
+            c.r = fabsf(v.w);
+            // with exactly two types the shadow's sign is the type: no type load
+            c.t = MULTI ? (P.n_types == 2 ? (v.w < 0.0f ? 1 : 0) : a.T[j]) : 0;
         }
-        c.t = MULTI ? a.T[j] : 0;
         return c;
     };
     auto eval = [&](const Cand& c) {
@@ -2191,7 +2213,7 @@ __global__ __launch_bounds__(FL_WAVES * WAVE) void k_force_lds(PhysArgs P, Force
             if constexpr (PREC == 0) {
                 me = make_double4(a.XS[0][i], a.XS[1][i], a.XS[2][i], a.R[i]);
             } else {
-                me = a.SH[i];
+                me = shadow_at(a.SH, i);
             }
             const int ti = MULTI ? a.T[i] : 0;
             Real acc[3] = {0, 0, 0}, cmp[3] = {0, 0, 0};
@@ -2230,7 +2252,7 @@ __global__ __launch_bounds__(FL_WAVES * WAVE) void k_force_lds(PhysArgs P, Force
                     if constexpr (PREC == 0) {
                         stage[f] = make_double4(a.XS[0][gi], a.XS[1][gi], a.XS[2][gi], a.R[gi]);
                     } else {
-                        stage[f] = a.SH[gi];
+                        stage[f] = shadow_at(a.SH, gi);
                     }
                     if (MULTI) s_type[w][f] = (uint8_t)a.T[gi];
                 }
@@ -2416,6 +2438,8 @@ struct Layout {
 };
 
 bool is_fp32(const MechParams& p) { return p.precision != MECH_FP64; }
+// the float shadow's sign carries the cell type (the two-type FP32 kernels read no type)
+bool sign_type(const MechParams& p) { return is_fp32(p) && p.n_types == 2; }
 
 Layout make_layout(const MechParams& p, int64_t ncap, uint64_t vcap, int32_t scap)
 {
@@ -2695,6 +2719,7 @@ void enqueue_binning(MechBatch* B)
     g.ID_new = B->at<uint32_t>(L.ID[nxt]);
     g.SH = is_fp32(B->prm) ? B->at<float4>(L.SH) : nullptr;
     g.QS = B->at<uint2>(L.QS);
+    g.sign_type = sign_type(B->prm) ? 1 : 0;
     g.slot_of = B->at<uint32_t>(L.slot_of);
     g.slots = B->at<SlotDesc>(L.slots);
     g.alpha = B->phys.alpha;
@@ -2933,7 +2958,8 @@ void enqueue_binning_inplace(MechBatch* B)
                        B->at<double>(L.X[1]), B->at<double>(L.X[2]), B->at<double>(L.R[cur]),
                        is_fp32(B->prm) ? B->at<float4>(L.SH) : nullptr, B->at<uint2>(L.QS),
                        B->at<uint32_t>(L.slot_of),
-                       B->at<SlotDesc>(L.slots), B->phys.alpha);
+                       B->at<SlotDesc>(L.slots), B->phys.alpha, B->at<int32_t>(L.T[cur]),
+                       sign_type(B->prm) ? 1 : 0);
     enqueue_keys(B, false);
     hipLaunchKernelGGL(k_rank_perm, dim3(nbc), dim3(BLOCK), 0, B->stream, hdr, B->at<uint32_t>(L.vid_cur),
                        B->at<uint32_t>(L.tmp_key), B->at<uint32_t>(L.tmp_src), B->at<uint32_t>(L.start),
