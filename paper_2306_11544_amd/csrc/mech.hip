@@ -692,6 +692,7 @@ struct GatherArgs {
     const VPT* VP_cur[3];
     VPT* VP_new[3];
     float4* SH;              // nullptr in FP64
+    double4* XR;             // FP64 records (x, y, z, r) of one-type arenas, or nullptr
     uint2* QS;               // quantised shadow (prefilter)
     int32_t sign_type;       // the shadow's sign carries the type (exactly two types)
     const uint32_t* slot_of;
@@ -731,6 +732,7 @@ __global__ __launch_bounds__(BLOCK) void k_rank_gather(const uint32_t* __restric
         for (int c = 0; c < 3; ++c) a.VP_new[c][d] = a.VP_cur[c][s];
         a.vid_sorted[d] = v;
         if (a.SH) a.SH[d] = shadow(x, y, z, r, ty, a.sign_type != 0);
+        if (a.XR) a.XR[d] = make_double4(x, y, z, r);
         a.QS[d] = quantise(x, y, z, r, (double)a.slots[a.slot_of[s]].q_scale, a.alpha);
     }
 }
@@ -854,6 +856,7 @@ __global__ __launch_bounds__(SMALL_BLOCK) void k_bin_small(const uint32_t* __res
         for (int c = 0; c < 3; ++c) a.VP_new[c][d] = a.VP_cur[c][s];
         a.vid_sorted[d] = v;
         if (a.SH) a.SH[d] = shadow(x, y, z, r, ty, a.sign_type != 0);
+        if (a.XR) a.XR[d] = make_double4(x, y, z, r);
         a.QS[d] = quantise(x, y, z, r, (double)a.slots[a.slot_of[s]].q_scale, a.alpha);
     }
 }
@@ -893,17 +896,19 @@ __global__ __launch_bounds__(BLOCK) void k_commit(const uint32_t* __restrict__ h
     }
 }
 
-// Cells left in place: the float shadow of the positions, in storage order.
+// Cells left in place: the float shadow and the FP64 records of the cells, in storage order.
 __global__ __launch_bounds__(BLOCK) void k_shadow(const uint32_t* __restrict__ hdr, const double* __restrict__ x0,
                                                   const double* __restrict__ x1, const double* __restrict__ x2,
                                                   const double* __restrict__ r, float4* __restrict__ sh,
                                                   uint2* __restrict__ qs, const uint32_t* __restrict__ slot_of,
                                                   const SlotDesc* __restrict__ slots, double alpha,
-                                                  const int32_t* __restrict__ type, int32_t sign_type)
+                                                  const int32_t* __restrict__ type, int32_t sign_type,
+                                                  double4* __restrict__ xr)
 {
     const uint32_t n = hdr[H_CELLS];
     for (uint32_t s = blockIdx.x * BLOCK + threadIdx.x; s < n; s += gridDim.x * BLOCK) {
         if (sh) sh[s] = shadow(x0[s], x1[s], x2[s], r[s], sign_type != 0 ? type[s] : 0, sign_type != 0);
+        if (xr) xr[s] = make_double4(x0[s], x1[s], x2[s], r[s]);
         qs[s] = quantise(x0[s], x1[s], x2[s], r[s], (double)slots[slot_of[s]].q_scale, alpha);
     }
 }
@@ -1210,6 +1215,7 @@ struct ForceArgs {
     const double* R;
     const int32_t* T;
     const float4* SH;
+    const double4* XR;         // FP64 records (x, y, z, r) of one-type arenas, as XS and R; or nullptr
     const uint2* QS;
     const uint32_t* vid_sorted;
     const uint32_t* voxel_start;
@@ -1696,10 +1702,19 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
     auto fetch = [&](uint32_t j) {
         Cand c;
         if constexpr (PREC == 0) {
-            c.x = a.XS[0][j];
-            c.y = a.XS[1][j];
-            c.z = a.XS[2][j];
-            c.r = a.R[j];
+            if constexpr (!MULTI) {
+                // one 32-byte record instead of four gathers
+                const double4 v = a.XR[j];
+                c.x = v.x;
+                c.y = v.y;
+                c.z = v.z;
+                c.r = v.w;
+            } else {
+                c.x = a.XS[0][j];
+                c.y = a.XS[1][j];
+                c.z = a.XS[2][j];
+                c.r = a.R[j];
+            }
             c.t = MULTI ? a.T[j] : 0;
         } else {
             const float4 v = a.SH[j];
@@ -2432,10 +2447,20 @@ __global__ __launch_bounds__(BLOCK) void k_load_cells(uint32_t n, const double* 
 inline uint32_t blocks_for(uint64_t n, uint32_t per) { return (uint32_t)((n + per - 1) / per); }
 
 struct Layout {
-    size_t X[3], XS[3], R[2], T[2], ID[2], VP[2][3], SH, QS, slot_of, vid_cur, off, tmp_key, dtsum,
+    size_t X[3], XS[3], R[2], T[2], ID[2], VP[2][3], SH, XR, QS, slot_of, vid_cur, off, tmp_key, dtsum,
         tmp_src, vid_sorted, count, start, occ, hdr, tsum, stats, cadh, cadh_f, slots, stage, work, split;
     size_t total;
+    bool xr = false;   // the FP64 records XR are kept
 };
+
+// One-type FP64 arenas keep a record (x, y, z, r) per cell, written by the gather, for the
+// one-type kernels' evaluation: one 32-byte load per listed candidate instead of four
+// gathers.  The 1M-cell tumour's step was 1.3-2.4% faster with it.  The two-type FP64
+// kernels read the four arrays: with the record the 100k spheroid and the 256 small
+// simulations run one at a time were about 2% slower (the gather writes 32 more bytes
+// per cell, and these force kernels are latency-bound), and choosing between the two
+// at run time cost the one-type kernel 4%.
+bool fp64_records(const MechParams& p) { return p.precision == MECH_FP64 && p.n_types == 1; }
 
 bool is_fp32(const MechParams& p) { return p.precision != MECH_FP64; }
 // the float shadow's sign carries the cell type (the two-type FP32 kernels read no type)
@@ -2462,6 +2487,8 @@ Layout make_layout(const MechParams& p, int64_t ncap, uint64_t vcap, int32_t sca
         for (int c = 0; c < 3; ++c) L.VP[k][c] = take(nn * vpb);
     }
     L.SH = take(is_fp32(p) ? nn * 16 : 0);   // read by the FP32 kernels only
+    L.xr = fp64_records(p);
+    L.XR = take(L.xr ? nn * 32 : 0);
     L.QS = take((nn + QS_PAD) * 8);        // a trip of the force kernel may read past the last cell
     L.slot_of = take(nn * 4);
     L.vid_cur = take(nn * 4);
@@ -2718,6 +2745,7 @@ void enqueue_binning(MechBatch* B)
     g.T_new = B->at<int32_t>(L.T[nxt]);
     g.ID_new = B->at<uint32_t>(L.ID[nxt]);
     g.SH = is_fp32(B->prm) ? B->at<float4>(L.SH) : nullptr;
+    g.XR = L.xr ? B->at<double4>(L.XR) : nullptr;
     g.QS = B->at<uint2>(L.QS);
     g.sign_type = sign_type(B->prm) ? 1 : 0;
     g.slot_of = B->at<uint32_t>(L.slot_of);
@@ -2860,6 +2888,7 @@ void enqueue_force(MechBatch* B, int parity_after_sort)
     a.R = B->at<double>(L.R[p]);
     a.T = B->at<int32_t>(L.T[p]);
     a.SH = is_fp32(B->prm) ? B->at<float4>(L.SH) : nullptr;
+    a.XR = L.xr ? B->at<double4>(L.XR) : nullptr;
     a.QS = B->at<uint2>(L.QS);
     a.vid_sorted = B->at<uint32_t>(L.vid_sorted);
     a.voxel_start = B->at<uint32_t>(L.start);
@@ -2930,6 +2959,7 @@ void enqueue_force_inplace(MechBatch* B)
     a.R = B->at<double>(L.R[cur]);
     a.T = B->at<int32_t>(L.T[cur]);
     a.SH = is_fp32(B->prm) ? B->at<float4>(L.SH) : nullptr;
+    a.XR = L.xr ? B->at<double4>(L.XR) : nullptr;
     a.QS = B->at<uint2>(L.QS);
     a.vid_sorted = B->at<uint32_t>(L.vid_cur);
     a.voxel_start = B->at<uint32_t>(L.start);
@@ -2959,7 +2989,7 @@ void enqueue_binning_inplace(MechBatch* B)
                        is_fp32(B->prm) ? B->at<float4>(L.SH) : nullptr, B->at<uint2>(L.QS),
                        B->at<uint32_t>(L.slot_of),
                        B->at<SlotDesc>(L.slots), B->phys.alpha, B->at<int32_t>(L.T[cur]),
-                       sign_type(B->prm) ? 1 : 0);
+                       sign_type(B->prm) ? 1 : 0, L.xr ? B->at<double4>(L.XR) : nullptr);
     enqueue_keys(B, false);
     hipLaunchKernelGGL(k_rank_perm, dim3(nbc), dim3(BLOCK), 0, B->stream, hdr, B->at<uint32_t>(L.vid_cur),
                        B->at<uint32_t>(L.tmp_key), B->at<uint32_t>(L.tmp_src), B->at<uint32_t>(L.start),
