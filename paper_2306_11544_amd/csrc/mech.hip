@@ -1234,14 +1234,15 @@ struct ForceArgs {
 
 // a7 for one cell: two-step Adams-Bashforth from the gathered position, reflecting
 // walls of its slot, history <- v.
+// x0: the gathered position when the caller holds it, else null (read from XS).
 template <typename VPT>
 __device__ __forceinline__ void integrate(const ForceArgs<VPT>& a, const PhysArgs& P, const SlotDesc& d,
-                                          uint32_t i, const double v[3])
+                                          uint32_t i, const double v[3], const double* x0 = nullptr)
 {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const double vp = d.euler_now ? v[c] : (double)a.VP[c][i];
-        const double xn = a.XS[c][i] + P.dt * (1.5 * v[c] - 0.5 * vp);
+        const double xn = (x0 ? x0[c] : a.XS[c][i]) + P.dt * (1.5 * v[c] - 0.5 * vp);
         a.X[c][i] = reflect(xn, d.lo[c], d.hi[c]);
         a.VP[c][i] = (VPT)v[c];
     }
@@ -1250,10 +1251,10 @@ __device__ __forceinline__ void integrate(const ForceArgs<VPT>& a, const PhysArg
 // A frozen slot (its steps are done) keeps its state: the gathered position is copied
 // back and the gathered history is left as it is.
 template <typename VPT>
-__device__ __forceinline__ void hold(const ForceArgs<VPT>& a, uint32_t i)
+__device__ __forceinline__ void hold(const ForceArgs<VPT>& a, uint32_t i, const double* x0 = nullptr)
 {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) a.X[c][i] = a.XS[c][i];
+    for (int c = 0; c < 3; ++c) a.X[c][i] = x0 ? x0[c] : a.XS[c][i];
 }
 
 // 1/sqrt(x) and 1/x in FP64 from the hardware estimates (about 24 correct bits) and one
@@ -1532,9 +1533,15 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
     // the one-type FP64 kernel only, whose candidate stream limits it most (the others ran
     // slower with the registers staging takes)
     constexpr bool STAGE = !PRUNE && !IND && PREC == 0 && !MULTI && STAGE_ROWS;
+    // one-type FP64: the cell's own position and radius come from its record as well,
+    // so the kernel reads neither XS nor R
+    constexpr bool REC = PREC == 0 && !MULTI;
     using Real = typename std::conditional<PREC == 0, double, float>::type;
     const bool in_pop = i < n;
     const uint32_t ii = in_pop ? i : n - 1;  // idle lanes mirror the last cell
+    double4 rec{};
+    if constexpr (REC) rec = a.XR[ii];
+    const double r_own = REC ? rec.w : a.R[ii];
     const SlotDesc& d = a.slots[a.slot_of[ii]];
     const bool valid = in_pop && d.active_now != 0;
     const Cellgeo g = cell_geo(a.vid_sorted[ii] / XSUB, d);
@@ -1546,8 +1553,8 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
     // counted from the first slab of the row's voxels and clipped to them.
     uint32_t w0 = 0, w1 = 0;
     if constexpr (!PRUNE) {
-        const double xg = a.XS[0][ii];
-        const double reach = P.alpha * (a.R[ii] + d.r_max);
+        const double xg = REC ? rec.x : a.XS[0][ii];
+        const double reach = P.alpha * (r_own + d.r_max);
         const double m = reach * (1.0 + 1e-6) + 1e-3 + 5e-7 * (fabs(xg) + reach);
         const double xs = (double)XSUB * d.inv_h;
         const double lo_s = floor((xg - d.lo[0] - m) * xs), hi_s = floor((xg - d.lo[0] + m) * xs);
@@ -1570,8 +1577,8 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
     // in row order (dz, then dy), go to the lane's LDS slots rng0[k * WAVE], k < nr.
     uint32_t nr = 0;
     if (PRUNE && valid) {
-        const double xg = a.XS[0][ii], yg = a.XS[1][ii], zg = a.XS[2][ii];
-        const double reach = P.alpha * (a.R[ii] + d.r_max);
+        const double xg = REC ? rec.x : a.XS[0][ii], yg = REC ? rec.y : a.XS[1][ii], zg = REC ? rec.z : a.XS[2][ii];
+        const double reach = P.alpha * (r_own + d.r_max);
         const double pm = fmax(fabs(xg), fmax(fabs(yg), fabs(zg)));
         const double m = reach * (1.0 + 1e-6) + 1e-3 + 5e-7 * (pm + reach);
         const float rh = (float)(m * d.inv_h) * (1.0f + 1e-5f);           // voxel units
@@ -1606,7 +1613,12 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
         }
     }
     Real xi, yi, zi, ri;
-    if constexpr (PREC == 0) {
+    if constexpr (REC) {
+        xi = rec.x;
+        yi = rec.y;
+        zi = rec.z;
+        ri = rec.w;
+    } else if constexpr (PREC == 0) {
         xi = a.XS[0][ii];
         yi = a.XS[1][ii];
         zi = a.XS[2][ii];
@@ -1622,7 +1634,7 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
     // and its reach ceil(alpha r_i S) plus the margin (below)
     const uint2 qi = a.QS[ii];
     const uint32_t q_xy = qi.x, q_z = qi.y & 0xffffu;
-    const uint32_t q_a = (uint32_t)ceil(P.alpha * a.R[ii] * (double)d.q_scale) + Q_MARGIN + (uint32_t)d.q_pad;
+    const uint32_t q_a = (uint32_t)ceil(P.alpha * r_own * (double)d.q_scale) + Q_MARGIN + (uint32_t)d.q_pad;
     const int ti = MULTI ? a.T[ii] : 0;
     Real acc[3] = {0, 0, 0}, cmp[3] = {0, 0, 0};
     // The short list (LIST = 16, picked for dense populations) is a ring,
@@ -2049,9 +2061,19 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
         double v[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) v[c] = (double)acc[c];
-        integrate(a, P, d, i, v);
+        if constexpr (REC) {
+            const double x0[3] = {rec.x, rec.y, rec.z};
+            integrate(a, P, d, i, v, x0);
+        } else {
+            integrate(a, P, d, i, v);
+        }
     } else if (in_pop) {
-        hold(a, i);
+        if constexpr (REC) {
+            const double x0[3] = {rec.x, rec.y, rec.z};
+            hold(a, i, x0);
+        } else {
+            hold(a, i);
+        }
     }
 }
 
