@@ -2079,8 +2079,8 @@ __device__ __forceinline__ void force_cells_cell(const PhysArgs& P, const ForceA
 
 // Waves per SIMD the register allocation of a force kernel is asked to fit (1: as
 // compiled), measured per shape on the tumour and the batch:
-// * the staged one-type FP64 ring kernels, 6 (80 VGPRs, one or two spilled; the compiler
-//   would take 88 and hold 5): 3% faster;
+// * the staged one-type FP64 ring kernels, 6 (80 VGPRs, none spilled in the default
+//   shape; the compiler would take 88 and hold 5): 3% faster;
 // * the one-wave FP32 kernels with trips of 8 and 16-entry rings, 8 (64 VGPRs): the
 //   two-type batch kernel fits without spills (71 as compiled, 7 waves) and ran 4%
 //   faster, the one-type FP32 + Kahan kernel spills two (73, 6 waves) and ran 1% faster;
