@@ -44,7 +44,7 @@ METRIC = "cell-neighbour interactions/s and cell-steps/s at 1M cells; p50/p99 si
 # MI355X published peaks
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_VECTOR_TFLOPS = 157.3        # packed FP32 (two operations per lane and cycle)
-PEAK_FP32_UNPACKED_TFLOPS = 78.6       # what this build's FP32 code can issue (packed off)
+PEAK_FP32_UNPACKED_TFLOPS = 78.6       # what FP32 code compiled without packed-FP32 ops can issue
 PEAK_FP64_VECTOR_TFLOPS = 78.6
 
 # Algorithmic work of the force kernel (a6 + a7), per unit, as the method counts it:
